@@ -1,0 +1,243 @@
+/*
+ * dpt_oracle.c -- FP64 CPU oracle for dynamical perturbation theory (D-PT).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is loaded by the test-suite, by the
+ * smoke check and by the CPU-baseline leg of the benchmark, nothing else.  It
+ * shares no code, header, table or helper with the HIP library and must never
+ * be called from the product path.
+ *
+ * What it computes (Kenmoe, Smerlak, Zadorin, "Dynamical perturbation theory
+ * for eigenvalue problems", arXiv:2002.12872):
+ *
+ *   M = D + lambda*Delta, D = diag(theta) with simple theta (Sec. II.B).
+ *   For each requested eigenvector index n the candidate z_n (chart z_n[n] = 1)
+ *   is iterated with the single-line map of eq. (single_line_dyn):
+ *
+ *     F_n(z)[m] = delta_nm + lambda * ((Delta z)[m] - (Delta z)[n] * z[m]) / (theta_n - theta_m),
+ *
+ *   with the gap factor taken as zero on the diagonal, starting from z = e_n,
+ *   i.e. A^(0) = I (Sec. II.B, the iteration F^k(I) of eq. (dyn), whose n-th row
+ *   evolves under F_n alone).  The eigenvalue attached to an iterate is
+ *   E_n = theta_n + lambda * (Delta z_n)[n]  (Sec. II.B readout; the factor
+ *   lambda is the one the main text omits and Supplement B makes explicit:
+ *   the order-l eigenvalue coefficient is (a^(l-1) Delta')_nn).
+ *
+ * Stopping rule (the paper states none; reading recorded in the design notes):
+ *   delta_k = max over requested rows and all m of |z^(k)[m] - z^(k-1)[m]|;
+ *   stop with OK as soon as delta_k < tol; DIVERGED when an iterate is
+ *   non-finite or max |z - e_n| exceeds `blowup`; NOT_CONVERGED at the cap.
+ *   In fixed-step mode exactly max_iter applications are made (no tol stop).
+ *   The returned iterate is the last one computed and E is read from it.
+ *
+ * Arithmetic: plain loops, FP64, products (Delta z)[m] summed over l in
+ * ascending column order (dense) or in stored order (CSR), the gap applied by
+ * division.  No blocking, no fusion, no reordering.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_NOT_CONVERGED 1
+#define OR_DIVERGED 3
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+
+/* Problem description.  Exactly one of `dense` or (`indptr`,`indices`,`values`)
+ * is set.  dense: n*n row-major, dense[m*n + l] = Delta[m][l].
+ * CSR: row m holds entries indices[indptr[m] .. indptr[m+1]) with values. */
+typedef struct {
+    int64_t n;
+    const double *theta;
+    const double *dense;
+    const int64_t *indptr;
+    const int32_t *indices;
+    const double *values;
+    double lambda;
+} or_problem;
+
+/* (Delta z)[m] for one m. */
+static double delta_row_dot(const or_problem *p, int64_t m, const double *z)
+{
+    double s = 0.0;
+    if (p->dense) {
+        const double *row = p->dense + m * p->n;
+        for (int64_t l = 0; l < p->n; ++l) s += row[l] * z[l];
+    } else {
+        for (int64_t e = p->indptr[m]; e < p->indptr[m + 1]; ++e)
+            s += p->values[e] * z[p->indices[e]];
+    }
+    return s;
+}
+
+/* One application of F_n (eq. single_line_dyn) to z, result in znew.
+ * c is scratch of length n holding Delta z. */
+static void apply_single_line_map(const or_problem *p, int64_t nidx, const double *z,
+                                  double *znew, double *c)
+{
+    const int64_t n = p->n;
+    for (int64_t m = 0; m < n; ++m) c[m] = delta_row_dot(p, m, z);
+    const double cn = c[nidx];
+    for (int64_t m = 0; m < n; ++m) {
+        if (m == nidx) {
+            znew[m] = 1.0;
+        } else {
+            znew[m] = p->lambda * (c[m] - cn * z[m]) / (p->theta[nidx] - p->theta[m]);
+        }
+    }
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+static int validate(const or_problem *p)
+{
+    if (!p || p->n < 1 || !p->theta) return OR_EINVAL;
+    if (!p->dense && !(p->indptr && p->indices && p->values)) return OR_EINVAL;
+    if (!isfinite(p->lambda)) return OR_EINVAL;
+    /* The unperturbed eigenvalues must be simple (Sec. II.B): reject exact
+     * duplicates (sort a copy, compare neighbours). */
+    double *sorted = (double *)malloc(sizeof(double) * (size_t)p->n);
+    if (!sorted) return OR_ENOMEM;
+    for (int64_t i = 0; i < p->n; ++i) {
+        if (!isfinite(p->theta[i])) {
+            free(sorted);
+            return OR_EINVAL;
+        }
+        sorted[i] = p->theta[i];
+    }
+    qsort(sorted, (size_t)p->n, sizeof(double), cmp_double);
+    for (int64_t i = 1; i < p->n; ++i) {
+        if (sorted[i] == sorted[i - 1]) {
+            free(sorted);
+            return OR_EINVAL;
+        }
+    }
+    free(sorted);
+    if (!p->dense) {
+        if (p->indptr[0] != 0) return OR_EINVAL;
+        for (int64_t m = 0; m < p->n; ++m) {
+            if (p->indptr[m + 1] < p->indptr[m]) return OR_EINVAL;
+            for (int64_t e = p->indptr[m]; e < p->indptr[m + 1]; ++e)
+                if (p->indices[e] < 0 || p->indices[e] >= p->n) return OR_EINVAL;
+        }
+    }
+    return OR_OK;
+}
+
+/*
+ * Iterate the rows `rows[0..nrows)` of A^(k) = F^k(A^(0)).
+ *   z0        : nrows*n initial rows (row r is the start of eigenvector rows[r]),
+ *               or NULL for e_n (A^(0) = I).  Entry rows[r] of each start row is
+ *               forced to 1 (the chart z^n = 1).
+ *   max_iter  : iteration cap (>= 0); in fixed mode the exact number of steps.
+ *   tol       : stop when delta_k < tol (ignored in fixed mode).
+ *   blowup    : DIVERGED threshold on max |z - e_n|.
+ *   nthreads  : OpenMP threads (<= 0: library default).
+ * Outputs (all caller-owned):
+ *   z         : nrows*n, final iterate rows
+ *   e         : nrows, E_n = theta_n + lambda (Delta z_n)[n] of the final iterate
+ *   delta_hist: max_iter entries (may be NULL); entries past *iters untouched
+ *   iters     : number of applications of F made
+ * Returns OR_OK / OR_NOT_CONVERGED / OR_DIVERGED, or OR_EINVAL / OR_ENOMEM.
+ */
+int or_iterate(const or_problem *p, int64_t nrows, const int64_t *rows, const double *z0,
+               int max_iter, double tol, int fixed_steps, double blowup, int nthreads,
+               double *z, double *e, double *delta_hist, int *iters)
+{
+    int rc = validate(p);
+    if (rc != OR_OK) return rc;
+    if (nrows < 1 || !rows || !z || !e || !iters || max_iter < 0) return OR_EINVAL;
+    if (!fixed_steps && !(tol > 0.0)) return OR_EINVAL;
+    const int64_t n = p->n;
+    for (int64_t r = 0; r < nrows; ++r)
+        if (rows[r] < 0 || rows[r] >= n) return OR_EINVAL;
+
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    double *znew = (double *)malloc(sizeof(double) * (size_t)(nrows * n));
+    double *scratch = (double *)malloc(sizeof(double) * (size_t)n * (size_t)nth);
+    if (!znew || !scratch) {
+        free(znew);
+        free(scratch);
+        return OR_ENOMEM;
+    }
+
+    for (int64_t r = 0; r < nrows; ++r) {
+        double *zr = z + r * n;
+        if (z0) {
+            memcpy(zr, z0 + r * n, sizeof(double) * (size_t)n);
+        } else {
+            for (int64_t m = 0; m < n; ++m) zr[m] = 0.0;
+        }
+        zr[rows[r]] = 1.0;
+    }
+
+    int status = fixed_steps ? OR_OK : OR_NOT_CONVERGED;
+    int k = 0;
+    while (k < max_iter) {
+        double dk = 0.0, wmax = 0.0;
+        int nonfinite = 0;
+#pragma omp parallel for schedule(static) num_threads(nth) reduction(max : dk, wmax) reduction(| : nonfinite)
+        for (int64_t r = 0; r < nrows; ++r) {
+            int t = 0;
+#ifdef _OPENMP
+            t = omp_get_thread_num();
+#endif
+            double *c = scratch + (size_t)t * (size_t)n;
+            const double *zr = z + r * n;
+            double *zn = znew + r * n;
+            apply_single_line_map(p, rows[r], zr, zn, c);
+            for (int64_t m = 0; m < n; ++m) {
+                if (!isfinite(zn[m])) nonfinite = 1;
+                double ch = fabs(zn[m] - zr[m]);
+                if (ch > dk) dk = ch;
+                double off = fabs(zn[m] - (m == rows[r] ? 1.0 : 0.0));
+                if (off > wmax) wmax = off;
+            }
+        }
+        memcpy(z, znew, sizeof(double) * (size_t)(nrows * n));
+        if (delta_hist) delta_hist[k] = nonfinite ? NAN : dk;
+        ++k;
+        if (nonfinite || !(wmax <= blowup)) {
+            status = OR_DIVERGED;
+            break;
+        }
+        if (!fixed_steps && dk < tol) {
+            status = OR_OK;
+            break;
+        }
+    }
+    free(scratch);
+    free(znew);
+    *iters = k;
+
+    for (int64_t r = 0; r < nrows; ++r)
+        e[r] = p->theta[rows[r]] + p->lambda * delta_row_dot(p, rows[r], z + r * n);
+    return status;
+}
+
+/* Threads the OpenMP runtime would use (reported as the CPU-baseline core count). */
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
