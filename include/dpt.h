@@ -1,0 +1,184 @@
+/*
+ * dpt.h -- C ABI of the MI355X (gfx950) dynamical-perturbation-theory library.
+ *
+ * Method: Kenmoe, Smerlak, Zadorin, "Dynamical perturbation theory for
+ * eigenvalue problems", arXiv:2002.12872.
+ *
+ * Problem (Sec. II.B): M = D + lambda * Delta with D = diag(theta), theta simple
+ * (pairwise distinct).  The library iterates the bundled map of eq. (dyn),
+ *
+ *     F(A) = I + lambda * theta-gap (.) (A Delta' - diag(A Delta') A),
+ *     gap[n][m] = 1 / (theta_n - theta_m) for m != n, 0 on the diagonal,
+ *
+ * from A = I (or a caller-given start), where row n of A is the candidate
+ * eigenvector z_n in the chart z_n[n] = 1 (Sec. II.A/B).  Eigenvalues are read
+ * from the current iterate as E_n = theta_n + lambda * (Delta z_n)[n]
+ * (Sec. II.B; the factor lambda follows Supplement B).
+ *
+ * Layout conventions used throughout this header:
+ *   - dense Delta:   delta[m * n + l] = Delta[m][l]  (row-major, n*n entries)
+ *   - CSR Delta:     row m holds columns indices[indptr[m] .. indptr[m+1])
+ *                    with values delta[...]; indices sorted ascending within a
+ *                    row, no duplicates; indptr has n+1 entries, indptr[0] = 0
+ *   - eigenvectors:  Z[k * n + m] = component m of eigenvector k, Z[k*n + k] = 1
+ *                    (row k = z_k; byte-identical to a column-major matrix whose
+ *                    column k is eigenvector k)
+ *
+ * Memory and ownership:
+ *   - DPT_MEM_HOST inputs are copied during the call; the caller may free them
+ *     when the call returns.
+ *   - DPT_MEM_DEVICE inputs (HIP device pointers, e.g. a torch tensor's
+ *     data_ptr()) are borrowed: they must stay valid and unchanged for the life of
+ *     the handle; the library never frees or writes them.
+ *   - Output buffers are always caller-owned.  Each handle owns its internal
+ *     device state; dpt_destroy releases it.
+ *   - All device work is ordered on problem.stream (a hipStream_t; NULL means the
+ *     default stream).  Calls that return host-visible results synchronise that
+ *     stream before returning.
+ *   - A handle is used by one host thread at a time; distinct handles are
+ *     independent.
+ *
+ * Errors: no exception or abort crosses this interface.  Negative return codes
+ * are errors and leave the handle state unchanged; positive codes are
+ * numerical outcomes whose results are valid and can be read.
+ */
+#ifndef DPT_H
+#define DPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ----------------------------------------------------- */
+#define DPT_OK 0              /* converged: delta_k < tol in the final phase            */
+#define DPT_NOT_CONVERGED 1   /* iteration cap reached (cycles and chaos end here)        */
+#define DPT_STALLED 2         /* the final phase stopped improving above tol              */
+#define DPT_DIVERGED 3        /* non-finite iterate, or max |Z - I| above options.blowup */
+#define DPT_EAGAIN 4          /* serving: result not ready yet                            */
+#define DPT_EINVAL (-1)       /* invalid argument                                         */
+#define DPT_ENOMEM (-2)       /* device or host allocation failed                         */
+#define DPT_EDEVICE (-3)      /* HIP runtime error or no usable gfx950 device             */
+#define DPT_ESTATE (-4)       /* call not valid in the handle's current state             */
+
+/* ---- precision forms -------------------------------------------------- */
+#define DPT_FP64 0       /* every product and update in FP64                           */
+#define DPT_FP32 1       /* FP32 products and updates (gaps from FP64 theta)           */
+#define DPT_BF16_FP32 2  /* BF16 products (FP32 accumulate) until stall, then FP32     */
+
+/* ---- storage ---------------------------------------------------------- */
+#define DPT_DENSE 0
+#define DPT_CSR 1
+#define DPT_MEM_HOST 0
+#define DPT_MEM_DEVICE 1
+#define DPT_DTYPE_F64 0
+#define DPT_DTYPE_F32 1
+
+typedef struct dpt_ctx *dpt_handle;
+
+/* The eigenproblem (Sec. II.B: theta, Delta, lambda). */
+typedef struct dpt_problem {
+    int64_t n;               /* matrix order, >= 1                                       */
+    const double *theta;     /* n unperturbed eigenvalues, pairwise distinct (mem kind)  */
+    const void *delta;       /* dense: n*n values; CSR: nnz values (dtype, mem kind)     */
+    const int64_t *indptr;   /* CSR only: n+1 row offsets (mem kind)                     */
+    const int32_t *indices;  /* CSR only: nnz column indices (mem kind)                  */
+    int64_t nnz;             /* CSR only                                                 */
+    double lambda;           /* perturbation strength, finite                            */
+    void *stream;            /* hipStream_t or NULL                                      */
+    int32_t format;          /* DPT_DENSE or DPT_CSR                                     */
+    int32_t dtype;           /* DPT_DTYPE_F64 or DPT_DTYPE_F32 (values of delta)         */
+    int32_t mem;             /* DPT_MEM_HOST or DPT_MEM_DEVICE (all input arrays)        */
+    int32_t reserved;        /* must be 0                                                */
+} dpt_problem;
+
+/* Stopping and precision control.  The paper prescribes no stopping rule; the
+ * one used here: delta_k = max_{n,m} |Z_k[n][m] - Z_{k-1}[n][m]| after the k-th
+ * application of F, convergence when delta_k < tol. */
+typedef struct dpt_options {
+    double tol;             /* > 0; threshold on delta_k for the final phase              */
+    double fp64_final_tol;  /* > 0: after FP32 convergence run FP64 sweeps to this; 0 off */
+    double stall_ratio;     /* stall when delta_k >= stall_ratio * min_{j<k} delta_j ...  */
+    double blowup;          /* DIVERGED when max |Z - I| exceeds this (> 0)               */
+    int32_t max_iter;       /* >= 0; cap on applications of F over all phases              */
+    int32_t precision;      /* DPT_FP64, DPT_FP32 or DPT_BF16_FP32                         */
+    int32_t stall_patience; /* ... for this many consecutive checks (>= 1), or delta_k = 0 */
+    int32_t check_every;    /* read delta back every this many steps (>= 1)                */
+} dpt_options;
+
+typedef struct dpt_result {
+    double last_delta;      /* delta_k of the last application of F (NaN if none)          */
+    double *delta_history;  /* caller-owned array of history_cap entries, or NULL         */
+    int32_t history_cap;
+    int32_t status;         /* DPT_OK / NOT_CONVERGED / STALLED / DIVERGED                */
+    int32_t iters;          /* applications of F made by this call                         */
+    int32_t iters_bf16;
+    int32_t iters_fp32;
+    int32_t iters_fp64;
+} dpt_result;
+
+/* Fill *o with defaults: tol 1e-6, max_iter 200, DPT_FP32, fp64_final_tol 0,
+ * stall_ratio 0.5, stall_patience 2, check_every 1, blowup 1e6. */
+void dpt_options_default(dpt_options *o);
+
+/* Host-only argument check (no device call): pointer/size/enum sanity and, for
+ * host-memory inputs, distinct finite theta and a well-formed CSR.  Returns
+ * DPT_OK or DPT_EINVAL.  `o` may be NULL. */
+int dpt_validate(const dpt_problem *p, const dpt_options *o);
+
+/* Create a handle for the dense or CSR problem p.  Stages Delta on the device
+ * (precision copies, transpose when Delta is not symmetric), validates theta.
+ * z0 == NULL starts from A^(0) = I (Sec. II.B); otherwise z0 holds an n*n start
+ * in the eigenvector layout above, same dtype and memory kind as the problem
+ * (its diagonal is taken as 1: the chart z_k[k] = 1).  This warm start is the
+ * paper's refinement of approximate eigenvectors (Sec. II.H, last paragraph).
+ * Returns DPT_OK, or DPT_EINVAL (bad argument, duplicate theta), DPT_ENOMEM,
+ * DPT_EDEVICE; *h is set only on success. */
+int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const void *z0);
+
+/* Apply F exactly nsteps (>= 0) times in the handle's current precision phase,
+ * with no stopping test (eq. dyn).  *last_delta (may be NULL) receives delta of
+ * the last step (NaN when nsteps == 0).  Returns DPT_OK or an error. */
+int dpt_step(dpt_handle h, int nsteps, double *last_delta);
+
+/* Iterate until the stopping rule ends the solve (options of dpt_init).
+ * DPT_BF16_FP32: BF16 steps until delta_k < tol or a stall, then FP32 sweeps
+ * until delta_k < tol (at least one), then FP64 sweeps when fp64_final_tol > 0.
+ * Returns the status (also in r->status when r != NULL) or an error. */
+int dpt_solve(dpt_handle h, dpt_result *r);
+
+/* E_k = theta_k + lambda (Delta z_k)[k] for all k from the current iterate
+ * (FP64 accumulation).  E: n doubles in memory kind `mem`. */
+int dpt_eigenvalues(dpt_handle h, double *E, int mem);
+
+/* Current iterate in the eigenvector layout above, as DPT_DTYPE_F32/F64 in
+ * memory kind `mem` (n*n entries). */
+int dpt_eigenvectors(dpt_handle h, void *Z, int dtype, int mem);
+
+/* Acceptance check, not part of the method: for the eigenvectors rows[0..nrows)
+ * of the current iterate, res[i] = || M z - E z ||_2 with M = diag(theta) +
+ * lambda Delta evaluated in FP64 on the device (the eigen-equation, Sec. II.A).
+ * rows and res are host arrays. */
+int dpt_residuals(dpt_handle h, int64_t nrows, const int64_t *rows, double *res);
+
+/* Dominant-eigenvector mode (Sec. II.H): iterate only the single-line map
+ * F_index of eq. (single_line_dyn) on one vector from e_index.  index < 0
+ * selects argmax theta.  Uses o->tol, o->max_iter, o->blowup and o->precision
+ * (DPT_FP64 -> FP64, otherwise FP32).  eigvec: n values of p->dtype in p->mem
+ * (eigvec[index] = 1).  *eigval receives theta_index + lambda (Delta z)[index].
+ * Returns the numerical status or an error. */
+int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval,
+                 void *eigvec, dpt_result *r);
+
+/* Release the handle (NULL is accepted). */
+void dpt_destroy(dpt_handle h);
+
+/* Static description of a return code. */
+const char *dpt_status_str(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPT_H */

@@ -1,0 +1,702 @@
+// Host runtime and C ABI (include/dpt.h) of the D-PT library.
+//
+// A handle owns the device copies of Delta needed by its precision phases, the
+// ping-pong eigenvector state W = Z - I, theta, the diagonal vector
+// d_n = (Delta z_n)[n] and a ring of per-step statistics.  Each application of
+// the map of eq. (dyn) (Kenmoe, Smerlak, Zadorin, arXiv:2002.12872, Sec. II.B) is
+// one pre-pass kernel (d) and one fused MFMA kernel (product + update + stats);
+// the very first application from A = I is the closed form F(I) = I + lambda
+// gap * Delta' and needs no product.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "dpt.h"
+#include "dpt_internal.h"
+#include "dpt_sparse.h"
+
+using namespace dpt;
+
+namespace {
+
+int map_err(hipError_t e) {
+    if (e == hipSuccess) return DPT_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return DPT_ENOMEM;
+    return DPT_EDEVICE;
+}
+
+#define DPT_TRY(expr)                              \
+    do {                                           \
+        hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) return map_err(e_);  \
+    } while (0)
+
+double bits_to_double(unsigned long long b) {
+    double x;
+    std::memcpy(&x, &b, sizeof(x));
+    return x;
+}
+
+int64_t pad_order(int64_t n) {
+    const int64_t q = n >= 1024 ? 256 : 64;
+    return (n + q - 1) / q * q;
+}
+
+bool valid_options(const dpt_options *o) {
+    if (!o) return true;
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return false;
+    if (o->max_iter < 0) return false;
+    if (o->precision != DPT_FP64 && o->precision != DPT_FP32 && o->precision != DPT_BF16_FP32) return false;
+    if (!(o->fp64_final_tol >= 0.0) || !std::isfinite(o->fp64_final_tol)) return false;
+    if (!(o->stall_ratio >= 0.0) || !(o->stall_ratio <= 1.0)) return false;
+    if (o->stall_patience < 1 || o->check_every < 1) return false;
+    if (!(o->blowup > 0.0)) return false;
+    return true;
+}
+
+bool theta_ok(const double *theta, int64_t n) {
+    std::vector<double> t(theta, theta + n);
+    for (double v : t)
+        if (!std::isfinite(v)) return false;
+    std::sort(t.begin(), t.end());
+    for (int64_t i = 1; i < n; ++i)
+        if (t[i] == t[i - 1]) return false;  // unperturbed eigenvalues must be simple (Sec. II.B)
+    return true;
+}
+
+bool csr_ok(const int64_t *indptr, const int32_t *indices, int64_t n, int64_t nnz) {
+    if (indptr[0] != 0 || indptr[n] != nnz) return false;
+    for (int64_t m = 0; m < n; ++m) {
+        if (indptr[m + 1] < indptr[m]) return false;
+        for (int64_t e = indptr[m]; e < indptr[m + 1]; ++e) {
+            if (indices[e] < 0 || indices[e] >= n) return false;
+            if (e > indptr[m] && indices[e] <= indices[e - 1]) return false;
+        }
+    }
+    return true;
+}
+
+int check_device() {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return DPT_EDEVICE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DPT_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DPT_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return DPT_EDEVICE;
+    return DPT_OK;
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+}  // namespace
+
+struct dpt_ctx {
+    int64_t n = 0, ld = 0;
+    double lambda = 0.0;
+    hipStream_t stream = nullptr;
+    dpt_options opt{};
+    int format = DPT_DENSE, in_dtype = DPT_DTYPE_F32, mem = DPT_MEM_HOST;
+    bool symmetric = false;
+
+    double *theta = nullptr;  // ld entries
+    double *dvec = nullptr;   // ld entries
+    double *evec = nullptr;   // ld entries
+    unsigned long long *stats = nullptr;
+    unsigned long long *stats_host = nullptr;  // pinned mirror of the ring
+
+    // dense Delta copies (padded ld x ld); *_own tells whether we free them
+    float *d32 = nullptr, *dT32 = nullptr;
+    double *d64 = nullptr, *dT64 = nullptr;
+    __bf16 *db16 = nullptr;
+    bool d32_own = false, d64_own = false;
+
+    // state
+    float *W32[2] = {nullptr, nullptr};
+    __bf16 *Wb[2] = {nullptr, nullptr};
+    double *W64[2] = {nullptr, nullptr};
+    int cur = 0;
+    int phase = PH_FP32;
+    bool at_identity = true;
+    int64_t k = 0;
+
+    SparseState *sp = nullptr;
+
+    ~dpt_ctx() {
+        if (sp) sparse_destroy(sp);
+        void *own[] = {theta, dvec, evec, stats, db16, W32[0], W32[1], Wb[0], Wb[1], W64[0], W64[1]};
+        for (void *p : own)
+            if (p) (void)hipFree(p);
+        if (dT32 && dT32 != d32) (void)hipFree(dT32);
+        if (dT64 && dT64 != d64) (void)hipFree(dT64);
+        if (d32 && d32_own) (void)hipFree(d32);
+        if (d64 && d64_own) (void)hipFree(d64);
+        if (stats_host) (void)hipHostFree(stats_host);
+    }
+};
+
+namespace {
+
+// Stage a dense Delta of the input dtype into padded device copy(ies).
+template <typename T>
+hipError_t stage_dense(dpt_ctx *c, const dpt_problem *p, T **dst, bool *own) {
+    const int64_t n = c->n, ld = c->ld;
+    const bool same_type = (sizeof(T) == 8) == (p->dtype == DPT_DTYPE_F64);
+    if (same_type && p->mem == DPT_MEM_DEVICE && n == ld) {
+        *dst = (T *)p->delta;  // borrowed
+        *own = false;
+        return hipSuccess;
+    }
+    hipError_t e = dalloc(dst, (size_t)(ld * ld));
+    if (e != hipSuccess) return e;
+    *own = true;
+    const void *src = p->delta;
+    void *tmp = nullptr;
+    const size_t in_bytes = (size_t)(n * n) * (p->dtype == DPT_DTYPE_F64 ? 8 : 4);
+    if (p->mem == DPT_MEM_HOST) {
+        e = hipMalloc(&tmp, in_bytes);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(tmp, p->delta, in_bytes, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return e;
+        }
+        src = tmp;
+    }
+    if (sizeof(T) == 4) {
+        e = p->dtype == DPT_DTYPE_F64
+                ? launch_pad_copy_f32_from_f64((float *)*dst, (const double *)src, n, ld, c->stream)
+                : launch_pad_copy_f32_from_f32((float *)*dst, (const float *)src, n, ld, c->stream);
+    } else {
+        e = p->dtype == DPT_DTYPE_F64
+                ? launch_pad_copy_f64_from_f64((double *)*dst, (const double *)src, n, ld, c->stream)
+                : launch_pad_copy_f64_from_f32((double *)*dst, (const float *)src, n, ld, c->stream);
+    }
+    if (tmp) {
+        hipError_t e2 = hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        if (e == hipSuccess) e = e2;
+    }
+    return e;
+}
+
+// FP64 copies for the FP64 phase (on demand when the input is FP32).
+int ensure_f64(dpt_ctx *c) {
+    if (!c->d64) {
+        DPT_TRY(dalloc(&c->d64, (size_t)(c->ld * c->ld)));
+        c->d64_own = true;
+        DPT_TRY(launch_cvt_f32_to_f64(c->d64, c->d32, c->ld * c->ld, c->stream));
+    }
+    if (!c->dT64) {
+        if (c->symmetric) {
+            c->dT64 = c->d64;
+        } else {
+            DPT_TRY(dalloc(&c->dT64, (size_t)(c->ld * c->ld)));
+            DPT_TRY(launch_transpose_f64(c->dT64, c->d64, c->ld, c->stream));
+        }
+    }
+    for (int i = 0; i < 2; ++i)
+        if (!c->W64[i]) {
+            DPT_TRY(dalloc(&c->W64[i], (size_t)(c->ld * c->ld)));
+            DPT_TRY(launch_fill_zero(c->W64[i], sizeof(double) * (size_t)(c->ld * c->ld), c->stream));
+        }
+    return DPT_OK;
+}
+
+StepArgs step_args(dpt_ctx *c, unsigned long long *slot) {
+    StepArgs a;
+    a.n = c->n;
+    a.ld = c->ld;
+    a.lambda = c->lambda;
+    a.theta = c->theta;
+    a.d = c->dvec;
+    a.stat = slot;
+    return a;
+}
+
+// Switch the state to the FP64 phase (upcast the FP32 state).
+int enter_fp64(dpt_ctx *c) {
+    int rc = ensure_f64(c);
+    if (rc != DPT_OK) return rc;
+    if (c->phase != PH_FP64) {
+        DPT_TRY(launch_cvt_f32_to_f64(c->W64[c->cur], c->W32[c->cur], c->ld * c->ld, c->stream));
+        c->phase = PH_FP64;
+    }
+    return DPT_OK;
+}
+
+// One application of F in the current phase; the stats land in ring slot k.
+int dense_step(dpt_ctx *c) {
+    const int slot = (int)(c->k % kStatRing);
+    unsigned long long *st = c->stats + 2 * slot;
+    const StepArgs a = step_args(c, st);
+    const int nx = c->cur ^ 1;
+    hipStream_t s = c->stream;
+    if (c->at_identity) {
+        DPT_TRY(launch_zero_u64(st, 2, s));
+        if (c->phase == PH_FP64)
+            DPT_TRY(launch_first_iterate_f64(a, c->dT64, c->W64[nx], s));
+        else
+            DPT_TRY(launch_first_iterate_f32(a, c->dT32, c->W32[nx], c->phase == PH_BF16 ? c->Wb[nx] : nullptr, s));
+    } else if (c->phase == PH_FP64) {
+        DPT_TRY(launch_prepass_f64_f64(c->W64[c->cur], c->d64, a, c->dvec, nullptr, st, s));
+        DPT_TRY(launch_step_f64(a, c->W64[c->cur], c->d64, c->dT64, c->W64[nx], s));
+    } else if (c->phase == PH_FP32) {
+        DPT_TRY(launch_prepass_f32_f32(c->W32[c->cur], c->d32, a, c->dvec, nullptr, st, s));
+        DPT_TRY(launch_step_f32(a, c->W32[c->cur], c->d32, c->dT32, c->W32[nx], nullptr, s));
+    } else {
+        DPT_TRY(launch_prepass_f32_f32(c->W32[c->cur], c->d32, a, c->dvec, nullptr, st, s));
+        DPT_TRY(launch_step_bf16(a, c->Wb[c->cur], c->db16, c->dT32, c->W32[c->cur], c->W32[nx], c->Wb[nx], s));
+    }
+    c->cur = nx;
+    c->at_identity = false;
+    c->k += 1;
+    return DPT_OK;
+}
+
+int do_step(dpt_ctx *c) { return c->sp ? sparse_step(c->sp, c->lambda, c->theta, c->stats, &c->k, c->stream) : dense_step(c); }
+
+// Copy the stats of steps [k0, k1) to the pinned mirror and synchronise.
+int fetch_stats(dpt_ctx *c, int64_t k0, int64_t k1) {
+    if (k1 <= k0) return DPT_OK;
+    if (k1 - k0 > kStatRing) k0 = k1 - kStatRing;
+    int64_t i = k0;
+    while (i < k1) {
+        const int64_t s0 = i % kStatRing;
+        const int64_t run = std::min<int64_t>(k1 - i, kStatRing - s0);
+        DPT_TRY(hipMemcpyAsync(c->stats_host + 2 * s0, c->stats + 2 * s0, (size_t)run * 16, hipMemcpyDeviceToHost,
+                               c->stream));
+        i += run;
+    }
+    DPT_TRY(hipStreamSynchronize(c->stream));
+    return DPT_OK;
+}
+
+void stat_of(dpt_ctx *c, int64_t step, double *delta, double *wmax) {
+    const int64_t s0 = step % kStatRing;
+    *delta = bits_to_double(c->stats_host[2 * s0]);
+    *wmax = bits_to_double(c->stats_host[2 * s0 + 1]);
+}
+
+int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
+    const int64_t ld = c->ld;
+    const size_t nn = (size_t)(ld * ld);
+    const int prec = c->opt.precision;
+    hipStream_t s = c->stream;
+    // Primary copy in the input dtype; the symmetry test runs on it.
+    if (p->dtype == DPT_DTYPE_F64) {
+        DPT_TRY(stage_dense<double>(c, p, &c->d64, &c->d64_own));
+        unsigned int *flag = nullptr;
+        DPT_TRY(dalloc(&flag, 1));
+        DPT_TRY(launch_fill_zero(flag, 4, s));
+        DPT_TRY(launch_symmetry_check_f64(c->d64, ld, flag, s));
+        unsigned int h = 0;
+        DPT_TRY(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s));
+        DPT_TRY(hipStreamSynchronize(s));
+        (void)hipFree(flag);
+        c->symmetric = (h == 0);
+        if (prec != DPT_FP64) DPT_TRY(stage_dense<float>(c, p, &c->d32, &c->d32_own));
+    } else {
+        DPT_TRY(stage_dense<float>(c, p, &c->d32, &c->d32_own));
+        unsigned int *flag = nullptr;
+        DPT_TRY(dalloc(&flag, 1));
+        DPT_TRY(launch_fill_zero(flag, 4, s));
+        DPT_TRY(launch_symmetry_check_f32(c->d32, ld, flag, s));
+        unsigned int h = 0;
+        DPT_TRY(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s));
+        DPT_TRY(hipStreamSynchronize(s));
+        (void)hipFree(flag);
+        c->symmetric = (h == 0);
+        if (prec == DPT_FP64) {
+            DPT_TRY(dalloc(&c->d64, nn));
+            c->d64_own = true;
+            DPT_TRY(launch_cvt_f32_to_f64(c->d64, c->d32, (int64_t)nn, s));
+        }
+    }
+    if (prec == DPT_FP64) {
+        int rc = ensure_f64(c);
+        if (rc != DPT_OK) return rc;
+        c->phase = PH_FP64;
+        if (z0) {
+            DPT_TRY(launch_load_state_f64(c->W64[0], z0, p->dtype == DPT_DTYPE_F64, c->n, ld, s));
+            c->at_identity = false;
+        }
+    } else {
+        if (c->symmetric) {
+            c->dT32 = c->d32;
+        } else {
+            DPT_TRY(dalloc(&c->dT32, nn));
+            DPT_TRY(launch_transpose_f32(c->dT32, c->d32, ld, s));
+        }
+        for (int i = 0; i < 2; ++i) {
+            DPT_TRY(dalloc(&c->W32[i], nn));
+            DPT_TRY(launch_fill_zero(c->W32[i], nn * 4, s));
+        }
+        if (prec == DPT_BF16_FP32) {
+            DPT_TRY(dalloc(&c->db16, nn));
+            DPT_TRY(launch_cvt_f32_to_bf16(c->db16, c->d32, (int64_t)nn, s));
+            for (int i = 0; i < 2; ++i) {
+                DPT_TRY(dalloc(&c->Wb[i], nn));
+                DPT_TRY(launch_fill_zero(c->Wb[i], nn * 2, s));
+            }
+            c->phase = PH_BF16;
+        } else {
+            c->phase = PH_FP32;
+        }
+        if (z0) {
+            DPT_TRY(launch_load_state_f32(c->W32[0], z0, p->dtype == DPT_DTYPE_F64, c->n, ld, s));
+            if (c->phase == PH_BF16) DPT_TRY(launch_cvt_f32_to_bf16(c->Wb[0], c->W32[0], (int64_t)nn, s));
+            c->at_identity = false;
+        }
+    }
+    return DPT_OK;
+}
+
+// E = theta + lambda d from the current state, into c->evec.
+int compute_eigenvalues(dpt_ctx *c) {
+    if (c->sp) return map_err(sparse_eigenvalues(c->sp, c->lambda, c->theta, c->evec, c->stream));
+    const StepArgs a = step_args(c, nullptr);
+    if (c->phase == PH_FP64) {
+        DPT_TRY(launch_prepass_f64_f64(c->W64[c->cur], c->d64, a, c->dvec, c->evec, nullptr, c->stream));
+    } else if (c->d64) {
+        DPT_TRY(launch_prepass_f32_f64(c->W32[c->cur], c->d64, a, c->dvec, c->evec, nullptr, c->stream));
+    } else {
+        DPT_TRY(launch_prepass_f32_f32(c->W32[c->cur], c->d32, a, c->dvec, c->evec, nullptr, c->stream));
+    }
+    return DPT_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+void dpt_options_default(dpt_options *o) {
+    if (!o) return;
+    o->tol = 1e-6;
+    o->fp64_final_tol = 0.0;
+    o->stall_ratio = 0.5;
+    o->blowup = 1e6;
+    o->max_iter = 200;
+    o->precision = DPT_FP32;
+    o->stall_patience = 2;
+    o->check_every = 1;
+}
+
+int dpt_validate(const dpt_problem *p, const dpt_options *o) {
+    if (!p || p->n < 1 || !p->theta || !p->delta) return DPT_EINVAL;
+    if (p->format != DPT_DENSE && p->format != DPT_CSR) return DPT_EINVAL;
+    if (p->dtype != DPT_DTYPE_F64 && p->dtype != DPT_DTYPE_F32) return DPT_EINVAL;
+    if (p->mem != DPT_MEM_HOST && p->mem != DPT_MEM_DEVICE) return DPT_EINVAL;
+    if (p->reserved != 0 || !std::isfinite(p->lambda)) return DPT_EINVAL;
+    if (p->n > (int64_t)1 << 31) return DPT_EINVAL;
+    if (p->format == DPT_CSR) {
+        if (!p->indptr || !p->indices || p->nnz < 0 || p->nnz >= ((int64_t)1 << 31)) return DPT_EINVAL;
+        if (p->mem == DPT_MEM_HOST && !csr_ok(p->indptr, p->indices, p->n, p->nnz)) return DPT_EINVAL;
+    }
+    if (p->mem == DPT_MEM_HOST && !theta_ok(p->theta, p->n)) return DPT_EINVAL;
+    if (!valid_options(o)) return DPT_EINVAL;
+    return DPT_OK;
+}
+
+int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const void *z0) {
+    if (!h) return DPT_EINVAL;
+    int rc = dpt_validate(p, o);
+    if (rc != DPT_OK) return rc;
+    if (p->format == DPT_CSR && z0) return DPT_EINVAL;  // warm start: dense problems only
+    rc = check_device();
+    if (rc != DPT_OK) return rc;
+    dpt_ctx *c = new (std::nothrow) dpt_ctx();
+    if (!c) return DPT_ENOMEM;
+    auto fail = [&](int code) {
+        (void)hipStreamSynchronize(c->stream);
+        delete c;
+        return code;
+    };
+    c->n = p->n;
+    c->lambda = p->lambda;
+    c->stream = (hipStream_t)p->stream;
+    if (o) {
+        c->opt = *o;
+    } else {
+        dpt_options_default(&c->opt);
+    }
+    c->format = p->format;
+    c->in_dtype = p->dtype;
+    c->mem = p->mem;
+    c->ld = p->format == DPT_CSR ? sparse_pad_order(p->n) : pad_order(p->n);
+
+    // theta: validate on the host, upload padded with zeros
+    std::vector<double> th((size_t)c->ld, 0.0);
+    if (p->mem == DPT_MEM_DEVICE) {
+        if (hipMemcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(DPT_EDEVICE);
+        if (!theta_ok(th.data(), p->n)) return fail(DPT_EINVAL);
+    } else {
+        std::memcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n);
+    }
+    if (dalloc(&c->theta, (size_t)c->ld) != hipSuccess || dalloc(&c->dvec, (size_t)c->ld) != hipSuccess ||
+        dalloc(&c->evec, (size_t)c->ld) != hipSuccess || dalloc(&c->stats, (size_t)2 * kStatRing) != hipSuccess)
+        return fail(DPT_ENOMEM);
+    if (hipHostMalloc((void **)&c->stats_host, sizeof(unsigned long long) * 2 * kStatRing, 0) != hipSuccess)
+        return fail(DPT_ENOMEM);
+    if (hipMemcpyAsync(c->theta, th.data(), sizeof(double) * (size_t)c->ld, hipMemcpyHostToDevice, c->stream) !=
+        hipSuccess)
+        return fail(DPT_EDEVICE);
+    if (launch_fill_zero(c->dvec, sizeof(double) * (size_t)c->ld, c->stream) != hipSuccess ||
+        launch_fill_zero(c->evec, sizeof(double) * (size_t)c->ld, c->stream) != hipSuccess ||
+        launch_zero_u64(c->stats, 2 * kStatRing, c->stream) != hipSuccess)
+        return fail(DPT_EDEVICE);
+
+    if (p->format == DPT_CSR) {
+        rc = map_err(sparse_create(&c->sp, p, c->opt.precision == DPT_FP64, c->ld, c->stream));
+        if (rc == DPT_OK && !c->sp) rc = DPT_ENOMEM;
+        if (rc == DPT_OK) c->phase = c->opt.precision == DPT_FP64 ? PH_FP64 : PH_FP32;
+    } else {
+        rc = init_dense(c, p, z0);
+    }
+    if (rc != DPT_OK) return fail(rc);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(DPT_EDEVICE);
+    *h = c;
+    return DPT_OK;
+}
+
+int dpt_step(dpt_handle h, int nsteps, double *last_delta) {
+    if (!h || nsteps < 0) return DPT_EINVAL;
+    if (last_delta) *last_delta = std::numeric_limits<double>::quiet_NaN();
+    for (int i = 0; i < nsteps; ++i) {
+        int rc = do_step(h);
+        if (rc != DPT_OK) return rc;
+    }
+    if (nsteps > 0) {
+        int rc = fetch_stats(h, h->k - 1, h->k);
+        if (rc != DPT_OK) return rc;
+        double dl, wm;
+        stat_of(h, h->k - 1, &dl, &wm);
+        if (last_delta) *last_delta = dl;
+    } else {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return DPT_EDEVICE;
+    }
+    return DPT_OK;
+}
+
+int dpt_solve(dpt_handle h, dpt_result *r) {
+    if (!h) return DPT_EINVAL;
+    const dpt_options &o = h->opt;
+    int status = DPT_NOT_CONVERGED;
+    int iters = 0, it_phase[3] = {0, 0, 0};
+    double best = std::numeric_limits<double>::infinity();
+    int stall_run = 0;
+    double last = std::numeric_limits<double>::quiet_NaN();
+    int64_t checked = h->k;  // stats already consumed
+    bool done = false;
+    while (!done && iters < o.max_iter) {
+        int rc = do_step(h);
+        if (rc != DPT_OK) return rc;
+        ++iters;
+        ++it_phase[h->phase];
+        if (iters % o.check_every != 0 && iters < o.max_iter) continue;
+        rc = fetch_stats(h, checked, h->k);
+        if (rc != DPT_OK) return rc;
+        for (int64_t s = checked; s < h->k; ++s) {
+            double dl, wm;
+            stat_of(h, s, &dl, &wm);
+            const int idx = iters - (int)(h->k - s);
+            if (r && r->delta_history && idx >= 0 && idx < r->history_cap) r->delta_history[idx] = dl;
+        }
+        checked = h->k;
+        double dl, wm;
+        stat_of(h, h->k - 1, &dl, &wm);
+        last = dl;
+        if (!std::isfinite(dl) || !(wm <= o.blowup)) {
+            status = DPT_DIVERGED;
+            break;
+        }
+        // A stall is a rounding floor: no progress while delta already sits within
+        // a few thousand ulps (of the phase's precision) of the state's magnitude.
+        // Larger non-decreasing deltas are cycles or chaos and run to the cap.
+        static const double kFloor[3] = {1.0, 1e4 * 5.96e-8, 1e4 * 1.11e-16};
+        bool stalled = false;
+        if (dl == 0.0) {
+            stalled = true;
+        } else if (dl >= o.stall_ratio * best && dl <= kFloor[h->phase] * std::max(1.0, wm)) {
+            stalled = ++stall_run >= o.stall_patience;
+        } else {
+            stall_run = 0;
+        }
+        best = std::min(best, dl);
+        if (h->phase == PH_BF16) {
+            // The BF16 fixed point is biased: always finish with FP32 sweeps.
+            if (dl < o.tol || stalled) {
+                h->phase = PH_FP32;
+                best = std::numeric_limits<double>::infinity();
+                stall_run = 0;
+            }
+        } else if (h->phase == PH_FP32) {
+            if (dl < o.tol) {
+                if (o.fp64_final_tol > 0.0 && !h->sp) {
+                    rc = enter_fp64(h);
+                    if (rc != DPT_OK) return rc;
+                    best = std::numeric_limits<double>::infinity();
+                    stall_run = 0;
+                } else {
+                    status = DPT_OK;
+                    done = true;
+                }
+            } else if (stalled) {
+                status = DPT_STALLED;
+                done = true;
+            }
+        } else {
+            const double target = (o.precision == DPT_FP64) ? o.tol : o.fp64_final_tol;
+            if (dl < target) {
+                status = DPT_OK;
+                done = true;
+            } else if (stalled) {
+                status = DPT_STALLED;
+                done = true;
+            }
+        }
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return DPT_EDEVICE;
+    if (r) {
+        r->status = status;
+        r->iters = iters;
+        r->iters_bf16 = it_phase[PH_BF16];
+        r->iters_fp32 = it_phase[PH_FP32];
+        r->iters_fp64 = it_phase[PH_FP64];
+        r->last_delta = last;
+    }
+    return status;
+}
+
+int dpt_eigenvalues(dpt_handle h, double *E, int mem) {
+    if (!h || !E || (mem != DPT_MEM_HOST && mem != DPT_MEM_DEVICE)) return DPT_EINVAL;
+    int rc = compute_eigenvalues(h);
+    if (rc != DPT_OK) return rc;
+    DPT_TRY(hipMemcpyAsync(E, h->evec, sizeof(double) * (size_t)h->n,
+                           mem == DPT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
+    DPT_TRY(hipStreamSynchronize(h->stream));
+    return DPT_OK;
+}
+
+int dpt_eigenvectors(dpt_handle h, void *Z, int dtype, int mem) {
+    if (!h || !Z || (mem != DPT_MEM_HOST && mem != DPT_MEM_DEVICE)) return DPT_EINVAL;
+    if (dtype != DPT_DTYPE_F32 && dtype != DPT_DTYPE_F64) return DPT_EINVAL;
+    const size_t bytes = (size_t)(h->n * h->n) * (dtype == DPT_DTYPE_F64 ? 8 : 4);
+    void *dst = Z;
+    void *tmp = nullptr;
+    if (mem == DPT_MEM_HOST) {
+        DPT_TRY(hipMalloc(&tmp, bytes));
+        dst = tmp;
+    }
+    hipError_t e;
+    if (h->sp)
+        e = sparse_export(h->sp, h->n, dst, dtype == DPT_DTYPE_F64, h->stream);
+    else if (h->phase == PH_FP64)
+        e = launch_export_f64(h->W64[h->cur], h->n, h->ld, dst, dtype == DPT_DTYPE_F64, h->stream);
+    else
+        e = launch_export_f32(h->W32[h->cur], h->n, h->ld, dst, dtype == DPT_DTYPE_F64, h->stream);
+    if (e == hipSuccess && tmp) e = hipMemcpyAsync(Z, tmp, bytes, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (tmp) (void)hipFree(tmp);
+    return map_err(e);
+}
+
+int dpt_residuals(dpt_handle h, int64_t nrows, const int64_t *rows, double *res) {
+    if (!h || nrows < 1 || !rows || !res) return DPT_EINVAL;
+    for (int64_t i = 0; i < nrows; ++i)
+        if (rows[i] < 0 || rows[i] >= h->n) return DPT_EINVAL;
+    if (h->sp) {
+        int rc = compute_eigenvalues(h);
+        if (rc != DPT_OK) return rc;
+        return map_err(sparse_residuals(h->sp, h->lambda, h->theta, h->evec, rows, nrows, res, h->stream));
+    }
+    int rc = compute_eigenvalues(h);
+    if (rc != DPT_OK) return rc;
+    const int nch = residual_chunks(h->ld);
+    int64_t *drows = nullptr;
+    double *part = nullptr;
+    hipError_t e = dalloc(&drows, (size_t)nrows);
+    if (e == hipSuccess) e = dalloc(&part, (size_t)(nrows * nch));
+    if (e == hipSuccess) e = hipMemcpyAsync(drows, rows, sizeof(int64_t) * nrows, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+        const StepArgs a = step_args(h, nullptr);
+        const void *D = h->d64 ? (const void *)h->d64 : (const void *)h->d32;
+        const int d64 = h->d64 ? 1 : 0;
+        e = h->phase == PH_FP64 ? launch_residual_f64(h->W64[h->cur], D, d64, a, drows, nrows, h->evec, part, h->stream)
+                                : launch_residual_f32(h->W32[h->cur], D, d64, a, drows, nrows, h->evec, part, h->stream);
+    }
+    std::vector<double> hp((size_t)(nrows * nch));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (drows) (void)hipFree(drows);
+    if (part) (void)hipFree(part);
+    if (e != hipSuccess) return map_err(e);
+    for (int64_t i = 0; i < nrows; ++i) {
+        double s = 0.0;
+        for (int c = 0; c < nch; ++c) s += hp[(size_t)(i * nch + c)];
+        res[i] = std::sqrt(s);
+    }
+    return DPT_OK;
+}
+
+int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval, void *eigvec,
+                 dpt_result *r) {
+    int rc = dpt_validate(p, o);
+    if (rc != DPT_OK) return rc;
+    if (!eigval || !eigvec || index >= p->n) return DPT_EINVAL;
+    rc = check_device();
+    if (rc != DPT_OK) return rc;
+    dpt_options opt;
+    if (o) {
+        opt = *o;
+    } else {
+        dpt_options_default(&opt);
+    }
+    std::vector<double> th((size_t)p->n);
+    if (p->mem == DPT_MEM_DEVICE) {
+        if (hipMemcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost) != hipSuccess)
+            return DPT_EDEVICE;
+        if (!theta_ok(th.data(), p->n)) return DPT_EINVAL;
+    } else {
+        std::memcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n);
+    }
+    if (index < 0) index = (int64_t)(std::max_element(th.begin(), th.end()) - th.begin());
+    return dominant_solve(p, &opt, th.data(), index, eigval, eigvec, r);
+}
+
+void dpt_destroy(dpt_handle h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+const char *dpt_status_str(int code) {
+    switch (code) {
+        case DPT_OK: return "DPT_OK: converged";
+        case DPT_NOT_CONVERGED: return "DPT_NOT_CONVERGED: iteration cap reached";
+        case DPT_STALLED: return "DPT_STALLED: stopped improving above the tolerance";
+        case DPT_DIVERGED: return "DPT_DIVERGED: non-finite iterate or |Z - I| above the blow-up bound";
+        case DPT_EAGAIN: return "DPT_EAGAIN: result not ready";
+        case DPT_EINVAL: return "DPT_EINVAL: invalid argument";
+        case DPT_ENOMEM: return "DPT_ENOMEM: out of memory";
+        case DPT_EDEVICE: return "DPT_EDEVICE: HIP runtime error or no gfx950 device";
+        case DPT_ESTATE: return "DPT_ESTATE: call not valid in this state";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal launch interface between the host runtime and the HIP kernels.
+// Not part of the public ABI (include/dpt.h).
+//
+// Device state layout (dense path): all N x N matrices are stored padded to
+// ld x ld (ld a multiple of 64), row-major, zero outside the leading N x N
+// block.  The eigenvector state is W = Z - I (zero diagonal): row n of Z is the
+// candidate eigenvector z_n in the chart z_n[n] = 1 (Sec. II.B of the paper).
+// Sparse path: the state is stored transposed, WT[m * ld + n] = W[n][m], so that
+// one CSR non-zero of Delta touches a contiguous run of eigenvectors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpt {
+
+// stats slot layout: two u64 per step, holding the bit patterns of non-negative
+// doubles so that unsigned max equals numeric max (NaN sorts above +inf):
+//   slot[0] = delta_k = max |W_k - W_{k-1}|,  slot[1] = max |W_k|.
+constexpr int kStatRing = 4096;
+
+enum Phase { PH_BF16 = 0, PH_FP32 = 1, PH_FP64 = 2 };
+
+struct StepArgs {
+    int64_t n;                 // valid order N
+    int64_t ld;                // padded leading dimension
+    double lambda;
+    const double *theta;       // ld entries (pad entries arbitrary but finite)
+    const double *d;           // ld entries: d_n = (Delta z_n)[n] of the current state
+    unsigned long long *stat;  // 2 u64 for this step (zeroed before the step)
+};
+
+// ---- dense kernels (kernels_dense.hip) -----------------------------------
+hipError_t launch_zero_u64(unsigned long long *p, int64_t count, hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+// dst (ld x ld, Tdst) <- src (n x n row-major, Tsrc) with zero padding.
+hipError_t launch_pad_copy_f32_from_f32(float *dst, const float *src, int64_t n, int64_t ld, hipStream_t s);
+hipError_t launch_pad_copy_f32_from_f64(float *dst, const double *src, int64_t n, int64_t ld, hipStream_t s);
+hipError_t launch_pad_copy_f64_from_f64(double *dst, const double *src, int64_t n, int64_t ld, hipStream_t s);
+hipError_t launch_pad_copy_f64_from_f32(double *dst, const float *src, int64_t n, int64_t ld, hipStream_t s);
+// Start state from a caller-given Z (n x n): W = Z - I with the diagonal forced to 0.
+hipError_t launch_load_state_f32(float *W, const void *z0, int z0_is_f64, int64_t n, int64_t ld, hipStream_t s);
+hipError_t launch_load_state_f64(double *W, const void *z0, int z0_is_f64, int64_t n, int64_t ld, hipStream_t s);
+
+hipError_t launch_cvt_f32_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s);
+hipError_t launch_cvt_f32_to_f64(double *dst, const float *src, int64_t count, hipStream_t s);
+hipError_t launch_transpose_f32(float *dst, const float *src, int64_t ld, hipStream_t s);
+hipError_t launch_transpose_f64(double *dst, const double *src, int64_t ld, hipStream_t s);
+// *flag |= 1 when src != src^T anywhere (bitwise).  flag must be zeroed first.
+hipError_t launch_symmetry_check_f32(const float *src, int64_t ld, unsigned int *flag, hipStream_t s);
+hipError_t launch_symmetry_check_f64(const double *src, int64_t ld, unsigned int *flag, hipStream_t s);
+
+// First application of F from A = I: W_1[n][m] = lambda Delta[m][n] / (theta_n - theta_m).
+hipError_t launch_first_iterate_f32(const StepArgs &a, const float *deltaT, float *W, __bf16 *Wb, hipStream_t s);
+hipError_t launch_first_iterate_f64(const StepArgs &a, const double *deltaT, double *W, hipStream_t s);
+
+// d_n = Delta[n][n] + sum_k W[n][k] Delta[n][k] (FP64 accumulation); E_n = theta_n + lambda d_n
+// when E != NULL.  stat_clear (may be NULL) is zeroed (2 u64).
+hipError_t launch_prepass_f32_f32(const float *W, const float *D, const StepArgs &a, double *d, double *E,
+                                  unsigned long long *stat_clear, hipStream_t s);
+hipError_t launch_prepass_f32_f64(const float *W, const double *D, const StepArgs &a, double *d, double *E,
+                                  unsigned long long *stat_clear, hipStream_t s);
+hipError_t launch_prepass_f64_f64(const double *W, const double *D, const StepArgs &a, double *d, double *E,
+                                  unsigned long long *stat_clear, hipStream_t s);
+
+// One fused step: C = W Delta^T on MFMA, then
+//   W'[n][m] = lambda (Delta[m][n] + C[n][m] - d_n W[n][m]) / (theta_n - theta_m)   (m != n)
+// and the stats.  BF16: A = Wb, B = Deltab, epilogue in FP32 with W (FP32) and
+// deltaT (FP32); writes W' (FP32) and Wb' (BF16).
+hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
+                            const float *W, float *Wn, __bf16 *Wbn, hipStream_t s);
+hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta, const float *deltaT,
+                           float *Wn, __bf16 *Wbn, hipStream_t s);
+hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT,
+                           double *Wn, hipStream_t s);
+
+// Z export: out[i*n + j] = (i == j) ? 1 : W[i*ld + j], as float or double.
+hipError_t launch_export_f32(const float *W, int64_t n, int64_t ld, void *out, int out_f64, hipStream_t s);
+hipError_t launch_export_f64(const double *W, int64_t n, int64_t ld, void *out, int out_f64, hipStream_t s);
+
+// Residual check (FP64): for each of nrows eigenvector rows r, partial sums of
+// |(M z)_m - E z_m|^2 over m-chunks into part[r * nchunks + c].
+int residual_chunks(int64_t ld);
+hipError_t launch_residual_f32(const float *W, const void *D, int d_is_f64, const StepArgs &a,
+                               const int64_t *rows, int64_t nrows, const double *E, double *part, hipStream_t s);
+hipError_t launch_residual_f64(const double *W, const void *D, int d_is_f64, const StepArgs &a,
+                               const int64_t *rows, int64_t nrows, const double *E, double *part, hipStream_t s);
+
+}  // namespace dpt

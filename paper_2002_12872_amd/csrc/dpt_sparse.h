@@ -1,0 +1,41 @@
+// Internal interface of the CSR (sparse Delta) path and of the single-vector
+// dominant-eigenvector mode.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dpt.h"
+
+namespace dpt {
+
+struct SparseState;
+
+// Padded order of the transposed sparse-path state (multiple of the SpMM panel).
+int64_t sparse_pad_order(int64_t n);
+
+// Stage the CSR Delta of p (host or device) and allocate the transposed state
+// WT[m * ld + n] = W[n][m] (two buffers, FP32 or FP64).  *out is NULL on failure.
+hipError_t sparse_create(SparseState **out, const dpt_problem *p, bool fp64, int64_t ld, hipStream_t s);
+void sparse_destroy(SparseState *sp);
+
+// One application of eq. (dyn) with the CSR product; stats go to ring slot *k
+// of `stats` (2 u64 per slot), then *k is incremented.
+int sparse_step(SparseState *sp, double lambda, const double *theta, unsigned long long *stats, int64_t *k,
+                hipStream_t s);
+
+// E_n = theta_n + lambda (Delta z_n)[n] of the current iterate, into evec (device).
+hipError_t sparse_eigenvalues(SparseState *sp, double lambda, const double *theta, double *evec, hipStream_t s);
+
+// out[i * n + j] = Z[i][j] (eigenvector i), float or double, device memory.
+hipError_t sparse_export(SparseState *sp, int64_t n, void *out, int out_f64, hipStream_t s);
+
+// ||M z_j - E_j z_j||_2 for the host-given rows; res on the host.
+hipError_t sparse_residuals(SparseState *sp, double lambda, const double *theta, const double *evec,
+                            const int64_t *rows, int64_t nrows, double *res, hipStream_t s);
+
+// Dominant-eigenvector mode: iterate the single-line map F_index from e_index.
+int dominant_solve(const dpt_problem *p, const dpt_options *o, const double *theta_host, int64_t index,
+                   double *eigval, void *eigvec, dpt_result *r);
+
+}  // namespace dpt

@@ -1,0 +1,649 @@
+// Dense-path kernels for gfx950 (MI355X): staging, first iterate, diagonal
+// pre-pass, the fused MFMA step (product W Delta^T + update of eq. (dyn)),
+// export and residual check.
+//
+// Paper: Kenmoe, Smerlak, Zadorin, arXiv:2002.12872.  With W = A - I (zero
+// diagonal) and C = A Delta' = Delta' + W Delta', one application of eq. (dyn) is
+//   W'[n][m] = lambda (C[n][m] - C[n][n] W[n][m]) / (theta_n - theta_m),  m != n,
+// and the eigenvalue readout of Sec. II.B is E_n = theta_n + lambda C[n][n].
+#include <float.h>
+
+#include "dpt_internal.h"
+
+namespace dpt {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16_t;
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4_t;
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr unsigned long long kNanBits = 0x7ff8000000000000ull;
+
+inline unsigned int grid_1d(int64_t work_items, int64_t cap = 1 << 20) {
+    int64_t blocks = (work_items + kThreads - 1) / kThreads;
+    if (blocks < 1) blocks = 1;
+    if (blocks > cap) blocks = cap;
+    return (unsigned int)blocks;
+}
+
+__device__ __forceinline__ unsigned long long dbits(double x) {
+    return (unsigned long long)__double_as_longlong(x);
+}
+
+// Wave-wide max of (delta, |w|) plus a non-finite flag; lane 0 of every wave
+// publishes with one atomicMax per value (max is order-independent, so the
+// result is deterministic).  Must be reached by all 64 lanes.
+__device__ __forceinline__ void publish_stats(unsigned long long *stat, double dmax, double wmax, bool bad) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        dmax = fmax(dmax, __shfl_xor(dmax, o));
+        wmax = fmax(wmax, __shfl_xor(wmax, o));
+    }
+    const bool any_bad = __any(bad ? 1 : 0);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(stat, any_bad ? kNanBits : dbits(dmax));
+        atomicMax(stat + 1, any_bad ? kNanBits : dbits(wmax));
+    }
+}
+
+// ----------------------------------------------------------------- utilities
+__global__ void k_zero_u64(unsigned long long *p, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+__global__ void k_fill_zero_u32(unsigned int *p, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+template <typename TD, typename TS>
+__global__ void k_pad_copy(TD *__restrict__ dst, const TS *__restrict__ src, int64_t n, int64_t ld) {
+    const int64_t total = ld * ld;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / ld, c = i - r * ld;
+        dst[i] = (r < n && c < n) ? (TD)src[r * n + c] : (TD)0;
+    }
+}
+
+template <typename TD, typename TS>
+__global__ void k_load_state(TD *__restrict__ W, const TS *__restrict__ z0, int64_t n, int64_t ld) {
+    const int64_t total = ld * ld;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / ld, c = i - r * ld;
+        W[i] = (r < n && c < n && r != c) ? (TD)z0[r * n + c] : (TD)0;
+    }
+}
+
+__global__ void k_cvt_f32_bf16(__bf16 *__restrict__ dst, const float *__restrict__ src, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (__bf16)src[i];
+}
+
+__global__ void k_cvt_f32_f64(double *__restrict__ dst, const float *__restrict__ src, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
+// 64x64 tiles through LDS: dst[i][j] = src[j][i].  grid = (ld/64, ld/64).
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ src, T *__restrict__ dst, int64_t ld) {
+    __shared__ T tile[64][65];
+    const int64_t bx = blockIdx.x, by = blockIdx.y;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) tile[r][tx] = src[(by * 64 + r) * ld + bx * 64 + tx];
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) dst[(bx * 64 + r) * ld + by * 64 + tx] = tile[tx][r];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_symmetry_check(const T *__restrict__ src, int64_t ld, unsigned int *flag) {
+    __shared__ T tile[64][65];
+    const int64_t bx = blockIdx.x, by = blockIdx.y;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) tile[r][tx] = src[(by * 64 + r) * ld + bx * 64 + tx];
+    __syncthreads();
+    bool diff = false;
+    for (int r = ty; r < 64; r += 4) {
+        // src[bx*64 + r][by*64 + tx] against its mirror src[by*64 + tx][bx*64 + r]
+        const T v = src[(bx * 64 + r) * ld + by * 64 + tx];
+        diff |= !(v == tile[tx][r]);
+    }
+    if (__any(diff ? 1 : 0) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+// ----------------------------------------------------------- first iterate
+// F(I) = I + lambda gap * Delta'  (the Hadamard with the gap removes any diagonal).
+template <typename T>
+__global__ __launch_bounds__(256) void k_first_iterate(StepArgs a, const T *__restrict__ dT, T *__restrict__ W,
+                                                       __bf16 *__restrict__ Wb) {
+    const int64_t total = a.ld * a.ld;
+    double dmax = 0.0;
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t n = i / a.ld, m = i - n * a.ld;
+        T w = (T)0;
+        if (n < a.n && m < a.n && n != m) w = (T)(a.lambda * (double)dT[i] / (a.theta[n] - a.theta[m]));
+        W[i] = w;
+        if (Wb) Wb[i] = (__bf16)(float)w;
+        const double v = fabs((double)w);
+        dmax = fmax(dmax, v);
+        bad |= !(v <= DBL_MAX);
+    }
+    publish_stats(a.stat, dmax, dmax, bad);
+}
+
+// ---------------------------------------------------------------- pre-pass
+__device__ __forceinline__ void load4(const float *p, double out[4]) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double *p, double out[4]) {
+    const double2 v0 = *reinterpret_cast<const double2 *>(p);
+    const double2 v1 = *reinterpret_cast<const double2 *>(p + 2);
+    out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+}
+
+// One block per row n; fixed per-thread strides and a fixed butterfly make the
+// FP64 sum deterministic.  Rows are ld-aligned and zero-padded, so the loop runs
+// over the whole padded row with 4-wide loads.
+template <typename TW, typename TD>
+__global__ __launch_bounds__(256) void k_prepass(const TW *__restrict__ W, const TD *__restrict__ D, StepArgs a,
+                                                 double *__restrict__ d, double *__restrict__ E,
+                                                 unsigned long long *stat_clear) {
+    const int64_t n = blockIdx.x;
+    const TW *w = W + n * a.ld;
+    const TD *dl = D + n * a.ld;
+    double s = 0.0;
+    for (int64_t k = 4 * (int64_t)threadIdx.x; k < a.ld; k += 4 * 256) {
+        double wv[4], dv[4];
+        load4(w + k, wv);
+        load4(dl + k, dv);
+        s += wv[0] * dv[0] + wv[1] * dv[1] + wv[2] * dv[2] + wv[3] * dv[3];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double dn = (double)dl[n] + ((red[0] + red[1]) + (red[2] + red[3]));
+        d[n] = dn;
+        if (E) E[n] = a.theta[n] + a.lambda * dn;
+        if (stat_clear && n == 0) {
+            stat_clear[0] = 0ull;
+            stat_clear[1] = 0ull;
+        }
+    }
+}
+
+// --------------------------------------------------------- fused MFMA step
+// MFMA policies.  Operand fragments: lane l holds KPL consecutive K elements of
+// row (l % MI) of its operand, from K-group (l / MI).  The accumulator layouts
+// are those of the CDNA3/CDNA4 matrix instructions:
+//   32x32 (16 values/lane): element r of lane l is C[(r&3) + 4*(l>>5) + 8*(r>>2)][l & 31]
+//   16x16 ( 4 values/lane): element r of lane l is C[r + 4*(l>>4)][l & 15]
+// Any permutation of K that is applied identically to both operands leaves the
+// product unchanged; each lane's K-group therefore walks a contiguous span of
+// the LDS row, which makes the LDS reads 16-byte vectors.
+struct PolBF16 {
+    using in_t = __bf16;
+    using frag_t = bf16x8_t;
+    using cvec_t = floatx16_t;
+    static constexpr int MI = 32, KPL = 8, KGROUPS = 2, NACC = 16;
+    static __device__ __forceinline__ cvec_t mma(frag_t x, frag_t y, cvec_t c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
+    }
+    // step s of a lane's K span held as 16-byte chunks
+    static __device__ __forceinline__ frag_t frag(const u32x4_t *chunks, int s) {
+        return __builtin_bit_cast(frag_t, chunks[s]);
+    }
+    static __device__ __forceinline__ int acc_row(int r, int lane) { return (r & 3) + ((lane >> 5) << 2) + ((r >> 2) << 3); }
+    static __device__ __forceinline__ int acc_col(int lane) { return lane & 31; }
+};
+
+__device__ __forceinline__ unsigned int u32_of(const u32x4_t &c, int e) { return c[e]; }
+
+struct PolF32 {
+    using in_t = float;
+    using frag_t = float;
+    using cvec_t = floatx16_t;
+    static constexpr int MI = 32, KPL = 1, KGROUPS = 2, NACC = 16;
+    static __device__ __forceinline__ cvec_t mma(frag_t x, frag_t y, cvec_t c) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ frag_t frag(const u32x4_t *chunks, int s) {
+        return __uint_as_float(u32_of(chunks[s >> 2], s & 3));
+    }
+    static __device__ __forceinline__ int acc_row(int r, int lane) { return (r & 3) + ((lane >> 5) << 2) + ((r >> 2) << 3); }
+    static __device__ __forceinline__ int acc_col(int lane) { return lane & 31; }
+};
+
+struct PolF64 {
+    using in_t = double;
+    using frag_t = double;
+    using cvec_t = doublex4_t;
+    static constexpr int MI = 16, KPL = 1, KGROUPS = 4, NACC = 4;
+    static __device__ __forceinline__ cvec_t mma(frag_t x, frag_t y, cvec_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ frag_t frag(const u32x4_t *chunks, int s) {
+        const u32x4_t c = chunks[s >> 1];
+        const unsigned long long lo = c[(s & 1) * 2], hi = c[(s & 1) * 2 + 1];
+        return __longlong_as_double((long long)(lo | (hi << 32)));
+    }
+    static __device__ __forceinline__ int acc_row(int r, int lane) { return r + ((lane >> 4) << 2); }
+    static __device__ __forceinline__ int acc_col(int lane) { return lane & 15; }
+};
+
+// Block -> output tile.  Workgroups are dispatched round-robin over the 8 XCDs
+// (bid % 8), so first make each XCD's blocks a contiguous range of logical tile
+// ids, then walk the tiles in groups of 8 tile-rows so that the blocks resident
+// on one XCD share operand panels in that XCD's L2.
+__device__ __forceinline__ void tile_coords(int bid, int nblocks, int tiles_m, int tiles_n, int &tm, int &tn) {
+    int t = bid;
+    if ((nblocks & 7) == 0) t = (bid & 7) * (nblocks >> 3) + (bid >> 3);
+    constexpr int G = 8;
+    const int group_size = G * tiles_n;
+    const int group = t / group_size;
+    const int first = group * G;
+    const int gm = min(tiles_m - first, G);
+    const int within = t - group * group_size;
+    tm = first + within % gm;
+    tn = within / gm;
+}
+
+template <class P, int BM, int BN, int BK, int WM, int WN, typename S>
+__global__ __launch_bounds__(WM *WN * 64) void k_step_gemm(const typename P::in_t *__restrict__ A,
+                                                           const typename P::in_t *__restrict__ B,
+                                                           const S *__restrict__ deltaT, const S *__restrict__ Wold,
+                                                           S *__restrict__ Wnew, __bf16 *__restrict__ Wbnew,
+                                                           StepArgs a, int tiles_m, int tiles_n) {
+    using in_t = typename P::in_t;
+    constexpr int NT = WM * WN * 64;
+    constexpr int VEC = 16 / (int)sizeof(in_t);  // elements per 16-byte chunk
+    constexpr int LDK = BK + VEC;                // row pitch with 16 bytes of padding
+    constexpr int WTM = BM / WM, WTN = BN / WN;  // wave tile
+    constexpr int TM = WTM / P::MI, TN = WTN / P::MI;
+    constexpr int KSPAN = BK / P::KGROUPS;       // K elements one lane reads per tile row
+    constexpr int STEPS = KSPAN / P::KPL;        // MFMAs per block pair per K-tile
+    constexpr int NV = KSPAN / VEC;
+    constexpr int CPR = BK / VEC;                // 16-byte chunks per tile row
+    constexpr int A_CH = BM * CPR / NT, B_CH = BN * CPR / NT;
+    static_assert(WTM % P::MI == 0 && WTN % P::MI == 0, "wave tile");
+    static_assert(KSPAN % VEC == 0 && KSPAN % P::KPL == 0, "K span");
+    static_assert((BM * CPR) % NT == 0 && (BN * CPR) % NT == 0, "load split");
+
+    __shared__ __attribute__((aligned(16))) in_t sA[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) in_t sB[2][BN * LDK];
+
+    int tm, tn;
+    tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WN, wc = wave % WN;
+    const int64_t ld = a.ld;
+    const int ktiles = (int)(ld / BK);
+
+    typename P::cvec_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < P::NACC; ++r) acc[i][j][r] = 0;
+
+    // global -> register staging (16-byte chunks), double-buffered LDS
+    const in_t *gA = A + row0 * ld;
+    const in_t *gB = B + col0 * ld;
+    u32x4_t ra[A_CH], rb[B_CH];
+#pragma unroll
+    for (int i = 0; i < A_CH; ++i) {
+        const int c = tid + i * NT;
+        ra[i] = *reinterpret_cast<const u32x4_t *>(gA + (int64_t)(c / CPR) * ld + (c % CPR) * VEC);
+    }
+#pragma unroll
+    for (int i = 0; i < B_CH; ++i) {
+        const int c = tid + i * NT;
+        rb[i] = *reinterpret_cast<const u32x4_t *>(gB + (int64_t)(c / CPR) * ld + (c % CPR) * VEC);
+    }
+#pragma unroll
+    for (int i = 0; i < A_CH; ++i) {
+        const int c = tid + i * NT;
+        *reinterpret_cast<u32x4_t *>(&sA[0][(c / CPR) * LDK + (c % CPR) * VEC]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_CH; ++i) {
+        const int c = tid + i * NT;
+        *reinterpret_cast<u32x4_t *>(&sB[0][(c / CPR) * LDK + (c % CPR) * VEC]) = rb[i];
+    }
+    __syncthreads();
+
+    const int grp = lane / P::MI, rr = lane % P::MI;
+    const int a_off = (wr * WTM + rr) * LDK + grp * KSPAN;
+    const int b_off = (wc * WTN + rr) * LDK + grp * KSPAN;
+    for (int kt = 0; kt < ktiles; ++kt) {
+        const int buf = kt & 1;
+        const bool more = kt + 1 < ktiles;
+        if (more) {
+            const int64_t koff = (int64_t)(kt + 1) * BK;
+#pragma unroll
+            for (int i = 0; i < A_CH; ++i) {
+                const int c = tid + i * NT;
+                ra[i] = *reinterpret_cast<const u32x4_t *>(gA + (int64_t)(c / CPR) * ld + koff + (c % CPR) * VEC);
+            }
+#pragma unroll
+            for (int i = 0; i < B_CH; ++i) {
+                const int c = tid + i * NT;
+                rb[i] = *reinterpret_cast<const u32x4_t *>(gB + (int64_t)(c / CPR) * ld + koff + (c % CPR) * VEC);
+            }
+        }
+        u32x4_t fa[TM][NV], fb[TN][NV];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                fa[i][v] = *reinterpret_cast<const u32x4_t *>(&sA[buf][a_off + i * P::MI * LDK + v * VEC]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                fb[j][v] = *reinterpret_cast<const u32x4_t *>(&sB[buf][b_off + j * P::MI * LDK + v * VEC]);
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s)
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = P::mma(P::frag(fa[i], s), P::frag(fb[j], s), acc[i][j]);
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < A_CH; ++i) {
+                const int c = tid + i * NT;
+                *reinterpret_cast<u32x4_t *>(&sA[buf ^ 1][(c / CPR) * LDK + (c % CPR) * VEC]) = ra[i];
+            }
+#pragma unroll
+            for (int i = 0; i < B_CH; ++i) {
+                const int c = tid + i * NT;
+                *reinterpret_cast<u32x4_t *>(&sB[buf ^ 1][(c / CPR) * LDK + (c % CPR) * VEC]) = rb[i];
+            }
+        }
+        __syncthreads();
+    }
+
+    // Epilogue: C = Delta^T (exact, state precision) + acc; update of eq. (dyn).
+    const S lam = (S)a.lambda;
+    double dmax = 0.0, wmax = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int64_t m = col0 + wc * WTN + j * P::MI + P::acc_col(lane);
+        const double th_m = a.theta[m];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+#pragma unroll
+            for (int r = 0; r < P::NACC; ++r) {
+                const int64_t n = row0 + wr * WTM + i * P::MI + P::acc_row(r, lane);
+                const int64_t idx = n * ld + m;
+                const S c = (S)acc[i][j][r] + deltaT[idx];
+                const S wo = Wold[idx];
+                S w = (S)0;
+                if (n < a.n && m < a.n && n != m) {
+                    const S num = c - (S)a.d[n] * wo;
+                    const S gap = (S)(a.theta[n] - th_m);
+                    w = lam * num / gap;
+                }
+                Wnew[idx] = w;
+                if (Wbnew) Wbnew[idx] = (__bf16)(float)w;
+                const double dv = fabs((double)w - (double)wo), av = fabs((double)w);
+                dmax = fmax(dmax, dv);
+                wmax = fmax(wmax, av);
+                bad |= !(dv <= DBL_MAX) || !(av <= DBL_MAX);
+            }
+        }
+    }
+    publish_stats(a.stat, dmax, wmax, bad);
+}
+
+// ------------------------------------------------------------------ export
+template <typename TW, typename TO>
+__global__ void k_export(const TW *__restrict__ W, int64_t n, int64_t ld, TO *__restrict__ out) {
+    const int64_t total = n * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / n, c = i - r * n;
+        out[i] = (r == c) ? (TO)1 : (TO)W[r * ld + c];
+    }
+}
+
+// ---------------------------------------------------------------- residual
+// grid = (nchunks, nrows); each wave computes (Delta z)[m] for rows m of the
+// chunk, z = e_j + W[j][:], and accumulates |(M z)_m - E_j z_m|^2.
+constexpr int kResChunk = 256;
+
+template <typename TW, typename TD>
+__global__ __launch_bounds__(256) void k_residual(const TW *__restrict__ W, const TD *__restrict__ D, StepArgs a,
+                                                  const int64_t *__restrict__ rows, const double *__restrict__ E,
+                                                  double *__restrict__ part) {
+    const int64_t j = rows[blockIdx.y];
+    const TW *wj = W + j * a.ld;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double ej = E[j];
+    double acc = 0.0;
+    const int64_t m_begin = (int64_t)blockIdx.x * kResChunk;
+    for (int64_t m = m_begin + wave; m < m_begin + kResChunk && m < a.n; m += 4) {
+        const TD *dm = D + m * a.ld;
+        double s = 0.0;
+        for (int64_t l = lane; l < a.n; l += 64) {
+            const double zl = (l == j) ? 1.0 : (double)wj[l];
+            s += (double)dm[l] * zl;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        const double zm = (m == j) ? 1.0 : (double)wj[m];
+        const double rm = a.theta[m] * zm + a.lambda * s - ej * zm;
+        acc += rm * rm;
+    }
+    __shared__ double red[4];
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <class P, int BM, int BN, int BK, int WM, int WN, typename S>
+hipError_t launch_gemm(const StepArgs &a, const typename P::in_t *A, const typename P::in_t *B, const S *deltaT,
+                       const S *Wold, S *Wnew, __bf16 *Wbnew, hipStream_t s) {
+    if (a.ld % BM || a.ld % BN || a.ld % BK) return hipErrorInvalidValue;
+    const int tiles_m = (int)(a.ld / BM), tiles_n = (int)(a.ld / BN);
+    const unsigned int blocks = (unsigned int)tiles_m * (unsigned int)tiles_n;
+    hipLaunchKernelGGL((k_step_gemm<P, BM, BN, BK, WM, WN, S>), dim3(blocks), dim3(WM * WN * 64), 0, s, A, B,
+                       deltaT, Wold, Wnew, Wbnew, a, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ============================================================== launchers
+hipError_t launch_zero_u64(unsigned long long *p, int64_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid_1d(count, 1024)), dim3(kThreads), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
+    if (bytes % 4) return hipErrorInvalidValue;
+    const int64_t count = (int64_t)(bytes / 4);
+    hipLaunchKernelGGL(k_fill_zero_u32, dim3(grid_1d(count)), dim3(kThreads), 0, s, (unsigned int *)p, count);
+    return hipGetLastError();
+}
+
+#define DPT_PAD_COPY(NAME, TD, TS)                                                                        \
+    hipError_t NAME(TD *dst, const TS *src, int64_t n, int64_t ld, hipStream_t s) {                      \
+        hipLaunchKernelGGL((k_pad_copy<TD, TS>), dim3(grid_1d(ld * ld)), dim3(kThreads), 0, s, dst, src, n, ld); \
+        return hipGetLastError();                                                                         \
+    }
+DPT_PAD_COPY(launch_pad_copy_f32_from_f32, float, float)
+DPT_PAD_COPY(launch_pad_copy_f32_from_f64, float, double)
+DPT_PAD_COPY(launch_pad_copy_f64_from_f64, double, double)
+DPT_PAD_COPY(launch_pad_copy_f64_from_f32, double, float)
+#undef DPT_PAD_COPY
+
+hipError_t launch_load_state_f32(float *W, const void *z0, int z0_is_f64, int64_t n, int64_t ld, hipStream_t s) {
+    if (z0_is_f64)
+        hipLaunchKernelGGL((k_load_state<float, double>), dim3(grid_1d(ld * ld)), dim3(kThreads), 0, s, W,
+                           (const double *)z0, n, ld);
+    else
+        hipLaunchKernelGGL((k_load_state<float, float>), dim3(grid_1d(ld * ld)), dim3(kThreads), 0, s, W,
+                           (const float *)z0, n, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_state_f64(double *W, const void *z0, int z0_is_f64, int64_t n, int64_t ld, hipStream_t s) {
+    if (z0_is_f64)
+        hipLaunchKernelGGL((k_load_state<double, double>), dim3(grid_1d(ld * ld)), dim3(kThreads), 0, s, W,
+                           (const double *)z0, n, ld);
+    else
+        hipLaunchKernelGGL((k_load_state<double, float>), dim3(grid_1d(ld * ld)), dim3(kThreads), 0, s, W,
+                           (const float *)z0, n, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_cvt_f32_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_cvt_f32_bf16, dim3(grid_1d(count)), dim3(kThreads), 0, s, dst, src, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_cvt_f32_to_f64(double *dst, const float *src, int64_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_cvt_f32_f64, dim3(grid_1d(count)), dim3(kThreads), 0, s, dst, src, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_f32(float *dst, const float *src, int64_t ld, hipStream_t s) {
+    if (ld % 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_transpose<float>), dim3(ld / 64, ld / 64), dim3(256), 0, s, src, dst, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_f64(double *dst, const double *src, int64_t ld, hipStream_t s) {
+    if (ld % 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_transpose<double>), dim3(ld / 64, ld / 64), dim3(256), 0, s, src, dst, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_symmetry_check_f32(const float *src, int64_t ld, unsigned int *flag, hipStream_t s) {
+    if (ld % 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_symmetry_check<float>), dim3(ld / 64, ld / 64), dim3(256), 0, s, src, ld, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_symmetry_check_f64(const double *src, int64_t ld, unsigned int *flag, hipStream_t s) {
+    if (ld % 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_symmetry_check<double>), dim3(ld / 64, ld / 64), dim3(256), 0, s, src, ld, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_first_iterate_f32(const StepArgs &a, const float *deltaT, float *W, __bf16 *Wb, hipStream_t s) {
+    hipLaunchKernelGGL((k_first_iterate<float>), dim3(grid_1d(a.ld * a.ld, 65536)), dim3(256), 0, s, a, deltaT, W,
+                       Wb);
+    return hipGetLastError();
+}
+
+hipError_t launch_first_iterate_f64(const StepArgs &a, const double *deltaT, double *W, hipStream_t s) {
+    hipLaunchKernelGGL((k_first_iterate<double>), dim3(grid_1d(a.ld * a.ld, 65536)), dim3(256), 0, s, a, deltaT, W,
+                       (__bf16 *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepass_f32_f32(const float *W, const float *D, const StepArgs &a, double *d, double *E,
+                                  unsigned long long *stat_clear, hipStream_t s) {
+    hipLaunchKernelGGL((k_prepass<float, float>), dim3((unsigned int)a.n), dim3(256), 0, s, W, D, a, d, E,
+                       stat_clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepass_f32_f64(const float *W, const double *D, const StepArgs &a, double *d, double *E,
+                                  unsigned long long *stat_clear, hipStream_t s) {
+    hipLaunchKernelGGL((k_prepass<float, double>), dim3((unsigned int)a.n), dim3(256), 0, s, W, D, a, d, E,
+                       stat_clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepass_f64_f64(const double *W, const double *D, const StepArgs &a, double *d, double *E,
+                                  unsigned long long *stat_clear, hipStream_t s) {
+    hipLaunchKernelGGL((k_prepass<double, double>), dim3((unsigned int)a.n), dim3(256), 0, s, W, D, a, d, E,
+                       stat_clear);
+    return hipGetLastError();
+}
+
+// Tile configurations: large problems (ld a multiple of 256) use the big tiles,
+// everything else the 64x64 tiles.
+hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
+                            const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
+    if (a.ld % 256 == 0 && a.ld >= 1024)
+        return launch_gemm<PolBF16, 256, 128, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
+    return launch_gemm<PolBF16, 64, 64, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
+}
+
+hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta, const float *deltaT, float *Wn,
+                           __bf16 *Wbn, hipStream_t s) {
+    if (a.ld % 256 == 0 && a.ld >= 1024)
+        return launch_gemm<PolF32, 128, 128, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
+    return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
+}
+
+hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT, double *Wn,
+                           hipStream_t s) {
+    return launch_gemm<PolF64, 64, 64, 16, 2, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
+}
+
+hipError_t launch_export_f32(const float *W, int64_t n, int64_t ld, void *out, int out_f64, hipStream_t s) {
+    if (out_f64)
+        hipLaunchKernelGGL((k_export<float, double>), dim3(grid_1d(n * n)), dim3(kThreads), 0, s, W, n, ld,
+                           (double *)out);
+    else
+        hipLaunchKernelGGL((k_export<float, float>), dim3(grid_1d(n * n)), dim3(kThreads), 0, s, W, n, ld,
+                           (float *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_f64(const double *W, int64_t n, int64_t ld, void *out, int out_f64, hipStream_t s) {
+    if (out_f64)
+        hipLaunchKernelGGL((k_export<double, double>), dim3(grid_1d(n * n)), dim3(kThreads), 0, s, W, n, ld,
+                           (double *)out);
+    else
+        hipLaunchKernelGGL((k_export<double, float>), dim3(grid_1d(n * n)), dim3(kThreads), 0, s, W, n, ld,
+                           (float *)out);
+    return hipGetLastError();
+}
+
+int residual_chunks(int64_t ld) { return (int)((ld + kResChunk - 1) / kResChunk); }
+
+hipError_t launch_residual_f32(const float *W, const void *D, int d_is_f64, const StepArgs &a, const int64_t *rows,
+                               int64_t nrows, const double *E, double *part, hipStream_t s) {
+    const dim3 grid(residual_chunks(a.ld), (unsigned int)nrows);
+    if (d_is_f64)
+        hipLaunchKernelGGL((k_residual<float, double>), grid, dim3(256), 0, s, W, (const double *)D, a, rows, E, part);
+    else
+        hipLaunchKernelGGL((k_residual<float, float>), grid, dim3(256), 0, s, W, (const float *)D, a, rows, E, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_f64(const double *W, const void *D, int d_is_f64, const StepArgs &a, const int64_t *rows,
+                               int64_t nrows, const double *E, double *part, hipStream_t s) {
+    const dim3 grid(residual_chunks(a.ld), (unsigned int)nrows);
+    if (d_is_f64)
+        hipLaunchKernelGGL((k_residual<double, double>), grid, dim3(256), 0, s, W, (const double *)D, a, rows, E,
+                           part);
+    else
+        hipLaunchKernelGGL((k_residual<double, float>), grid, dim3(256), 0, s, W, (const float *)D, a, rows, E, part);
+    return hipGetLastError();
+}
+
+}  // namespace dpt

@@ -1,0 +1,333 @@
+"""Thin ctypes binding of the C ABI declared in ``include/dpt.h``.
+
+Argument marshalling only: every step of the method runs in the HIP library
+``_lib/libdpt.so``.  Importing this module fails loudly when the library has not
+been built; there is no CPU fallback.
+
+Inputs may be numpy arrays / CPU tensors (host memory, copied by the library) or
+torch device tensors (borrowed by the library; keep them alive and unchanged
+while the handle lives).  Function names mirror the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libdpt.so")
+
+DPT_OK, DPT_NOT_CONVERGED, DPT_STALLED, DPT_DIVERGED, DPT_EAGAIN = 0, 1, 2, 3, 4
+DPT_EINVAL, DPT_ENOMEM, DPT_EDEVICE, DPT_ESTATE = -1, -2, -3, -4
+DPT_FP64, DPT_FP32, DPT_BF16_FP32 = 0, 1, 2
+DPT_DENSE, DPT_CSR = 0, 1
+DPT_MEM_HOST, DPT_MEM_DEVICE = 0, 1
+DPT_DTYPE_F64, DPT_DTYPE_F32 = 0, 1
+
+
+class DptError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s%s" % (what + ": " if what else "", status_str(code)))
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("theta", ctypes.c_void_p),
+        ("delta", ctypes.c_void_p),
+        ("indptr", ctypes.c_void_p),
+        ("indices", ctypes.c_void_p),
+        ("nnz", ctypes.c_int64),
+        ("lam", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("format", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("mem", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("fp64_final_tol", ctypes.c_double),
+        ("stall_ratio", ctypes.c_double),
+        ("blowup", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("stall_patience", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("last_delta", ctypes.c_double),
+        ("delta_history", ctypes.c_void_p),
+        ("history_cap", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("iters_bf16", ctypes.c_int32),
+        ("iters_fp32", ctypes.c_int32),
+        ("iters_fp64", ctypes.c_int32),
+    ]
+
+
+_FUNCS = {
+    "dpt_options_default": (None, [ctypes.POINTER(Options)]),
+    "dpt_validate": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options)]),
+    "dpt_init": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Problem),
+                                ctypes.POINTER(Options), ctypes.c_void_p]),
+    "dpt_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "dpt_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Result)]),
+    "dpt_eigenvalues": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "dpt_eigenvectors": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "dpt_residuals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "dpt_dominant": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                    ctypes.POINTER(Result)]),
+    "dpt_destroy": (None, [ctypes.c_void_p]),
+    "dpt_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdpt.so (raises if it has not been built: no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError("libdpt.so not found at %s; run paper_2002_12872_amd.build.build()" % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _FUNCS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def status_str(code: int) -> str:
+    return load_library().dpt_status_str(int(code)).decode()
+
+
+dpt_status_str = status_str
+
+
+# ------------------------------------------------------------ marshalling
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _info(x):
+    """(pointer, dtype code or None, is_device, keep-alive object) of an array-like."""
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        dev = x.is_cuda
+        dt = str(x.dtype)
+        return x.data_ptr(), dt, dev, x
+    a = np.ascontiguousarray(x)
+    return a.ctypes.data, str(a.dtype), False, a
+
+
+def _dtype_code(dt):
+    if dt in ("float64", "torch.float64"):
+        return DPT_DTYPE_F64
+    if dt in ("float32", "torch.float32"):
+        return DPT_DTYPE_F32
+    raise ValueError("delta values must be float32 or float64, got %s" % dt)
+
+
+class ProblemSpec:
+    """A ``dpt_problem`` plus references keeping its arrays alive."""
+
+    def __init__(self, theta, delta, lam, stream=None):
+        keep = []
+        tp, tdt, tdev, tk = _info(theta if _is_torch(theta) else np.asarray(theta, np.float64))
+        if tdt not in ("float64", "torch.float64"):
+            raise ValueError("theta must be float64")
+        keep.append(tk)
+        st = Problem()
+        st.theta = tp
+        st.lam = float(lam)
+        st.reserved = 0
+        if isinstance(delta, tuple):
+            indptr, indices, values = delta
+            ip, ipdt, ipdev, ipk = _info(indptr if _is_torch(indptr) else np.asarray(indptr, np.int64))
+            ix, ixdt, ixdev, ixk = _info(indices if _is_torch(indices) else np.asarray(indices, np.int32))
+            vp, vdt, vdev, vk = _info(values)
+            if ipdt not in ("int64", "torch.int64") or ixdt not in ("int32", "torch.int32"):
+                raise ValueError("CSR needs int64 indptr and int32 indices")
+            devs = {tdev, ipdev, ixdev, vdev}
+            keep += [ipk, ixk, vk]
+            st.format = DPT_CSR
+            st.indptr, st.indices, st.delta = ip, ix, vp
+            st.nnz = int(values.shape[0])
+            st.n = int(indptr.shape[0]) - 1
+            st.dtype = _dtype_code(vdt)
+        else:
+            dp, ddt, ddev, dk = _info(delta)
+            devs = {tdev, ddev}
+            keep.append(dk)
+            st.format = DPT_DENSE
+            st.delta = dp
+            st.indptr = st.indices = None
+            st.nnz = 0
+            st.n = int(delta.shape[0])
+            if tuple(delta.shape) != (st.n, st.n):
+                raise ValueError("dense delta must be square")
+            st.dtype = _dtype_code(ddt)
+        if len(devs) != 1:
+            raise ValueError("all inputs must live in the same memory kind")
+        device = devs.pop()
+        st.mem = DPT_MEM_DEVICE if device else DPT_MEM_HOST
+        if int(theta.shape[0]) != st.n:
+            raise ValueError("theta length does not match delta")
+        if stream is None and device:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        st.stream = stream
+        self.struct = st
+        self.keep = keep
+        self.device = device
+
+
+def options(tol=1e-6, max_iter=200, precision=DPT_FP32, fp64_final_tol=0.0, stall_ratio=0.5,
+            stall_patience=2, check_every=1, blowup=1e6):
+    o = Options()
+    load_library().dpt_options_default(ctypes.byref(o))
+    o.tol, o.max_iter, o.precision = tol, max_iter, precision
+    o.fp64_final_tol, o.stall_ratio, o.stall_patience = fp64_final_tol, stall_ratio, stall_patience
+    o.check_every, o.blowup = check_every, blowup
+    return o
+
+
+def dpt_options_default():
+    o = Options()
+    load_library().dpt_options_default(ctypes.byref(o))
+    return o
+
+
+def dpt_validate(problem: ProblemSpec, opts: Options = None) -> int:
+    return load_library().dpt_validate(ctypes.byref(problem.struct),
+                                       ctypes.byref(opts) if opts is not None else None)
+
+
+class Handle:
+    def __init__(self, ptr, problem):
+        self.ptr = ptr
+        self.problem = problem      # keeps borrowed device inputs alive
+        self.n = problem.struct.n
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.dpt_destroy(self.ptr)
+            self.ptr = None
+
+
+def dpt_init(problem: ProblemSpec, opts: Options = None, z0=None) -> Handle:
+    h = ctypes.c_void_p()
+    zp = None
+    keep = None
+    if z0 is not None:
+        zp, _, _, keep = _info(z0)
+    rc = load_library().dpt_init(ctypes.byref(h), ctypes.byref(problem.struct),
+                                 ctypes.byref(opts) if opts is not None else None, zp)
+    del keep
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_init")
+    return Handle(h.value, problem)
+
+
+def dpt_step(h: Handle, nsteps: int) -> float:
+    d = ctypes.c_double()
+    rc = load_library().dpt_step(h.ptr, int(nsteps), ctypes.byref(d))
+    if rc < 0:
+        raise DptError(rc, "dpt_step")
+    return d.value
+
+
+def dpt_solve(h: Handle, history_cap: int = 256) -> dict:
+    hist = np.full(max(history_cap, 1), np.nan)
+    r = Result()
+    r.delta_history = hist.ctypes.data if history_cap > 0 else None
+    r.history_cap = history_cap
+    rc = load_library().dpt_solve(h.ptr, ctypes.byref(r))
+    if rc < 0:
+        raise DptError(rc, "dpt_solve")
+    return {"status": r.status, "iters": r.iters, "iters_bf16": r.iters_bf16,
+            "iters_fp32": r.iters_fp32, "iters_fp64": r.iters_fp64,
+            "last_delta": r.last_delta, "history": hist[:min(r.iters, history_cap)].copy()}
+
+
+def dpt_eigenvalues(h: Handle, out=None):
+    """Host numpy array by default; pass a float64 device tensor of length n to fill it."""
+    if out is None:
+        out = np.empty(h.n, np.float64)
+    p, dt, dev, keep = _info(out)
+    if dt not in ("float64", "torch.float64"):
+        raise ValueError("eigenvalues are float64")
+    rc = load_library().dpt_eigenvalues(h.ptr, p, DPT_MEM_DEVICE if dev else DPT_MEM_HOST)
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_eigenvalues")
+    return out
+
+
+def dpt_eigenvectors(h: Handle, out=None, dtype=np.float64):
+    """Z[k, m] = component m of eigenvector k (row k, Z[k, k] = 1)."""
+    if out is None:
+        out = np.empty((h.n, h.n), dtype=dtype)
+    p, dt, dev, keep = _info(out)
+    rc = load_library().dpt_eigenvectors(h.ptr, p, _dtype_code(dt),
+                                         DPT_MEM_DEVICE if dev else DPT_MEM_HOST)
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_eigenvectors")
+    return out
+
+
+def dpt_residuals(h: Handle, rows):
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    res = np.empty(rows.shape[0], np.float64)
+    rc = load_library().dpt_residuals(h.ptr, rows.shape[0], rows.ctypes.data, res.ctypes.data)
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_residuals")
+    return res
+
+
+def dpt_dominant(problem: ProblemSpec, opts: Options = None, index: int = -1, out=None,
+                 history_cap: int = 64):
+    """Returns (eigval, eigvec, result dict).  eigvec has the problem's dtype and memory kind."""
+    st = problem.struct
+    if out is None:
+        if problem.device:
+            import torch
+            out = torch.empty(st.n, dtype=torch.float64 if st.dtype == DPT_DTYPE_F64 else torch.float32,
+                              device="cuda")
+        else:
+            out = np.empty(st.n, np.float64 if st.dtype == DPT_DTYPE_F64 else np.float32)
+    p, _, _, keep = _info(out)
+    ev = ctypes.c_double()
+    hist = np.full(max(history_cap, 1), np.nan)
+    r = Result()
+    r.delta_history = hist.ctypes.data
+    r.history_cap = history_cap
+    rc = load_library().dpt_dominant(ctypes.byref(st), ctypes.byref(opts) if opts is not None else None,
+                                     int(index), ctypes.byref(ev), p, ctypes.byref(r))
+    if rc < 0:
+        raise DptError(rc, "dpt_dominant")
+    return ev.value, out, {"status": r.status, "iters": r.iters, "last_delta": r.last_delta,
+                           "history": hist[:min(r.iters, history_cap)].copy()}
+
+
+def dpt_destroy(h: Handle) -> None:
+    if h.ptr:
+        load_library().dpt_destroy(h.ptr)
+        h.ptr = None
