@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the D-PT hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): dense symmetric
+N = 16384, theta_i = i/4, Delta = (R + R^T)/2 with R off-diagonal iid
+N(0, (0.25/sqrt(N))^2), zero diagonal, lambda = 1, FP32 input values.  One
+"step" is one whole solve through the C ABI: dpt_init on device-resident
+inputs (staging, BF16 copy, symmetry test), dpt_solve in the BF16 -> FP32 form
+to tol 1e-6 on max|Z_k - Z_{k-1}|, and the eigenvalue readout.  The plain FP32
+solve of the same problem is timed beside it.
+
+Printed: one JSON line with value = D-PT iterations per second of the BF16 ->
+FP32 solve, the roofline of the dominant kernel (the fused BF16 MFMA step, HIP
+events on its stream), and the FP64 CPU oracle timed on a bounded row sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DPT iter/s + TFLOP/s at N=16384 (bf16→fp32 vs fp32); solves/s, p50/p99 lat"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_bf16_n16384.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2002_12872_amd", "csrc", "kernels_dense.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--fp32-solves", type=int, default=2)
+    ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle work")
+    return ap.parse_args()
+
+
+def kernel_hash():
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_traffic(n):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel source; None otherwise."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_hash() or int(vals.get("n", -1)) != n:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def solve_once(dpt, spec, opts, n, profile):
+    import torch
+    h = dpt.dpt_init(spec, opts)
+    if profile:
+        dpt.dpt_profile_enable(h, True)
+    res = dpt.dpt_solve(h, history_cap=64)
+    e = torch.empty(n, dtype=torch.float64, device="cuda")
+    dpt.dpt_eigenvalues(h, e)
+    return h, res, e
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the D-PT hot path on a single "
+              "MI355X (no multi-GPU path); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2002_12872_amd import dpt
+
+    n = args.n
+    dev = torch.device("cuda:0")
+    theta, delta = workloads.dense_sym_large(0, n=n)
+    th_d = torch.from_numpy(theta).to(dev)
+    de_d = torch.from_numpy(delta).to(dev)
+    torch.cuda.synchronize()
+    spec = dpt.ProblemSpec(th_d, de_d, 1.0)
+    opt_mixed = dpt.options(tol=args.tol, max_iter=100, precision=dpt.DPT_BF16_FP32)
+    opt_fp32 = dpt.options(tol=args.tol, max_iter=100, precision=dpt.DPT_FP32)
+
+    # ---- BF16 -> FP32 solves
+    for _ in range(args.warmup):
+        h, _, _ = solve_once(dpt, spec, opt_mixed, n, False)
+        dpt.dpt_destroy(h)
+    torch.cuda.synchronize()
+    handles, results = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h, res, e = solve_once(dpt, spec, opt_mixed, n, True)
+        handles.append(h)
+        results.append(res)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print("# mixed solves: %d in %.3f s, iterations %s" % (args.steps, elapsed,
+          [(r["iters_bf16"], r["iters_fp32"]) for r in results]), file=sys.stderr, flush=True)
+    prof = {}
+    for h in handles:
+        for k, (ms, cnt) in dpt.dpt_profile_read(h).items():
+            a = prof.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += cnt
+    e_gpu = e.cpu().numpy()
+    iters_total = sum(r["iters"] for r in results)
+    gemm_steps = sum(r["iters"] - 1 for r in results)   # the first iterate needs no product
+    flop = 2.0 * n ** 3
+    value = iters_total / elapsed
+    ms_per_solve = 1e3 * elapsed / args.steps
+
+    # roofline of the dominant kernel (fused BF16 step)
+    g_ms, g_cnt = prof.get("gemm_bf16", (float("nan"), 0))
+    avg_ms = g_ms / max(g_cnt, 1)
+    achieved = flop / (avg_ms * 1e-3) / 1e12
+    traffic = read_traffic(n)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
+                "traffic": traffic, "kernel": "k_step_gemm<PolBF16,256,128,32,2,2>",
+                "avg_launch_ms": round(avg_ms, 4), "launches": g_cnt,
+                "algorithmic_flop_per_launch": flop}
+
+    # ---- plain FP32 solves (comparison at the same tolerance)
+    fp32 = None
+    if args.fp32_solves > 0:
+        h, _, _ = solve_once(dpt, spec, opt_fp32, n, False)
+        dpt.dpt_destroy(h)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f_res, f_handles = [], []
+        for _ in range(args.fp32_solves):
+            h, res, _ = solve_once(dpt, spec, opt_fp32, n, True)
+            f_res.append(res)
+            f_handles.append(h)
+        torch.cuda.synchronize()
+        f_el = time.perf_counter() - t1
+        f_prof = [0.0, 0]
+        for h in f_handles:
+            ms, cnt = dpt.dpt_profile_read(h).get("gemm_fp32", (0.0, 0))
+            f_prof[0] += ms
+            f_prof[1] += cnt
+            dpt.dpt_destroy(h)
+        f_avg = f_prof[0] / max(f_prof[1], 1)
+        fp32 = {"iter_s": round(sum(r["iters"] for r in f_res) / f_el, 3),
+                "ms_per_solve": round(1e3 * f_el / args.fp32_solves, 2),
+                "iters": f_res[0]["iters"],
+                "gemm_fp32_avg_ms": round(f_avg, 3),
+                "gemm_fp32_tflops": round(flop / (f_avg * 1e-3) / 1e12, 2)}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_solve, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16->fp32", "data": "synthetic",
+        "config": {"workload": "dense symmetric N=%d, theta_i=i/4, Delta=(R+R^T)/2, "
+                               "R~N(0,(0.25/sqrt N)^2) zero diagonal, lambda=1; "
+                               "BF16->FP32 solve to max|dZ|<%g" % (n, args.tol),
+                   "n": n, "tol": args.tol, "step": "one full solve (init+solve+readout)"},
+        "iters_per_solve": [r["iters"] for r in results],
+        "iters_bf16_fp32": [results[0]["iters_bf16"], results[0]["iters_fp32"]],
+        "solve_tflops": round(gemm_steps * flop / elapsed / 1e12, 2),
+        "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
+        "roofline": roofline,
+        "fp32": fp32,
+        "speedup_vs_fp32": (round(fp32["ms_per_solve"] / ms_per_solve, 3) if fp32 else None),
+    }
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of eigenvector rows
+    if not args.skip_cpu:
+        import oracle
+        k = results[0]["iters"]
+        d64 = delta.astype(np.float64)
+        threads = oracle.max_threads()
+        probe_rows = workloads.sample_rows(n, max(threads, 2))
+        t = time.perf_counter()
+        oracle.iterate(theta, d64, 1.0, rows=probe_rows, max_iter=1, fixed_steps=True)
+        per_row_iter = (time.perf_counter() - t) / len(probe_rows)
+        rows_n = int(max(threads, min(256, args.cpu_seconds / max(per_row_iter * k, 1e-9))))
+        rows = workloads.sample_rows(n, rows_n)
+        t = time.perf_counter()
+        ref = oracle.iterate(theta, d64, 1.0, rows=rows, max_iter=k, fixed_steps=True)
+        cpu_t = time.perf_counter() - t
+        cpu_value = k * (len(rows) / n) / cpu_t
+        e_rel = float(np.max(np.abs(e_gpu[rows] - ref["e"]) /
+                             np.maximum(np.abs(ref["e"]), 1e-12 * np.abs(theta).max())))
+        out["cpu_baseline"] = {"value": round(cpu_value, 6), "unit": "iter/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "%d of %d eigenvector rows x %d iterations of the FP64 "
+                                         "oracle (rows evolve independently), %.1f s, scaled "
+                                         "by rows/N" % (len(rows), n, k, cpu_t)}
+        out["error_vs_fp64_oracle"] = {"max_rel_eigenvalue": e_rel, "rows": len(rows),
+                                       "oracle_iterations": k}
+    for h in handles:
+        dpt.dpt_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

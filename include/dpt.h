@@ -171,6 +171,29 @@ int dpt_residuals(dpt_handle h, int64_t nrows, const int64_t *rows, double *res)
 int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval,
                  void *eigvec, dpt_result *r);
 
+/* ---- kernel timing --------------------------------------------------------
+ * Device time of the library's kernels, measured with HIP events recorded on
+ * the handle's stream around each launch (accumulated per kernel class).
+ * Timing adds two event records per launch; it is off by default. */
+#define DPT_PROF_FIRST 0      /* first iterate F(I), no product                  */
+#define DPT_PROF_PREPASS 1    /* diagonal pre-pass d_n = (Delta z_n)[n]           */
+#define DPT_PROF_GEMM_BF16 2  /* fused BF16 MFMA product + update                */
+#define DPT_PROF_GEMM_FP32 3  /* fused FP32 MFMA product + update                */
+#define DPT_PROF_GEMM_FP64 4  /* fused FP64 MFMA product + update                */
+#define DPT_PROF_SPMM 5       /* fused CSR product + update                       */
+#define DPT_PROF_KINDS 8
+
+typedef struct dpt_profile {
+    double ms[DPT_PROF_KINDS];        /* summed device milliseconds per class      */
+    int64_t launches[DPT_PROF_KINDS]; /* number of timed launches per class        */
+} dpt_profile;
+
+/* on != 0 starts timing (and clears the totals); on == 0 stops it. */
+int dpt_profile_enable(dpt_handle h, int on);
+
+/* Synchronise the stream and copy the totals into *out. */
+int dpt_profile_read(dpt_handle h, dpt_profile *out);
+
 /* Release the handle (NULL is accepted). */
 void dpt_destroy(dpt_handle h);
 

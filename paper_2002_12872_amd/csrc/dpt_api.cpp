@@ -93,12 +93,96 @@ int check_device() {
     return DPT_OK;
 }
 
+// True when p is device (or managed) memory that kernels may dereference.
+bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // clear the error so later launch checks do not see it
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Inputs declared DPT_MEM_DEVICE must really be device memory (a host pointer
+// would be dereferenced by a kernel).
+bool device_inputs_ok(const dpt_problem *p, const void *z0) {
+    if (p->mem != DPT_MEM_DEVICE) return true;
+    if (!is_device_ptr(p->theta) || !is_device_ptr(p->delta)) return false;
+    if (p->format == DPT_CSR && (!is_device_ptr(p->indptr) || !is_device_ptr(p->indices))) return false;
+    if (z0 && !is_device_ptr(z0)) return false;
+    return true;
+}
+
 template <typename T>
 hipError_t dalloc(T **p, size_t count) {
     *p = nullptr;
     if (count == 0) return hipSuccess;
     return hipMalloc((void **)p, count * sizeof(T));
 }
+
+// HIP-event timing of kernel launches (per DPT_PROF_* class).
+struct Profiler : ProfHook {
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    bool on = false;
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[DPT_PROF_KINDS] = {};
+    int64_t launches[DPT_PROF_KINDS] = {};
+
+    hipEvent_t take() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void begin(int kind, hipStream_t s) override {
+        if (!on) return;
+        Rec r{kind, take(), take()};
+        if (!r.a || !r.b) return;
+        (void)hipEventRecord(r.a, s);
+        pending.push_back(r);
+    }
+    void end(hipStream_t s) override {
+        if (!on || pending.empty()) return;
+        (void)hipEventRecord(pending.back().b, s);
+        if (pending.size() > 8192) collect();
+    }
+    void collect() {
+        for (const Rec &r : pending) {
+            float t = 0.f;
+            if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                ms[r.kind] += t;
+                launches[r.kind] += 1;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    void reset() {
+        collect();
+        for (int i = 0; i < DPT_PROF_KINDS; ++i) {
+            ms[i] = 0.0;
+            launches[i] = 0;
+        }
+    }
+    ~Profiler() override {
+        for (const Rec &r : pending) {
+            (void)hipEventSynchronize(r.b);
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
 
 }  // namespace
 
@@ -132,6 +216,7 @@ struct dpt_ctx {
     int64_t k = 0;
 
     SparseState *sp = nullptr;
+    Profiler prof;
 
     ~dpt_ctx() {
         if (sp) sparse_destroy(sp);
@@ -214,6 +299,18 @@ int ensure_f64(dpt_ctx *c) {
     return DPT_OK;
 }
 
+// Scratch device buffer released (after its stream drains) on scope exit.
+struct DeviceTemp {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    ~DeviceTemp() {
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(p);
+        }
+    }
+};
+
 StepArgs step_args(dpt_ctx *c, unsigned long long *slot) {
     StepArgs a;
     a.n = c->n;
@@ -243,21 +340,37 @@ int dense_step(dpt_ctx *c) {
     const StepArgs a = step_args(c, st);
     const int nx = c->cur ^ 1;
     hipStream_t s = c->stream;
+    Profiler &pf = c->prof;
+    hipError_t e = hipSuccess;
     if (c->at_identity) {
         DPT_TRY(launch_zero_u64(st, 2, s));
+        pf.begin(DPT_PROF_FIRST, s);
         if (c->phase == PH_FP64)
-            DPT_TRY(launch_first_iterate_f64(a, c->dT64, c->W64[nx], s));
+            e = launch_first_iterate_f64(a, c->dT64, c->W64[nx], s);
         else
-            DPT_TRY(launch_first_iterate_f32(a, c->dT32, c->W32[nx], c->phase == PH_BF16 ? c->Wb[nx] : nullptr, s));
-    } else if (c->phase == PH_FP64) {
-        DPT_TRY(launch_prepass_f64_f64(c->W64[c->cur], c->d64, a, c->dvec, nullptr, st, s));
-        DPT_TRY(launch_step_f64(a, c->W64[c->cur], c->d64, c->dT64, c->W64[nx], s));
-    } else if (c->phase == PH_FP32) {
-        DPT_TRY(launch_prepass_f32_f32(c->W32[c->cur], c->d32, a, c->dvec, nullptr, st, s));
-        DPT_TRY(launch_step_f32(a, c->W32[c->cur], c->d32, c->dT32, c->W32[nx], nullptr, s));
+            e = launch_first_iterate_f32(a, c->dT32, c->W32[nx], c->phase == PH_BF16 ? c->Wb[nx] : nullptr, s);
+        pf.end(s);
+        DPT_TRY(e);
     } else {
-        DPT_TRY(launch_prepass_f32_f32(c->W32[c->cur], c->d32, a, c->dvec, nullptr, st, s));
-        DPT_TRY(launch_step_bf16(a, c->Wb[c->cur], c->db16, c->dT32, c->W32[c->cur], c->W32[nx], c->Wb[nx], s));
+        pf.begin(DPT_PROF_PREPASS, s);
+        if (c->phase == PH_FP64)
+            e = launch_prepass_f64_f64(c->W64[c->cur], c->d64, a, c->dvec, nullptr, st, s);
+        else
+            e = launch_prepass_f32_f32(c->W32[c->cur], c->d32, a, c->dvec, nullptr, st, s);
+        pf.end(s);
+        DPT_TRY(e);
+        if (c->phase == PH_FP64) {
+            pf.begin(DPT_PROF_GEMM_FP64, s);
+            e = launch_step_f64(a, c->W64[c->cur], c->d64, c->dT64, c->W64[nx], s);
+        } else if (c->phase == PH_FP32) {
+            pf.begin(DPT_PROF_GEMM_FP32, s);
+            e = launch_step_f32(a, c->W32[c->cur], c->d32, c->dT32, c->W32[nx], nullptr, s);
+        } else {
+            pf.begin(DPT_PROF_GEMM_BF16, s);
+            e = launch_step_bf16(a, c->Wb[c->cur], c->db16, c->dT32, c->W32[c->cur], c->W32[nx], c->Wb[nx], s);
+        }
+        pf.end(s);
+        DPT_TRY(e);
     }
     c->cur = nx;
     c->at_identity = false;
@@ -265,7 +378,9 @@ int dense_step(dpt_ctx *c) {
     return DPT_OK;
 }
 
-int do_step(dpt_ctx *c) { return c->sp ? sparse_step(c->sp, c->lambda, c->theta, c->stats, &c->k, c->stream) : dense_step(c); }
+int do_step(dpt_ctx *c) {
+    return c->sp ? sparse_step(c->sp, c->lambda, c->theta, c->stats, &c->k, c->stream, &c->prof) : dense_step(c);
+}
 
 // Copy the stats of steps [k0, k1) to the pinned mirror and synchronise.
 int fetch_stats(dpt_ctx *c, int64_t k0, int64_t k1) {
@@ -324,6 +439,15 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
             DPT_TRY(launch_cvt_f32_to_f64(c->d64, c->d32, (int64_t)nn, s));
         }
     }
+    // A host-memory start is first copied to the device.
+    const size_t z0_bytes = (size_t)(c->n * c->n) * (p->dtype == DPT_DTYPE_F64 ? 8 : 4);
+    DeviceTemp z0_dev;
+    z0_dev.s = s;
+    if (z0 && p->mem == DPT_MEM_HOST) {
+        DPT_TRY(hipMalloc(&z0_dev.p, z0_bytes));
+        DPT_TRY(hipMemcpyAsync(z0_dev.p, z0, z0_bytes, hipMemcpyHostToDevice, s));
+        z0 = z0_dev.p;
+    }
     if (prec == DPT_FP64) {
         int rc = ensure_f64(c);
         if (rc != DPT_OK) return rc;
@@ -360,6 +484,7 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
             c->at_identity = false;
         }
     }
+    if (z0_dev.p) DPT_TRY(hipStreamSynchronize(s));  // the temporary is freed on return
     return DPT_OK;
 }
 
@@ -417,6 +542,7 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
     if (p->format == DPT_CSR && z0) return DPT_EINVAL;  // warm start: dense problems only
     rc = check_device();
     if (rc != DPT_OK) return rc;
+    if (!device_inputs_ok(p, z0)) return DPT_EINVAL;
     dpt_ctx *c = new (std::nothrow) dpt_ctx();
     if (!c) return DPT_ENOMEM;
     auto fail = [&](int code) {
@@ -583,6 +709,7 @@ int dpt_solve(dpt_handle h, dpt_result *r) {
 
 int dpt_eigenvalues(dpt_handle h, double *E, int mem) {
     if (!h || !E || (mem != DPT_MEM_HOST && mem != DPT_MEM_DEVICE)) return DPT_EINVAL;
+    if (mem == DPT_MEM_DEVICE && !is_device_ptr(E)) return DPT_EINVAL;
     int rc = compute_eigenvalues(h);
     if (rc != DPT_OK) return rc;
     DPT_TRY(hipMemcpyAsync(E, h->evec, sizeof(double) * (size_t)h->n,
@@ -594,6 +721,7 @@ int dpt_eigenvalues(dpt_handle h, double *E, int mem) {
 int dpt_eigenvectors(dpt_handle h, void *Z, int dtype, int mem) {
     if (!h || !Z || (mem != DPT_MEM_HOST && mem != DPT_MEM_DEVICE)) return DPT_EINVAL;
     if (dtype != DPT_DTYPE_F32 && dtype != DPT_DTYPE_F64) return DPT_EINVAL;
+    if (mem == DPT_MEM_DEVICE && !is_device_ptr(Z)) return DPT_EINVAL;
     const size_t bytes = (size_t)(h->n * h->n) * (dtype == DPT_DTYPE_F64 ? 8 : 4);
     void *dst = Z;
     void *tmp = nullptr;
@@ -660,6 +788,7 @@ int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, doub
     if (!eigval || !eigvec || index >= p->n) return DPT_EINVAL;
     rc = check_device();
     if (rc != DPT_OK) return rc;
+    if (!device_inputs_ok(p, nullptr) || (p->mem == DPT_MEM_DEVICE && !is_device_ptr(eigvec))) return DPT_EINVAL;
     dpt_options opt;
     if (o) {
         opt = *o;
@@ -676,6 +805,24 @@ int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, doub
     }
     if (index < 0) index = (int64_t)(std::max_element(th.begin(), th.end()) - th.begin());
     return dominant_solve(p, &opt, th.data(), index, eigval, eigvec, r);
+}
+
+int dpt_profile_enable(dpt_handle h, int on) {
+    if (!h) return DPT_EINVAL;
+    h->prof.reset();
+    h->prof.on = on != 0;
+    return DPT_OK;
+}
+
+int dpt_profile_read(dpt_handle h, dpt_profile *out) {
+    if (!h || !out) return DPT_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return DPT_EDEVICE;
+    h->prof.collect();
+    for (int i = 0; i < DPT_PROF_KINDS; ++i) {
+        out->ms[i] = h->prof.ms[i];
+        out->launches[i] = h->prof.launches[i];
+    }
+    return DPT_OK;
 }
 
 void dpt_destroy(dpt_handle h) {

@@ -21,6 +21,14 @@ constexpr int kStatRing = 4096;
 
 enum Phase { PH_BF16 = 0, PH_FP32 = 1, PH_FP64 = 2 };
 
+// Optional timing hook: begin/end bracket one kernel launch of a class
+// (DPT_PROF_* in dpt.h) on a stream.
+struct ProfHook {
+    virtual void begin(int kind, hipStream_t s) = 0;
+    virtual void end(hipStream_t s) = 0;
+    virtual ~ProfHook() {}
+};
+
 struct StepArgs {
     int64_t n;                 // valid order N
     int64_t ld;                // padded leading dimension

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "dpt.h"
+#include "dpt_internal.h"
 
 namespace dpt {
 
@@ -22,7 +23,7 @@ void sparse_destroy(SparseState *sp);
 // One application of eq. (dyn) with the CSR product; stats go to ring slot *k
 // of `stats` (2 u64 per slot), then *k is incremented.
 int sparse_step(SparseState *sp, double lambda, const double *theta, unsigned long long *stats, int64_t *k,
-                hipStream_t s);
+                hipStream_t s, ProfHook *prof);
 
 // E_n = theta_n + lambda (Delta z_n)[n] of the current iterate, into evec (device).
 hipError_t sparse_eigenvalues(SparseState *sp, double lambda, const double *theta, double *evec, hipStream_t s);

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_prepass(const TW *__restrict__ W, const
 // row (l % MI) of its operand, from K-group (l / MI).  The accumulator layouts
 // are those of the CDNA3/CDNA4 matrix instructions:
 //   32x32 (16 values/lane): element r of lane l is C[(r&3) + 4*(l>>5) + 8*(r>>2)][l & 31]
-//   16x16 ( 4 values/lane): element r of lane l is C[r + 4*(l>>4)][l & 15]
+//   16x16 f64 (4 values/lane): element r of lane l is C[4*r + (l>>4)][l & 15]
 // Any permutation of K that is applied identically to both operands leaves the
 // product unchanged; each lane's K-group therefore walks a contiguous span of
 // the LDS row, which makes the LDS reads 16-byte vectors.
@@ -241,7 +241,8 @@ struct PolF64 {
         const unsigned long long lo = c[(s & 1) * 2], hi = c[(s & 1) * 2 + 1];
         return __longlong_as_double((long long)(lo | (hi << 32)));
     }
-    static __device__ __forceinline__ int acc_row(int r, int lane) { return r + ((lane >> 4) << 2); }
+    // f64 16x16x4: one row per register group, i.e. register r of lane l is row 4r + (l >> 4)
+    static __device__ __forceinline__ int acc_row(int r, int lane) { return (r << 2) + (lane >> 4); }
     static __device__ __forceinline__ int acc_col(int lane) { return lane & 15; }
 };
 

@@ -473,33 +473,46 @@ hipError_t sparse_create(SparseState **out, const dpt_problem *p, bool fp64, int
 }
 
 namespace {
+struct NoProf : ProfHook {
+    void begin(int, hipStream_t) override {}
+    void end(hipStream_t) override {}
+};
+
 template <typename T>
 hipError_t sparse_step_t(SparseState *sp, const T *val, T *const WT[2], double lambda, const double *theta,
-                         unsigned long long *st, hipStream_t s) {
+                         unsigned long long *st, hipStream_t s, ProfHook *prof) {
     const int nx = sp->cur ^ 1;
     const int64_t n = sp->n, ld = sp->ld;
     if (sp->at_identity) {
         hipLaunchKernelGGL((k_zero<unsigned long long>), dim3(1), dim3(64), 0, s, st, (int64_t)2);
+        prof->begin(DPT_PROF_FIRST, s);
         hipLaunchKernelGGL((k_sp_first_iterate<T>), dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, sp->rowptr,
                            sp->col, val, n, ld, lambda, theta, WT[nx], st);
+        prof->end(s);
         return hipGetLastError();
     }
+    prof->begin(DPT_PROF_PREPASS, s);
     hipLaunchKernelGGL((k_sp_prepass<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, sp->rowptr, sp->col, val,
                        sp->diag, n, ld, (const T *)WT[sp->cur], lambda, theta, sp->dvec, (double *)nullptr, st);
+    prof->end(s);
     const int64_t blocks = (ld / kPanel) * (ld / 4);
+    prof->begin(DPT_PROF_SPMM, s);
     hipLaunchKernelGGL((k_sp_spmm<T>), dim3((unsigned int)blocks), dim3(256), 0, s, sp->rowptr, sp->col, val, n, ld,
                        lambda, theta, (const double *)sp->dvec, (const T *)WT[sp->cur], WT[nx], st);
+    prof->end(s);
     return hipGetLastError();
 }
 }  // namespace
 
 int sparse_step(SparseState *sp, double lambda, const double *theta, unsigned long long *stats, int64_t *k,
-                hipStream_t s) {
+                hipStream_t s, ProfHook *prof) {
     unsigned long long *st = stats + 2 * (int)(*k % kStatRing);
     const int nx = sp->cur ^ 1;
     const bool first = sp->at_identity;
-    hipError_t e = sp->fp64 ? sparse_step_t<double>(sp, sp->val64, sp->WT64, lambda, theta, st, s)
-                            : sparse_step_t<float>(sp, sp->val32, sp->WT32, lambda, theta, st, s);
+    NoProf none;
+    if (!prof) prof = &none;
+    hipError_t e = sp->fp64 ? sparse_step_t<double>(sp, sp->val64, sp->WT64, lambda, theta, st, s, prof)
+                            : sparse_step_t<float>(sp, sp->val32, sp->WT32, lambda, theta, st, s, prof);
     if (e != hipSuccess) return err_code(e);
     (void)first;  // the first iterate writes only the pattern of Delta into a zeroed buffer
     sp->cur = nx;

@@ -75,6 +75,14 @@ class Result(ctypes.Structure):
     ]
 
 
+DPT_PROF_KINDS = 8
+PROF_NAMES = ["first_iterate", "prepass", "gemm_bf16", "gemm_fp32", "gemm_fp64", "spmm", "k6", "k7"]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * DPT_PROF_KINDS), ("launches", ctypes.c_int64 * DPT_PROF_KINDS)]
+
+
 _FUNCS = {
     "dpt_options_default": (None, [ctypes.POINTER(Options)]),
     "dpt_validate": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options)]),
@@ -88,6 +96,8 @@ _FUNCS = {
     "dpt_dominant": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
                                     ctypes.POINTER(Result)]),
+    "dpt_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "dpt_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Profile)]),
     "dpt_destroy": (None, [ctypes.c_void_p]),
     "dpt_status_str": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -325,6 +335,22 @@ def dpt_dominant(problem: ProblemSpec, opts: Options = None, index: int = -1, ou
         raise DptError(rc, "dpt_dominant")
     return ev.value, out, {"status": r.status, "iters": r.iters, "last_delta": r.last_delta,
                            "history": hist[:min(r.iters, history_cap)].copy()}
+
+
+def dpt_profile_enable(h: Handle, on: bool = True) -> None:
+    rc = load_library().dpt_profile_enable(h.ptr, int(bool(on)))
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_profile_enable")
+
+
+def dpt_profile_read(h: Handle) -> dict:
+    """{kernel class: (total device ms, launches)} from HIP events on the handle's stream."""
+    p = Profile()
+    rc = load_library().dpt_profile_read(h.ptr, ctypes.byref(p))
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_profile_read")
+    return {PROF_NAMES[i]: (p.ms[i], int(p.launches[i])) for i in range(DPT_PROF_KINDS)
+            if p.launches[i] > 0}
 
 
 def dpt_destroy(h: Handle) -> None:

@@ -29,7 +29,9 @@ def one_step_bound(theta, delta, lam, z, u_prod, k_eff, rows=None):
     The product W Delta' (W = Z - I) is formed with per-term relative error
     u_prod (operand rounding) and an accumulation error of k_eff * 2^-24 per
     magnitude sum; the identity part Delta' is exact; the update multiplies by
-    |lambda gap|.  Rows of z correspond to ``rows`` (default all).
+    |lambda gap|.  Rows of z correspond to ``rows`` (default all).  The FP32
+    matrix-core accumulation over K terms behaves like a drift of order
+    sqrt(K) ulps of the magnitude sum, hence callers pass k_eff = 8 + sqrt(K).
     """
     n = len(theta)
     rows = np.arange(n) if rows is None else np.asarray(rows)

@@ -104,7 +104,7 @@ def test_fp32_step_within_rounding_bound(n, sym):
     for k in (0, 2):
         zk, zk1, _ = _state_after(theta, delta32, 1.0, dpt.DPT_FP32, k)
         ref = oracle.iterate(theta, d64, 1.0, rows=rows, z0=zk[rows], max_iter=1, fixed_steps=True)
-        bound = one_step_bound(theta, d64, 1.0, zk[rows], 2.0 ** -24, 8, rows=rows)
+        bound = one_step_bound(theta, d64, 1.0, zk[rows], 2.0 ** -24, 8 + math.sqrt(n), rows=rows)
         err = np.abs(zk1[rows] - ref["z"])
         assert np.all(err <= bound), (k, float(np.max(err / bound)))
 
@@ -119,7 +119,7 @@ def test_bf16_step_within_rounding_bound(n, sym):
     for k in (1, 2):
         zk, zk1, _ = _state_after(theta, delta32, 1.0, dpt.DPT_BF16_FP32, k)
         ref = oracle.iterate(theta, d64, 1.0, rows=rows, z0=zk[rows], max_iter=1, fixed_steps=True)
-        bound = one_step_bound(theta, d64, 1.0, zk[rows], 2.0 ** -8, 8, rows=rows)
+        bound = one_step_bound(theta, d64, 1.0, zk[rows], 2.0 ** -8, 8 + math.sqrt(n), rows=rows)
         err = np.abs(zk1[rows] - ref["z"])
         assert np.all(err <= bound), (k, float(np.max(err / bound)))
 
@@ -140,7 +140,7 @@ def test_bf16_step_equals_rounded_operand_product(n):
     g = gap_matrix(theta)
     expect = 0.9 * g * (c - dvec[:, None] * w)
     mag = np.abs(wb) @ np.abs(db).T + np.abs(c) + np.abs(dvec)[:, None] * np.abs(w)
-    tol = np.abs(0.9 * g) * 8 * 2.0 ** -24 * mag + 4 * 2.0 ** -24 * np.abs(expect) + 1e-300
+    tol = np.abs(0.9 * g) * (8 + math.sqrt(n)) * 2.0 ** -24 * mag + 4 * 2.0 ** -24 * np.abs(expect) + 1e-300
     got = zk1 - np.eye(n)
     assert np.all(np.abs(got - expect) <= tol), float(np.max(np.abs(got - expect) / tol))
 
