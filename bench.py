@@ -42,7 +42,42 @@ def parse():
     ap.add_argument("--fp32-solves", type=int, default=2)
     ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle work")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="profiling mode: init once, run --steps BF16 steps (after --warmup), no solve")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="profiling mode: plain device-to-device copy of MIB MiB, --steps times")
     return ap.parse_args()
+
+
+def kernel_only(args):
+    """BF16 fused steps at size n only (for counter collection with rocprofv3)."""
+    import torch
+
+    import workloads
+    from paper_2002_12872_amd import dpt
+    theta, delta = workloads.dense_sym_large(0, n=args.n)
+    spec = dpt.ProblemSpec(torch.from_numpy(theta).cuda(), torch.from_numpy(delta).cuda(), 1.0)
+    h = dpt.dpt_init(spec, dpt.options(precision=dpt.DPT_BF16_FP32))
+    dpt.dpt_step(h, 1 + args.warmup)            # first iterate (no product) + warm-up steps
+    dpt.dpt_profile_enable(h, True)
+    last = dpt.dpt_step(h, args.steps)
+    prof = dpt.dpt_profile_read(h)
+    print(json.dumps({"mode": "kernel-only", "n": args.n, "steps": args.steps, "last_delta": last,
+                      "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items()}}), flush=True)
+
+
+def copy_probe(args):
+    """Plain copy of a known number of bytes (calibrates HBM byte counters)."""
+    import torch
+    count = args.copy_probe * (1 << 20) // 4
+    src = torch.ones(count, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy-probe", "bytes_read": count * 4, "bytes_written": count * 4,
+                      "launches": args.steps}), flush=True)
 
 
 def kernel_hash():
@@ -85,6 +120,10 @@ def main():
         print("bench.py measures one GPU only: this build runs the D-PT hot path on a single "
               "MI355X (no multi-GPU path); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.kernel_only:
+        return kernel_only(args)
+    if args.copy_probe:
+        return copy_probe(args)
     import numpy as np
     import torch
 

@@ -122,22 +122,33 @@ __global__ __launch_bounds__(256) void k_symmetry_check(const T *__restrict__ sr
 
 // ----------------------------------------------------------- first iterate
 // F(I) = I + lambda gap * Delta'  (the Hadamard with the gap removes any diagonal).
+// One block per row n; 4 consecutive columns per thread (ld is a multiple of 64).
 template <typename T>
 __global__ __launch_bounds__(256) void k_first_iterate(StepArgs a, const T *__restrict__ dT, T *__restrict__ W,
                                                        __bf16 *__restrict__ Wb) {
-    const int64_t total = a.ld * a.ld;
+    const int64_t n = blockIdx.x;
+    const double th_n = a.theta[n];
+    const bool row_ok = n < a.n;
     double dmax = 0.0;
     bool bad = false;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t n = i / a.ld, m = i - n * a.ld;
-        T w = (T)0;
-        if (n < a.n && m < a.n && n != m) w = (T)(a.lambda * (double)dT[i] / (a.theta[n] - a.theta[m]));
-        W[i] = w;
-        if (Wb) Wb[i] = (__bf16)(float)w;
-        const double v = fabs((double)w);
-        dmax = fmax(dmax, v);
-        bad |= !(v <= DBL_MAX);
+    for (int64_t m0 = 4 * (int64_t)threadIdx.x; m0 < a.ld; m0 += 4 * 256) {
+        const int64_t idx = n * a.ld + m0;
+        T w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t m = m0 + q;
+            w[q] = (T)0;
+            if (row_ok && m < a.n && m != n) w[q] = (T)(a.lambda * (double)dT[idx + q] / (th_n - a.theta[m]));
+            const double v = fabs((double)w[q]);
+            dmax = fmax(dmax, v);
+            bad |= !(v <= DBL_MAX);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) W[idx + q] = w[q];
+        if (Wb) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Wb[idx + q] = (__bf16)(float)w[q];
+        }
     }
     publish_stats(a.stat, dmax, dmax, bad);
 }
@@ -551,13 +562,12 @@ hipError_t launch_symmetry_check_f64(const double *src, int64_t ld, unsigned int
 }
 
 hipError_t launch_first_iterate_f32(const StepArgs &a, const float *deltaT, float *W, __bf16 *Wb, hipStream_t s) {
-    hipLaunchKernelGGL((k_first_iterate<float>), dim3(grid_1d(a.ld * a.ld, 65536)), dim3(256), 0, s, a, deltaT, W,
-                       Wb);
+    hipLaunchKernelGGL((k_first_iterate<float>), dim3((unsigned int)a.ld), dim3(256), 0, s, a, deltaT, W, Wb);
     return hipGetLastError();
 }
 
 hipError_t launch_first_iterate_f64(const StepArgs &a, const double *deltaT, double *W, hipStream_t s) {
-    hipLaunchKernelGGL((k_first_iterate<double>), dim3(grid_1d(a.ld * a.ld, 65536)), dim3(256), 0, s, a, deltaT, W,
+    hipLaunchKernelGGL((k_first_iterate<double>), dim3((unsigned int)a.ld), dim3(256), 0, s, a, deltaT, W,
                        (__bf16 *)nullptr);
     return hipGetLastError();
 }

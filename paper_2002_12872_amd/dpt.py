@@ -111,6 +111,13 @@ def load_library(path: str = LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise ImportError("libdpt.so not found at %s; run paper_2002_12872_amd.build.build()" % path)
+        # torch ships its own HIP runtime with the same soname (libamdhip64.so.7).
+        # Loading torch first makes libdpt.so bind to that copy, so a process that
+        # uses both has exactly one HIP runtime (two copies cannot share the GPU).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(path)
         for name, (res, args) in _FUNCS.items():
             fn = getattr(lib, name)

@@ -1,0 +1,91 @@
+"""Parity at the measured configurations' full sizes, on sampled outputs.
+
+Eigenvector rows evolve independently (Sec. II.B), so 64 sampled rows of the
+FP64 oracle are exactly those rows of the full FP64 iteration; the GPU runs the
+whole problem on device-resident inputs, as the benchmark does.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from helpers import rel_eig_error
+
+pytestmark = pytest.mark.gpu
+
+dpt = pytest.importorskip("paper_2002_12872_amd.dpt")
+
+
+def device(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def rows_of_state(h, n, rows):
+    import torch
+    z = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    dpt.dpt_eigenvectors(h, z)
+    out = z[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    del z
+    return out
+
+
+def test_c4_dense_symmetric_16384_bf16_then_fp32():
+    n = 16384
+    theta, delta = workloads.dense_sym_large(0, n=n)
+    spec = dpt.ProblemSpec(device(theta), device(delta), 1.0)
+    h = dpt.dpt_init(spec, dpt.options(tol=1e-6, max_iter=100, precision=dpt.DPT_BF16_FP32))
+    res = dpt.dpt_solve(h)
+    assert res["status"] == dpt.DPT_OK and res["iters_bf16"] >= 2 and res["iters_fp32"] >= 1
+    e = dpt.dpt_eigenvalues(h)
+    rows = workloads.sample_rows(n, 64)
+    ref = oracle.iterate(theta, delta.astype(np.float64), 1.0, rows=rows, max_iter=40, tol=1e-13)
+    assert ref["status"] == oracle.OR_OK
+    assert rel_eig_error(e[rows], ref["e"], theta) <= 1e-5
+    z = rows_of_state(h, n, rows)
+    assert np.max(np.abs(z - ref["z"])) / np.max(np.abs(ref["z"] - np.eye(n)[rows])) <= 1e-5
+    r = dpt.dpt_residuals(h, rows)
+    norm_ub = np.abs(theta).max() + float(np.linalg.norm(delta.astype(np.float64)))
+    assert np.max(r / (norm_ub * np.linalg.norm(z, axis=1))) <= 1e-5
+    # trace of the converged eigenvalues: sum E = sum theta (zero diagonal)
+    e_all = dpt.dpt_eigenvalues(h)
+    assert abs(e_all.sum() - theta.sum()) <= 1e-5 * np.abs(theta).sum() / n
+
+
+def test_c2_dense_unsymmetric_4096_thirty_fp32_steps():
+    n = 4096
+    theta, delta = workloads.dense_unsym(0, n=n)
+    spec = dpt.ProblemSpec(device(theta), device(delta), 1.0)
+    h = dpt.dpt_init(spec, dpt.options(precision=dpt.DPT_FP32))
+    last = dpt.dpt_step(h, 30)
+    assert np.isfinite(last) and last < 1e-6
+    e = dpt.dpt_eigenvalues(h)
+    rows = workloads.sample_rows(n, 64)
+    ref = oracle.iterate(theta, delta.astype(np.float64), 1.0, rows=rows, max_iter=30, fixed_steps=True)
+    assert rel_eig_error(e[rows], ref["e"], theta) <= 1e-5
+    z = rows_of_state(h, n, rows)
+    assert np.max(np.abs(z - ref["z"])) / np.max(np.abs(ref["z"] - np.eye(n)[rows])) <= 1e-5
+
+
+def test_c3_sparse_32768_spmm_twenty_steps_and_dominant():
+    n = 32768
+    theta, ip, ix, v = workloads.sparse_sym(0, n=n)
+    csr = (device(ip), device(ix), device(v))
+    spec = dpt.ProblemSpec(device(theta), csr, 1.0)
+    h = dpt.dpt_init(spec, dpt.options(precision=dpt.DPT_FP32))
+    last = dpt.dpt_step(h, 20)
+    assert np.isfinite(last)
+    e = dpt.dpt_eigenvalues(h)
+    rows = workloads.sample_rows(n, 64)
+    v64 = v.astype(np.float64)
+    ref = oracle.iterate(theta, (ip, ix, v64), 1.0, rows=rows, max_iter=20, fixed_steps=True)
+    assert rel_eig_error(e[rows], ref["e"], theta) <= 1e-5
+    z = rows_of_state(h, n, rows)
+    assert np.max(np.abs(z - ref["z"])) / np.max(np.abs(ref["z"] - np.eye(n)[rows])) <= 1e-5
+    del h
+    # dominant eigenvector alone, to max|dz| < 1e-6
+    ev, vec, res = dpt.dpt_dominant(spec, dpt.options(tol=1e-6, max_iter=50, precision=dpt.DPT_FP32))
+    assert res["status"] == dpt.DPT_OK and res["iters"] <= 4
+    rd = oracle.iterate(theta, (ip, ix, v64), 1.0, rows=[n - 1], max_iter=50, tol=1e-15)
+    assert abs(ev - rd["e"][0]) <= 1e-6 * abs(rd["e"][0])
+    assert np.max(np.abs(vec.cpu().numpy() - rd["z"][0])) <= 1e-5
