@@ -29,7 +29,7 @@ METRIC = "DPT iter/s + TFLOP/s at N=16384 (bf16→fp32 vs fp32); solves/s, p50/p
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_bf16_n16384.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2002_12872_amd", "csrc", "kernels_dense.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2002_12872_amd", "csrc", "kernels_gemm_bf16.hip")
 
 
 def parse():
@@ -175,7 +175,7 @@ def main():
     traffic = read_traffic(n)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
-                "traffic": traffic, "kernel": "k_step_gemm<PolBF16,256,128,32,2,2>",
+                "traffic": traffic, "kernel": "k_step_bf16_v2 (256x256 tile, 4-stage direct-to-LDS)",
                 "avg_launch_ms": round(avg_ms, 4), "launches": g_cnt,
                 "algorithmic_flop_per_launch": flop}
 

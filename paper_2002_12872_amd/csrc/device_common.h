@@ -1,0 +1,51 @@
+// Device helpers shared by the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpt {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16_t;
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4_t;
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr unsigned long long kNanBits = 0x7ff8000000000000ull;
+
+__device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
+
+// Wave-wide max of (delta, |w|) plus a non-finite flag; lane 0 of every wave
+// publishes with one atomicMax per value (max is order-independent, so the
+// result is deterministic).  Must be reached by all 64 lanes of the wave.
+__device__ __forceinline__ void publish_stats(unsigned long long *stat, double dmax, double wmax, bool bad) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        dmax = fmax(dmax, __shfl_xor(dmax, o));
+        wmax = fmax(wmax, __shfl_xor(wmax, o));
+    }
+    const bool any_bad = __any(bad ? 1 : 0);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(stat, any_bad ? kNanBits : dbits(dmax));
+        atomicMax(stat + 1, any_bad ? kNanBits : dbits(wmax));
+    }
+}
+
+// Block -> output tile.  Workgroups are dispatched round-robin over the 8 XCDs
+// (bid % 8), so first make each XCD's blocks a contiguous range of logical tile
+// ids, then walk the tiles in groups of G tile-rows so that the blocks resident
+// on one XCD share operand panels in that XCD's L2.
+template <int G>
+__device__ __forceinline__ void tile_coords(int bid, int nblocks, int tiles_m, int tiles_n, int &tm, int &tn) {
+    int t = bid;
+    if ((nblocks & 7) == 0) t = (bid & 7) * (nblocks >> 3) + (bid >> 3);
+    const int group_size = G * tiles_n;
+    const int group = t / group_size;
+    const int first = group * G;
+    const int gm = min(tiles_m - first, G);
+    const int within = t - group * group_size;
+    tm = first + within % gm;
+    tn = within / gm;
+}
+
+}  // namespace dpt

@@ -8,44 +8,19 @@
 // and the eigenvalue readout of Sec. II.B is E_n = theta_n + lambda C[n][n].
 #include <float.h>
 
+#include "device_common.h"
 #include "dpt_internal.h"
 
 namespace dpt {
 namespace {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16_t;
-typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4_t;
-typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
-
 constexpr int kThreads = 256;
-constexpr unsigned long long kNanBits = 0x7ff8000000000000ull;
 
 inline unsigned int grid_1d(int64_t work_items, int64_t cap = 1 << 20) {
     int64_t blocks = (work_items + kThreads - 1) / kThreads;
     if (blocks < 1) blocks = 1;
     if (blocks > cap) blocks = cap;
     return (unsigned int)blocks;
-}
-
-__device__ __forceinline__ unsigned long long dbits(double x) {
-    return (unsigned long long)__double_as_longlong(x);
-}
-
-// Wave-wide max of (delta, |w|) plus a non-finite flag; lane 0 of every wave
-// publishes with one atomicMax per value (max is order-independent, so the
-// result is deterministic).  Must be reached by all 64 lanes.
-__device__ __forceinline__ void publish_stats(unsigned long long *stat, double dmax, double wmax, bool bad) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        dmax = fmax(dmax, __shfl_xor(dmax, o));
-        wmax = fmax(wmax, __shfl_xor(wmax, o));
-    }
-    const bool any_bad = __any(bad ? 1 : 0);
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(stat, any_bad ? kNanBits : dbits(dmax));
-        atomicMax(stat + 1, any_bad ? kNanBits : dbits(wmax));
-    }
 }
 
 // ----------------------------------------------------------------- utilities
@@ -257,23 +232,6 @@ struct PolF64 {
     static __device__ __forceinline__ int acc_col(int lane) { return lane & 15; }
 };
 
-// Block -> output tile.  Workgroups are dispatched round-robin over the 8 XCDs
-// (bid % 8), so first make each XCD's blocks a contiguous range of logical tile
-// ids, then walk the tiles in groups of 8 tile-rows so that the blocks resident
-// on one XCD share operand panels in that XCD's L2.
-__device__ __forceinline__ void tile_coords(int bid, int nblocks, int tiles_m, int tiles_n, int &tm, int &tn) {
-    int t = bid;
-    if ((nblocks & 7) == 0) t = (bid & 7) * (nblocks >> 3) + (bid >> 3);
-    constexpr int G = 8;
-    const int group_size = G * tiles_n;
-    const int group = t / group_size;
-    const int first = group * G;
-    const int gm = min(tiles_m - first, G);
-    const int within = t - group * group_size;
-    tm = first + within % gm;
-    tn = within / gm;
-}
-
 template <class P, int BM, int BN, int BK, int WM, int WN, typename S>
 __global__ __launch_bounds__(WM *WN * 64) void k_step_gemm(const typename P::in_t *__restrict__ A,
                                                            const typename P::in_t *__restrict__ B,
@@ -299,7 +257,7 @@ __global__ __launch_bounds__(WM *WN * 64) void k_step_gemm(const typename P::in_
     __shared__ __attribute__((aligned(16))) in_t sB[2][BN * LDK];
 
     int tm, tn;
-    tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / WN, wc = wave % WN;
@@ -597,6 +555,7 @@ hipError_t launch_prepass_f64_f64(const double *W, const double *D, const StepAr
 // everything else the 64x64 tiles.
 hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                             const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
+    if (Wbn && step_bf16_v2_supported(a.ld)) return launch_step_bf16_v2(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
     if (a.ld % 256 == 0 && a.ld >= 1024)
         return launch_gemm<PolBF16, 256, 128, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
     return launch_gemm<PolBF16, 64, 64, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);

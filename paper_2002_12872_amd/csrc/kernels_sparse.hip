@@ -19,6 +19,7 @@
 #include <limits>
 #include <vector>
 
+#include "device_common.h"
 #include "dpt_internal.h"
 #include "dpt_sparse.h"
 
@@ -27,23 +28,6 @@ namespace dpt {
 namespace {
 
 constexpr int kPanel = 256;  // eigenvectors per SpMM wave (4 per lane)
-constexpr unsigned long long kNanBits = 0x7ff8000000000000ull;
-
-__device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
-
-__device__ __forceinline__ void publish_stats(unsigned long long *stat, double dmax, double wmax, bool bad) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        dmax = fmax(dmax, __shfl_xor(dmax, o));
-        wmax = fmax(wmax, __shfl_xor(wmax, o));
-    }
-    const bool any_bad = __any(bad ? 1 : 0);
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(stat, any_bad ? kNanBits : dbits(dmax));
-        atomicMax(stat + 1, any_bad ? kNanBits : dbits(wmax));
-    }
-}
-
 inline unsigned int blocks_for(int64_t items, int per_block, int64_t cap = 1 << 20) {
     int64_t b = (items + per_block - 1) / per_block;
     return (unsigned int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
