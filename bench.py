@@ -46,7 +46,83 @@ def parse():
                     help="profiling mode: init once, run --steps BF16 steps (after --warmup), no solve")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="profiling mode: plain device-to-device copy of MIB MiB, --steps times")
+    ap.add_argument("--serve-requests", type=int, default=4096,
+                    help="serving trace length (0 skips the serving measurement)")
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     return ap.parse_args()
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def serving_bench(args):
+    """Continuous batching vs one-at-a-time FP32 solves on the serving trace.
+
+    Trace: N log-uniform in [32, 2048], half symmetric, theta_i = i + U(0, 0.5),
+    Delta ~ N(0, (0.4/sqrt N)^2), tol 1e-5, BF16->FP32 in the engine.  The
+    one-at-a-time FP32 service rate mu_1 is measured first on the trace's
+    problems; arrivals are Poisson at rate mu_1.  Engine latencies come from its
+    own submit/finish timestamps; the one-at-a-time latencies from its measured
+    service times through a FIFO single-server queue on the same arrivals.
+    """
+    import numpy as np
+
+    import workloads
+    from paper_2002_12872_amd import dpt
+    count = args.serve_requests
+    trace = workloads.serving_trace(0, count=count, rate=None)
+    probs = [workloads.request_matrices(r) for r in trace]
+    specs = [dpt.ProblemSpec(th, de, 1.0, stream=0) for th, de in probs]
+    o_fp32 = dpt.options(tol=1e-5, max_iter=100, precision=dpt.DPT_FP32)
+    o_mixed = dpt.options(tol=1e-5, max_iter=100, precision=dpt.DPT_BF16_FP32)
+    # one-at-a-time FP32 solves: service time of every request
+    svc = np.empty(count)
+    ok = 0
+    for i, sp in enumerate(specs):
+        t = time.perf_counter()
+        h = dpt.dpt_init(sp, o_fp32)
+        r = dpt.dpt_solve(h, history_cap=0)
+        dpt.dpt_eigenvalues(h)
+        dpt.dpt_destroy(h)
+        svc[i] = time.perf_counter() - t
+        ok += r["status"] == dpt.DPT_OK
+    mu1 = count / svc.sum()
+    rng = np.random.default_rng(5_100)
+    arrivals = np.cumsum(rng.exponential(1.0 / mu1, size=count))
+    finish = np.empty(count)
+    prev = 0.0
+    for i in range(count):
+        prev = max(arrivals[i], prev) + svc[i]
+        finish[i] = prev
+    lat_base = finish - arrivals
+    base = {"solves_per_s": round(count / (finish[-1] - arrivals[0]), 2),
+            "p50_ms": round(1e3 * percentile(lat_base, 50), 3),
+            "p99_ms": round(1e3 * percentile(lat_base, 99), 3),
+            "mean_service_ms": round(1e3 * svc.mean(), 3), "converged": int(ok)}
+    # engine in real time on the same arrivals
+    srv = dpt.dpt_serve_open(int(args.serve_budget_gib * (1 << 30)), max_slots=1024, use_graph=True)
+    tickets = []
+    t0 = time.perf_counter()
+    for i, sp in enumerate(specs):
+        delay = arrivals[i] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(dpt.dpt_serve_submit(srv, sp, o_mixed))
+    res = [dpt.dpt_serve_poll(srv, t, wait_ms=-1) for t in tickets]
+    st = dpt.dpt_serve_stats_read(srv)
+    dpt.dpt_serve_close(srv)
+    lat = np.array([r["times"]["finish"] - r["times"]["submit"] for r in res])
+    span = max(r["times"]["finish"] for r in res) - min(r["times"]["submit"] for r in res)
+    eng = {"solves_per_s": round(count / span, 2), "p50_ms": round(1e3 * percentile(lat, 50), 3),
+           "p99_ms": round(1e3 * percentile(lat, 99), 3),
+           "converged": int(sum(r["status"] == dpt.DPT_OK for r in res)),
+           "steps": st["steps"], "peak_active": st["peak_active"],
+           "peak_arena_gib": round(st["peak_bytes"] / 2 ** 30, 3)}
+    return {"requests": count, "arrival_rate_per_s": round(mu1, 2), "tol": 1e-5,
+            "engine_bf16_fp32": eng, "one_at_a_time_fp32": base,
+            "p99_speedup": round(base["p99_ms"] / eng["p99_ms"], 2)}
 
 
 def kernel_only(args):
@@ -251,6 +327,9 @@ def main():
                                        "oracle_iterations": k}
     for h in handles:
         dpt.dpt_destroy(h)
+    if args.serve_requests > 0:
+        print("# serving trace of %d requests" % args.serve_requests, file=sys.stderr, flush=True)
+        out["serving"] = serving_bench(args)
     print(json.dumps(out), flush=True)
 
 

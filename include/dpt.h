@@ -194,6 +194,63 @@ int dpt_profile_enable(dpt_handle h, int on);
 /* Synchronise the stream and copy the totals into *out. */
 int dpt_profile_read(dpt_handle h, dpt_profile *out);
 
+/* ---- serving: continuous batching of many small dense problems ----------
+ * A server owns a device memory arena of budget_bytes and a worker thread.
+ * Submitted problems wait in FIFO order and are admitted while the arena and
+ * the slot table have room; every engine step advances all admitted problems
+ * by one application of F with one persistent grouped launch per precision
+ * phase (replayed as a HIP graph when use_graph != 0); each problem follows
+ * its own stopping rule and is retired individually (freeing its memory for
+ * the next admissions).  Results do not depend on which other problems share
+ * a step: every problem is computed with the same 64x64 tiles and its own
+ * statistics. */
+typedef struct dpt_server_ctx *dpt_server;
+
+typedef struct dpt_serve_config {
+    int64_t budget_bytes;   /* device arena for in-flight problems (> 0)              */
+    int32_t max_slots;      /* concurrent problems, 1 .. 1024                         */
+    int32_t use_graph;      /* 1: replay the grouped step as a HIP graph              */
+    int32_t grid_blocks;    /* persistent grid of the grouped kernels; 0 = 1024       */
+    int32_t reserved;       /* must be 0                                              */
+} dpt_serve_config;
+
+/* Seconds since dpt_serve_open on a monotonic clock. */
+typedef struct dpt_serve_times {
+    double submit_s, admit_s, first_step_s, finish_s;
+} dpt_serve_times;
+
+typedef struct dpt_serve_stats {
+    int64_t submitted, completed, steps;   /* problems and engine steps so far      */
+    int64_t peak_active, peak_bytes;       /* largest concurrent set and arena use  */
+    int64_t active, pending;               /* current counts                        */
+    double busy_s;                         /* wall time spent inside engine steps   */
+} dpt_serve_stats;
+
+/* Start a server on the current device (creates its own stream).  Returns
+ * DPT_OK, DPT_EINVAL, DPT_ENOMEM (arena allocation) or DPT_EDEVICE. */
+int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg);
+
+/* Queue a dense problem given in host memory (DPT_MEM_HOST; copied before the
+ * call returns).  o->precision must be DPT_FP32 or DPT_BF16_FP32 (o may be
+ * NULL: defaults).  want_eigenvectors != 0 keeps Z for dpt_serve_poll.  Returns
+ * DPT_OK and a ticket, DPT_EINVAL (bad problem, duplicate theta) or DPT_ENOMEM
+ * (the problem alone exceeds the arena). */
+int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o, int want_eigenvectors,
+                     int64_t *ticket);
+
+/* Wait up to wait_ms (0: do not wait, < 0: until done) for a ticket.  Returns
+ * DPT_EAGAIN while it is pending; otherwise its numerical status, with r, E (n
+ * doubles), Z (n*n values of z_dtype, only if requested at submit) and t filled
+ * when non-NULL.  A completed ticket is released by the call that returns its
+ * status (a later poll returns DPT_EINVAL). */
+int dpt_serve_poll(dpt_server srv, int64_t ticket, int wait_ms, dpt_result *r, double *E, void *Z, int z_dtype,
+                   dpt_serve_times *t);
+
+int dpt_serve_stats_read(dpt_server srv, dpt_serve_stats *out);
+
+/* Finish every queued problem, stop the worker and release the server. */
+void dpt_serve_close(dpt_server srv);
+
 /* Release the handle (NULL is accepted). */
 void dpt_destroy(dpt_handle h);
 

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "dpt.h"
+#include "controller.h"
 #include "dpt_internal.h"
 #include "dpt_sparse.h"
 
@@ -619,92 +620,44 @@ int dpt_step(dpt_handle h, int nsteps, double *last_delta) {
 
 int dpt_solve(dpt_handle h, dpt_result *r) {
     if (!h) return DPT_EINVAL;
-    const dpt_options &o = h->opt;
-    int status = DPT_NOT_CONVERGED;
-    int iters = 0, it_phase[3] = {0, 0, 0};
-    double best = std::numeric_limits<double>::infinity();
-    int stall_run = 0;
-    double last = std::numeric_limits<double>::quiet_NaN();
+    Controller ctl;
+    ctl.start(h->opt, h->phase, h->sp == nullptr);
     int64_t checked = h->k;  // stats already consumed
     bool done = false;
-    while (!done && iters < o.max_iter) {
+    while (!done && !ctl.capped()) {
         int rc = do_step(h);
         if (rc != DPT_OK) return rc;
-        ++iters;
-        ++it_phase[h->phase];
-        if (iters % o.check_every != 0 && iters < o.max_iter) continue;
+        ctl.count_step();
+        if (ctl.iters % h->opt.check_every != 0 && !ctl.capped()) continue;
         rc = fetch_stats(h, checked, h->k);
         if (rc != DPT_OK) return rc;
         for (int64_t s = checked; s < h->k; ++s) {
             double dl, wm;
             stat_of(h, s, &dl, &wm);
-            const int idx = iters - (int)(h->k - s);
+            const int idx = ctl.iters - (int)(h->k - s);
             if (r && r->delta_history && idx >= 0 && idx < r->history_cap) r->delta_history[idx] = dl;
         }
         checked = h->k;
         double dl, wm;
         stat_of(h, h->k - 1, &dl, &wm);
-        last = dl;
-        if (!std::isfinite(dl) || !(wm <= o.blowup)) {
-            status = DPT_DIVERGED;
-            break;
-        }
-        // A stall is a rounding floor: no progress while delta already sits within
-        // a few thousand ulps (of the phase's precision) of the state's magnitude.
-        // Larger non-decreasing deltas are cycles or chaos and run to the cap.
-        static const double kFloor[3] = {1.0, 1e4 * 5.96e-8, 1e4 * 1.11e-16};
-        bool stalled = false;
-        if (dl == 0.0) {
-            stalled = true;
-        } else if (dl >= o.stall_ratio * best && dl <= kFloor[h->phase] * std::max(1.0, wm)) {
-            stalled = ++stall_run >= o.stall_patience;
-        } else {
-            stall_run = 0;
-        }
-        best = std::min(best, dl);
-        if (h->phase == PH_BF16) {
-            // The BF16 fixed point is biased: always finish with FP32 sweeps.
-            if (dl < o.tol || stalled) {
+        switch (ctl.update(dl, wm)) {
+            case Controller::TO_FP32:
                 h->phase = PH_FP32;
-                best = std::numeric_limits<double>::infinity();
-                stall_run = 0;
-            }
-        } else if (h->phase == PH_FP32) {
-            if (dl < o.tol) {
-                if (o.fp64_final_tol > 0.0 && !h->sp) {
-                    rc = enter_fp64(h);
-                    if (rc != DPT_OK) return rc;
-                    best = std::numeric_limits<double>::infinity();
-                    stall_run = 0;
-                } else {
-                    status = DPT_OK;
-                    done = true;
-                }
-            } else if (stalled) {
-                status = DPT_STALLED;
+                break;
+            case Controller::TO_FP64:
+                rc = enter_fp64(h);
+                if (rc != DPT_OK) return rc;
+                break;
+            case Controller::DONE:
                 done = true;
-            }
-        } else {
-            const double target = (o.precision == DPT_FP64) ? o.tol : o.fp64_final_tol;
-            if (dl < target) {
-                status = DPT_OK;
-                done = true;
-            } else if (stalled) {
-                status = DPT_STALLED;
-                done = true;
-            }
+                break;
+            default:
+                break;
         }
     }
     if (hipStreamSynchronize(h->stream) != hipSuccess) return DPT_EDEVICE;
-    if (r) {
-        r->status = status;
-        r->iters = iters;
-        r->iters_bf16 = it_phase[PH_BF16];
-        r->iters_fp32 = it_phase[PH_FP32];
-        r->iters_fp64 = it_phase[PH_FP64];
-        r->last_delta = last;
-    }
-    return status;
+    ctl.fill(r);
+    return ctl.status;
 }
 
 int dpt_eigenvalues(dpt_handle h, double *E, int mem) {

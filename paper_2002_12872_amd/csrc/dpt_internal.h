@@ -100,4 +100,43 @@ hipError_t launch_residual_f32(const float *W, const void *D, int d_is_f64, cons
 hipError_t launch_residual_f64(const double *W, const void *D, int d_is_f64, const StepArgs &a,
                                const int64_t *rows, int64_t nrows, const double *E, double *part, hipStream_t s);
 
+// ---- serving: grouped persistent kernels (kernels_dense.hip) ---------------
+// One in-flight request as the grouped kernels see it (dense, padded to ld, a
+// multiple of 64; state W = Z - I in FP32 with a BF16 shadow in the BF16 phase).
+struct GroupReq {
+    const __bf16 *Wb;           // current BF16 state (BF16 phase)
+    const __bf16 *Db;           // BF16 Delta
+    const float *W;             // current FP32 state
+    const float *D;             // FP32 Delta, row-major
+    const float *DT;            // FP32 Delta^T (== D when symmetric)
+    float *Wn;                  // next FP32 state
+    __bf16 *Wbn;                // next BF16 state (BF16 phase), else null
+    const double *theta;        // ld entries
+    double *d;                  // ld entries, d_n of the current state
+    unsigned long long *stat;   // 2 u64: delta, max|W|
+    int64_t n, ld;
+    double lambda;
+};
+
+constexpr int kServeMaxSlots = 1024;
+
+// Work lists of one serving step, rewritten by the host before every step.
+// counts = {requests, BF16-phase requests, FP32-phase requests}; prefix arrays
+// hold running sums of rows (pre-pass) and of 64x64 tiles (step kernels).
+struct GroupTable {
+    int32_t counts[4];
+    int32_t pre_prefix[kServeMaxSlots + 1];
+    int32_t bf_idx[kServeMaxSlots];
+    int32_t bf_prefix[kServeMaxSlots + 1];
+    int32_t fp_idx[kServeMaxSlots];
+    int32_t fp_prefix[kServeMaxSlots + 1];
+    GroupReq reqs[kServeMaxSlots];
+};
+
+// Persistent grouped launches with a fixed grid (graph-capturable): the
+// pre-pass (also clears each request's stats) and the fused step for the
+// requests in one phase (PH_BF16 or PH_FP32).
+hipError_t launch_group_prepass(const GroupTable *t, int grid, hipStream_t s);
+hipError_t launch_group_step(const GroupTable *t, int phase, int grid, hipStream_t s);
+
 }  // namespace dpt

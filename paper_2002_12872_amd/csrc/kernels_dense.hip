@@ -232,12 +232,13 @@ struct PolF64 {
     static __device__ __forceinline__ int acc_col(int lane) { return lane & 15; }
 };
 
+// One output tile (tm, tn) of one fused step; called by the single-problem
+// kernel below and by the grouped serving kernel (one tile per work item).
 template <class P, int BM, int BN, int BK, int WM, int WN, typename S>
-__global__ __launch_bounds__(WM *WN * 64) void k_step_gemm(const typename P::in_t *__restrict__ A,
-                                                           const typename P::in_t *__restrict__ B,
-                                                           const S *__restrict__ deltaT, const S *__restrict__ Wold,
-                                                           S *__restrict__ Wnew, __bf16 *__restrict__ Wbnew,
-                                                           StepArgs a, int tiles_m, int tiles_n) {
+__device__ __forceinline__ void step_tile(const typename P::in_t *__restrict__ A, const typename P::in_t *__restrict__ B,
+                                          const S *__restrict__ deltaT, const S *__restrict__ Wold,
+                                          S *__restrict__ Wnew, __bf16 *__restrict__ Wbnew, const StepArgs &a, int tm,
+                                          int tn) {
     using in_t = typename P::in_t;
     constexpr int NT = WM * WN * 64;
     constexpr int VEC = 16 / (int)sizeof(in_t);  // elements per 16-byte chunk
@@ -256,8 +257,6 @@ __global__ __launch_bounds__(WM *WN * 64) void k_step_gemm(const typename P::in_
     __shared__ __attribute__((aligned(16))) in_t sA[2][BM * LDK];
     __shared__ __attribute__((aligned(16))) in_t sB[2][BN * LDK];
 
-    int tm, tn;
-    tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / WN, wc = wave % WN;
@@ -381,6 +380,86 @@ __global__ __launch_bounds__(WM *WN * 64) void k_step_gemm(const typename P::in_
         }
     }
     publish_stats(a.stat, dmax, wmax, bad);
+}
+
+template <class P, int BM, int BN, int BK, int WM, int WN, typename S>
+__global__ __launch_bounds__(WM *WN * 64) void k_step_gemm(const typename P::in_t *__restrict__ A,
+                                                           const typename P::in_t *__restrict__ B,
+                                                           const S *__restrict__ deltaT, const S *__restrict__ Wold,
+                                                           S *__restrict__ Wnew, __bf16 *__restrict__ Wbnew,
+                                                           StepArgs a, int tiles_m, int tiles_n) {
+    int tm, tn;
+    tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    step_tile<P, BM, BN, BK, WM, WN, S>(A, B, deltaT, Wold, Wnew, Wbnew, a, tm, tn);
+}
+
+// ------------------------------------------------------- grouped (serving)
+// Largest j in [0, cnt) with prefix[j] <= item (prefix ascending, prefix[0] = 0).
+__device__ __forceinline__ int find_segment(const int32_t *prefix, int cnt, int item) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// One wave per (request, row): d_n = Delta[n][n] + sum_k W[n][k] Delta[n][k] in
+// FP64 (fixed butterfly order); row 0 of every request clears its stats.
+__global__ __launch_bounds__(256) void k_group_prepass(const GroupTable *__restrict__ t) {
+    const int nreq = t->counts[0];
+    const int total = nreq > 0 ? t->pre_prefix[nreq] : 0;
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * 4;
+    for (int item = blockIdx.x * 4 + (threadIdx.x >> 6); item < total; item += nwaves) {
+        const int r = find_segment(t->pre_prefix, nreq, item);
+        const GroupReq &q = t->reqs[r];
+        const int64_t row = item - t->pre_prefix[r];
+        const float *w = q.W + row * q.ld;
+        const float *dl = q.D + row * q.ld;
+        double sum = 0.0;
+        for (int64_t k = lane; k < q.n; k += 64) sum += (double)w[k] * (double)dl[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+        if (lane == 0) {
+            q.d[row] = (double)dl[row] + sum;
+            if (row == 0) {
+                q.stat[0] = 0ull;
+                q.stat[1] = 0ull;
+            }
+        }
+    }
+}
+
+// One 64x64 output tile of one request per work item; blocks stride over the
+// items of every request in the phase (persistent grid, fixed size).
+template <int PHASE>
+__global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict__ t) {
+    const int cnt = PHASE == PH_BF16 ? t->counts[1] : t->counts[2];
+    const int32_t *idx = PHASE == PH_BF16 ? t->bf_idx : t->fp_idx;
+    const int32_t *prefix = PHASE == PH_BF16 ? t->bf_prefix : t->fp_prefix;
+    const int total = cnt > 0 ? prefix[cnt] : 0;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int j = find_segment(prefix, cnt, item);
+        const GroupReq &q = t->reqs[idx[j]];
+        const int tpr = (int)(q.ld / 64);
+        const int local = item - prefix[j];
+        const int tm = local / tpr, tn = local - tm * tpr;
+        StepArgs a;
+        a.n = q.n;
+        a.ld = q.ld;
+        a.lambda = q.lambda;
+        a.theta = q.theta;
+        a.d = q.d;
+        a.stat = q.stat;
+        if (PHASE == PH_BF16)
+            step_tile<PolBF16, 64, 64, 32, 2, 2, float>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
+        else
+            step_tile<PolF32, 64, 64, 16, 2, 2, float>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a, tm, tn);
+    }
 }
 
 // ------------------------------------------------------------------ export
@@ -590,6 +669,21 @@ hipError_t launch_export_f64(const double *W, int64_t n, int64_t ld, void *out, 
     else
         hipLaunchKernelGGL((k_export<double, float>), dim3(grid_1d(n * n)), dim3(kThreads), 0, s, W, n, ld,
                            (float *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_prepass(const GroupTable *t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_prepass, dim3((unsigned int)grid), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_step(const GroupTable *t, int phase, int grid, hipStream_t s) {
+    if (phase == PH_BF16)
+        hipLaunchKernelGGL(k_group_step<PH_BF16>, dim3((unsigned int)grid), dim3(256), 0, s, t);
+    else if (phase == PH_FP32)
+        hipLaunchKernelGGL(k_group_step<PH_FP32>, dim3((unsigned int)grid), dim3(256), 0, s, t);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

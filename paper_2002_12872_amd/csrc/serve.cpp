@@ -1,0 +1,612 @@
+// Serving engine: continuous batching of many small dense D-PT problems.
+//
+// A worker thread owns one stream, a device arena of the configured budget
+// and a slot table.  Each engine step:
+//   1. admits waiting problems in FIFO order while the arena and the slots have
+//      room (upload, padded FP32/BF16 copies, transpose when unsymmetric);
+//   2. applies the map of eq. (dyn) (Kenmoe, Smerlak, Zadorin, arXiv:2002.12872,
+//      Sec. II.B) once to every admitted problem: the closed-form first iterate
+//      for new ones, then one persistent grouped pre-pass and one persistent
+//      grouped fused step per precision phase over a device work table (the
+//      three launches are a HIP graph replayed every step);
+//   3. reads every problem's (delta, max|W|) back and runs its own controller
+//      (the same stopping rule as dpt_solve);
+//   4. retires finished problems (eigenvalues and optional eigenvectors copied
+//      out), releasing their arena space for the next admissions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstddef>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "controller.h"
+#include "dpt.h"
+#include "dpt_internal.h"
+
+using namespace dpt;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) with coalescing of neighbouring holes.
+class Arena {
+  public:
+    void init(size_t size) {
+        holes_.clear();
+        holes_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        for (auto it = holes_.begin(); it != holes_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, at = it->first + bytes;
+                holes_.erase(it);
+                if (rest) holes_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto it = holes_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != holes_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            holes_.erase(next);
+        }
+        if (it != holes_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                holes_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> holes_;
+};
+
+struct Request {
+    int64_t id = 0, n = 0, ld = 0;
+    double lambda = 0.0;
+    dpt_options opt{};
+    bool bf16 = false, symmetric = false, want_z = false;
+    std::vector<double> theta;  // ld entries (zero padded)
+    std::vector<float> delta;   // n*n row-major, freed after admission
+    // device memory inside the arena
+    size_t off = 0, bytes = 0;
+    int slot = -1;
+    double *theta_d = nullptr, *d_d = nullptr, *e_d = nullptr;
+    float *W[2] = {nullptr, nullptr}, *D = nullptr, *DT = nullptr;
+    __bf16 *Wb[2] = {nullptr, nullptr}, *Db = nullptr;
+    int cur = 0;
+    bool at_identity = true;
+    Controller ctl;
+    double t_submit = 0, t_admit = -1, t_first = -1, t_finish = -1;
+    std::vector<double> E;
+    std::vector<float> Z;
+    int status = DPT_NOT_CONVERGED;
+};
+
+size_t request_bytes(int64_t ld, bool bf16, bool symmetric) {
+    const size_t l = (size_t)ld, l2 = l * l;
+    size_t b = 3 * round_up(l * 8);          // theta, d, E
+    b += round_up(2 * l2 * 4);               // W[0], W[1] (W[1] doubles as upload staging)
+    b += round_up(l2 * 4);                   // D
+    if (!symmetric) b += round_up(l2 * 4);   // D^T
+    if (bf16) b += round_up(2 * l2 * 2) + round_up(l2 * 2);  // Wb[0..1], Db
+    return b;
+}
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct dpt_server_ctx {
+    dpt_serve_config cfg{};
+    int device = 0, grid = 1024;
+    hipStream_t stream = nullptr;
+    unsigned char *arena_base = nullptr;
+    Arena arena;
+    size_t arena_used = 0;
+    GroupTable *table_h = nullptr, *table_d = nullptr;
+    unsigned long long *stats_d = nullptr, *stats_h = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::chrono::steady_clock::time_point t0;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> pending;                  // guarded by mu
+    std::unordered_map<int64_t, Request *> done;    // guarded by mu
+    std::unordered_map<int64_t, int> live;          // ticket -> 1 (guarded by mu)
+    std::vector<Request *> active;                  // worker only
+    std::vector<int> free_slots;                    // worker only
+    int64_t next_id = 0;
+    bool stop = false;
+    int error = DPT_OK;
+    dpt_serve_stats st{};
+    std::thread worker;
+
+    ~dpt_server_ctx() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (arena_base) (void)hipFree(arena_base);
+        if (table_d) (void)hipFree(table_d);
+        if (stats_d) (void)hipFree(stats_d);
+        if (table_h) (void)hipHostFree(table_h);
+        if (stats_h) (void)hipHostFree(stats_h);
+        if (stream) (void)hipStreamDestroy(stream);
+        for (auto *r : pending) delete r;
+        for (auto &kv : done) delete kv.second;
+        for (auto *r : active) delete r;
+    }
+
+    // ------------------------------------------------------------ worker
+    hipError_t launch_grouped() {
+        if (cfg.use_graph) return hipGraphLaunch(graph_exec, stream);
+        hipError_t e = launch_group_prepass(table_d, grid, stream);
+        if (e == hipSuccess) e = launch_group_step(table_d, PH_BF16, grid, stream);
+        if (e == hipSuccess) e = launch_group_step(table_d, PH_FP32, grid, stream);
+        return e;
+    }
+
+    hipError_t admit_one(Request *r, size_t off) {
+        r->off = off;
+        r->bytes = request_bytes(r->ld, r->bf16, r->symmetric);
+        r->slot = free_slots.back();
+        free_slots.pop_back();
+        const size_t l = (size_t)r->ld, l2 = l * l;
+        unsigned char *p = arena_base + off;
+        auto take = [&](size_t bytes) {
+            unsigned char *q = p;
+            p += round_up(bytes);
+            return q;
+        };
+        r->theta_d = (double *)take(l * 8);
+        r->d_d = (double *)take(l * 8);
+        r->e_d = (double *)take(l * 8);
+        float *wpair = (float *)take(2 * l2 * 4);
+        r->W[0] = wpair;
+        r->W[1] = wpair + l2;
+        r->D = (float *)take(l2 * 4);
+        r->DT = r->symmetric ? r->D : (float *)take(l2 * 4);
+        if (r->bf16) {
+            __bf16 *bpair = (__bf16 *)take(2 * l2 * 2);
+            r->Wb[0] = bpair;
+            r->Wb[1] = bpair + l2;
+            r->Db = (__bf16 *)take(l2 * 2);
+        }
+        hipError_t e = hipMemcpyAsync(r->theta_d, r->theta.data(), l * 8, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->W[1], r->delta.data(), (size_t)(r->n * r->n) * 4, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = launch_pad_copy_f32_from_f32(r->D, r->W[1], r->n, r->ld, stream);
+        if (e == hipSuccess && !r->symmetric) e = launch_transpose_f32(r->DT, r->D, r->ld, stream);
+        if (e == hipSuccess && r->bf16) e = launch_cvt_f32_to_bf16(r->Db, r->D, (int64_t)l2, stream);
+        if (e == hipSuccess) e = launch_fill_zero(wpair, 2 * l2 * 4, stream);
+        if (e == hipSuccess && r->bf16) e = launch_fill_zero(r->Wb[0], 2 * l2 * 2, stream);
+        if (e == hipSuccess) e = launch_fill_zero(r->d_d, l * 8, stream);
+        r->ctl.start(r->opt, r->bf16 ? PH_BF16 : PH_FP32, false);
+        r->t_admit = now_s(t0);
+        return e;
+    }
+
+    hipError_t admit() {
+        for (;;) {
+            Request *r;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (pending.empty()) return hipSuccess;
+                r = pending.front();
+            }
+            if (free_slots.empty()) return hipSuccess;
+            size_t off;
+            if (!arena.alloc(request_bytes(r->ld, r->bf16, r->symmetric), &off)) return hipSuccess;  // FIFO
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                pending.pop_front();
+                st.pending = (int64_t)pending.size();
+            }
+            hipError_t e = admit_one(r, off);
+            active.push_back(r);
+            arena_used += r->bytes;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                st.peak_bytes = std::max<int64_t>(st.peak_bytes, (int64_t)arena_used);
+                st.peak_active = std::max<int64_t>(st.peak_active, (int64_t)active.size());
+                st.active = (int64_t)active.size();
+            }
+            if (e != hipSuccess) return e;
+        }
+    }
+
+    bool finished(const Request *r) const {
+        return r->ctl.status != DPT_NOT_CONVERGED || r->ctl.capped();
+    }
+
+    hipError_t step() {
+        GroupTable &t = *table_h;
+        int nreq = 0, nbf = 0, nfp = 0;
+        int32_t rows = 0, bft = 0, fpt = 0;
+        std::vector<Request *> first, stepping;
+        for (Request *r : active) {
+            if (finished(r)) continue;  // e.g. max_iter = 0: retired without a step
+            stepping.push_back(r);
+            if (r->at_identity) {
+                first.push_back(r);
+                continue;
+            }
+            const int nx = r->cur ^ 1;
+            const bool bf = r->ctl.phase == PH_BF16;
+            GroupReq &g = t.reqs[nreq];
+            g.Wb = bf ? r->Wb[r->cur] : nullptr;
+            g.Db = r->Db;
+            g.W = r->W[r->cur];
+            g.D = r->D;
+            g.DT = r->DT;
+            g.Wn = r->W[nx];
+            g.Wbn = bf ? r->Wb[nx] : nullptr;
+            g.theta = r->theta_d;
+            g.d = r->d_d;
+            g.stat = stats_d + 2 * r->slot;
+            g.n = r->n;
+            g.ld = r->ld;
+            g.lambda = r->lambda;
+            t.pre_prefix[nreq] = rows;
+            rows += (int32_t)r->n;
+            const int32_t tiles = (int32_t)((r->ld / 64) * (r->ld / 64));
+            if (bf) {
+                t.bf_idx[nbf] = nreq;
+                t.bf_prefix[nbf++] = bft;
+                bft += tiles;
+            } else {
+                t.fp_idx[nfp] = nreq;
+                t.fp_prefix[nfp++] = fpt;
+                fpt += tiles;
+            }
+            ++nreq;
+        }
+        t.pre_prefix[nreq] = rows;
+        t.bf_prefix[nbf] = bft;
+        t.fp_prefix[nfp] = fpt;
+        t.counts[0] = nreq;
+        t.counts[1] = nbf;
+        t.counts[2] = nfp;
+        t.counts[3] = 0;
+        hipError_t e = hipSuccess;
+        for (Request *r : first) {
+            StepArgs a;
+            a.n = r->n;
+            a.ld = r->ld;
+            a.lambda = r->lambda;
+            a.theta = r->theta_d;
+            a.d = r->d_d;
+            a.stat = stats_d + 2 * r->slot;
+            if (e == hipSuccess) e = launch_zero_u64(a.stat, 2, stream);
+            if (e == hipSuccess)
+                e = launch_first_iterate_f32(a, r->DT, r->W[1], r->bf16 ? r->Wb[1] : nullptr, stream);
+        }
+        if (e == hipSuccess && nreq > 0) {
+            e = hipMemcpyAsync(table_d, table_h, offsetof(GroupTable, reqs) + (size_t)nreq * sizeof(GroupReq),
+                               hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = launch_grouped();
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(stats_h, stats_d, 16 * (size_t)cfg.max_slots, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        const double t_now = now_s(t0);
+        for (Request *r : stepping) {
+            r->cur ^= 1;
+            if (r->at_identity) {
+                r->t_first = t_now;
+                std::vector<float>().swap(r->delta);  // staged on the device; drop the host copy
+            }
+            r->at_identity = false;
+            r->ctl.count_step();
+            double dl, wm;
+            std::memcpy(&dl, &stats_h[2 * r->slot], 8);
+            std::memcpy(&wm, &stats_h[2 * r->slot + 1], 8);
+            if (r->ctl.update(dl, wm) == Controller::DONE || r->ctl.capped()) r->status = r->ctl.status;
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        st.steps += 1;
+        return hipSuccess;
+    }
+
+    hipError_t retire() {
+        std::vector<Request *> out;
+        for (Request *r : active)
+            if (finished(r)) out.push_back(r);
+        if (out.empty()) return hipSuccess;
+        hipError_t e = hipSuccess;
+        for (Request *r : out) {
+            StepArgs a;
+            a.n = r->n;
+            a.ld = r->ld;
+            a.lambda = r->lambda;
+            a.theta = r->theta_d;
+            a.d = r->d_d;
+            a.stat = nullptr;
+            r->E.resize((size_t)r->n);
+            if (e == hipSuccess) e = launch_prepass_f32_f32(r->W[r->cur], r->D, a, r->d_d, r->e_d, nullptr, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->E.data(), r->e_d, (size_t)r->n * 8, hipMemcpyDeviceToHost, stream);
+            if (r->want_z) {
+                r->Z.resize((size_t)(r->n * r->n));
+                float *staging = r->W[r->cur ^ 1];
+                if (e == hipSuccess) e = launch_export_f32(r->W[r->cur], r->n, r->ld, staging, 0, stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(r->Z.data(), staging, r->Z.size() * 4, hipMemcpyDeviceToHost, stream);
+            }
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        const double t_now = now_s(t0);
+        for (Request *r : out) {
+            arena.release(r->off, r->bytes);
+            arena_used -= r->bytes;
+            free_slots.push_back(r->slot);
+            r->slot = -1;
+            r->t_finish = t_now;
+            r->status = r->ctl.status;
+            std::vector<float>().swap(r->delta);
+            active.erase(std::find(active.begin(), active.end(), r));
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (Request *r : out) done[r->id] = r;
+            st.completed += (int64_t)out.size();
+            st.active = (int64_t)active.size();
+        }
+        cv_done.notify_all();
+        return e;
+    }
+
+    void fail_all(int code) {
+        std::lock_guard<std::mutex> lk(mu);
+        error = code;
+        for (Request *r : active) {
+            r->status = code;
+            done[r->id] = r;
+        }
+        active.clear();
+        for (Request *r : pending) {
+            r->status = code;
+            done[r->id] = r;
+        }
+        pending.clear();
+        cv_done.notify_all();
+    }
+
+    void run() {
+        (void)hipSetDevice(device);
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                if (active.empty() && pending.empty()) {
+                    if (stop) break;
+                    cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                    continue;
+                }
+            }
+            const auto t_begin = std::chrono::steady_clock::now();
+            hipError_t e = admit();
+            if (e == hipSuccess && !active.empty()) e = step();
+            if (e == hipSuccess) e = retire();
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                st.busy_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
+            }
+            if (e != hipSuccess) {
+                fail_all(e == hipErrorOutOfMemory ? DPT_ENOMEM : DPT_EDEVICE);
+                std::unique_lock<std::mutex> lk(mu);
+                if (stop) break;
+            }
+            if (active.empty()) {
+                std::unique_lock<std::mutex> lk(mu);
+                if (!pending.empty() && free_slots.size() == (size_t)cfg.max_slots) {
+                    // the head problem cannot be admitted even into an empty arena
+                    Request *r = pending.front();
+                    pending.pop_front();
+                    r->status = DPT_ENOMEM;
+                    done[r->id] = r;
+                    cv_done.notify_all();
+                }
+            }
+        }
+    }
+};
+
+extern "C" {
+
+int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
+    if (!srv || !cfg || cfg->budget_bytes <= 0 || cfg->max_slots < 1 || cfg->max_slots > kServeMaxSlots ||
+        cfg->grid_blocks < 0 || cfg->reserved != 0)
+        return DPT_EINVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return DPT_EDEVICE;
+    dpt_server_ctx *c = new (std::nothrow) dpt_server_ctx();
+    if (!c) return DPT_ENOMEM;
+    c->cfg = *cfg;
+    c->grid = cfg->grid_blocks > 0 ? cfg->grid_blocks : 1024;
+    c->t0 = std::chrono::steady_clock::now();
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipStreamCreate(&c->stream);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->arena_base, (size_t)cfg->budget_bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->table_d, sizeof(GroupTable));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->stats_d, 16 * (size_t)cfg->max_slots);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->table_h, sizeof(GroupTable), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->stats_h, 16 * (size_t)cfg->max_slots, 0);
+    if (e == hipSuccess) {
+        std::memset(c->table_h, 0, sizeof(GroupTable));
+        e = hipMemcpy(c->table_d, c->table_h, sizeof(GroupTable), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && cfg->use_graph) {
+        e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e1 = launch_group_prepass(c->table_d, c->grid, c->stream);
+            hipError_t e2 = launch_group_step(c->table_d, PH_BF16, c->grid, c->stream);
+            hipError_t e3 = launch_group_step(c->table_d, PH_FP32, c->grid, c->stream);
+            e = hipStreamEndCapture(c->stream, &c->graph);
+            if (e == hipSuccess) e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess) {
+        const int code = (e == hipErrorOutOfMemory) ? DPT_ENOMEM : DPT_EDEVICE;
+        delete c;
+        return code;
+    }
+    c->arena.init((size_t)cfg->budget_bytes);
+    for (int i = cfg->max_slots - 1; i >= 0; --i) c->free_slots.push_back(i);
+    c->worker = std::thread([c] { c->run(); });
+    *srv = c;
+    return DPT_OK;
+}
+
+int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o, int want_eigenvectors,
+                     int64_t *ticket) {
+    if (!srv || !ticket) return DPT_EINVAL;
+    if (dpt_validate(p, o) != DPT_OK) return DPT_EINVAL;
+    if (p->format != DPT_DENSE || p->mem != DPT_MEM_HOST) return DPT_EINVAL;
+    dpt_options opt;
+    if (o) {
+        opt = *o;
+    } else {
+        dpt_options_default(&opt);
+    }
+    if (opt.precision != DPT_FP32 && opt.precision != DPT_BF16_FP32) return DPT_EINVAL;
+    Request *r = new (std::nothrow) Request();
+    if (!r) return DPT_ENOMEM;
+    r->n = p->n;
+    r->ld = (p->n + 63) / 64 * 64;
+    r->lambda = p->lambda;
+    r->opt = opt;
+    r->bf16 = opt.precision == DPT_BF16_FP32;
+    r->want_z = want_eigenvectors != 0;
+    const size_t nn = (size_t)(p->n * p->n);
+    try {
+        r->theta.assign((size_t)r->ld, 0.0);
+        r->delta.resize(nn);
+    } catch (...) {
+        delete r;
+        return DPT_ENOMEM;
+    }
+    std::memcpy(r->theta.data(), p->theta, sizeof(double) * (size_t)p->n);
+    if (p->dtype == DPT_DTYPE_F64) {
+        const double *src = (const double *)p->delta;
+        for (size_t i = 0; i < nn; ++i) r->delta[i] = (float)src[i];
+    } else {
+        std::memcpy(r->delta.data(), p->delta, nn * 4);
+    }
+    bool sym = true;
+    for (int64_t i = 0; i < p->n && sym; ++i)
+        for (int64_t j = i + 1; j < p->n; ++j)
+            if (!(r->delta[(size_t)(i * p->n + j)] == r->delta[(size_t)(j * p->n + i)])) {
+                sym = false;
+                break;
+            }
+    r->symmetric = sym;
+    if (request_bytes(r->ld, r->bf16, r->symmetric) > (size_t)srv->cfg.budget_bytes) {
+        delete r;
+        return DPT_ENOMEM;
+    }
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stop || srv->error != DPT_OK) {
+            delete r;
+            return srv->error != DPT_OK ? srv->error : DPT_ESTATE;
+        }
+        r->id = srv->next_id++;
+        r->t_submit = now_s(srv->t0);
+        srv->pending.push_back(r);
+        srv->live[r->id] = 1;
+        srv->st.submitted += 1;
+        srv->st.pending = (int64_t)srv->pending.size();
+        *ticket = r->id;
+    }
+    srv->cv_work.notify_one();
+    return DPT_OK;
+}
+
+int dpt_serve_poll(dpt_server srv, int64_t ticket, int wait_ms, dpt_result *res, double *E, void *Z, int z_dtype,
+                   dpt_serve_times *t) {
+    if (!srv) return DPT_EINVAL;
+    if (Z && z_dtype != DPT_DTYPE_F32 && z_dtype != DPT_DTYPE_F64) return DPT_EINVAL;
+    Request *r = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(srv->mu);
+        if (!srv->live.count(ticket)) return DPT_EINVAL;
+        auto ready = [&] { return srv->done.count(ticket) != 0; };
+        if (!ready() && wait_ms != 0) {
+            if (wait_ms < 0)
+                srv->cv_done.wait(lk, ready);
+            else
+                srv->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), ready);
+        }
+        auto it = srv->done.find(ticket);
+        if (it == srv->done.end()) return DPT_EAGAIN;
+        r = it->second;
+        srv->done.erase(it);
+        srv->live.erase(ticket);
+    }
+    const int status = r->status;
+    r->ctl.fill(res);
+    if (res) res->status = status;
+    if (status >= 0) {
+        if (E) std::memcpy(E, r->E.data(), r->E.size() * 8);
+        if (Z && r->want_z) {
+            if (z_dtype == DPT_DTYPE_F32) {
+                std::memcpy(Z, r->Z.data(), r->Z.size() * 4);
+            } else {
+                double *zd = (double *)Z;
+                for (size_t i = 0; i < r->Z.size(); ++i) zd[i] = r->Z[i];
+            }
+        }
+    }
+    if (t) {
+        t->submit_s = r->t_submit;
+        t->admit_s = r->t_admit;
+        t->first_step_s = r->t_first;
+        t->finish_s = r->t_finish;
+    }
+    delete r;
+    return status;
+}
+
+int dpt_serve_stats_read(dpt_server srv, dpt_serve_stats *out) {
+    if (!srv || !out) return DPT_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->st;
+    return DPT_OK;
+}
+
+void dpt_serve_close(dpt_server srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    if (srv->worker.joinable()) srv->worker.join();
+    (void)hipStreamSynchronize(srv->stream);
+    delete srv;
+}
+
+}  // extern "C"

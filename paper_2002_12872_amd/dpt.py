@@ -83,6 +83,23 @@ class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * DPT_PROF_KINDS), ("launches", ctypes.c_int64 * DPT_PROF_KINDS)]
 
 
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class ServeTimes(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("first_step_s", ctypes.c_double), ("finish_s", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("peak_active", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("active", ctypes.c_int64), ("pending", ctypes.c_int64), ("busy_s", ctypes.c_double)]
+
+
 _FUNCS = {
     "dpt_options_default": (None, [ctypes.POINTER(Options)]),
     "dpt_validate": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options)]),
@@ -98,6 +115,14 @@ _FUNCS = {
                                     ctypes.POINTER(Result)]),
     "dpt_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "dpt_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Profile)]),
+    "dpt_serve_open": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ServeConfig)]),
+    "dpt_serve_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                        ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
+    "dpt_serve_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Result),
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.POINTER(ServeTimes)]),
+    "dpt_serve_stats_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServeStats)]),
+    "dpt_serve_close": (None, [ctypes.c_void_p]),
     "dpt_destroy": (None, [ctypes.c_void_p]),
     "dpt_status_str": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -364,3 +389,73 @@ def dpt_destroy(h: Handle) -> None:
     if h.ptr:
         load_library().dpt_destroy(h.ptr)
         h.ptr = None
+
+
+# ------------------------------------------------------------------ serving
+class Server:
+    """Handle of a serving engine (continuous batching); remembers each ticket's order."""
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+        self.tickets = {}
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.dpt_serve_close(self.ptr)
+            self.ptr = None
+
+
+def dpt_serve_open(budget_bytes, max_slots=256, use_graph=True, grid_blocks=0) -> Server:
+    cfg = ServeConfig(int(budget_bytes), int(max_slots), int(bool(use_graph)), int(grid_blocks), 0)
+    h = ctypes.c_void_p()
+    rc = load_library().dpt_serve_open(ctypes.byref(h), ctypes.byref(cfg))
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_serve_open")
+    return Server(h.value)
+
+
+def dpt_serve_submit(srv: Server, problem: ProblemSpec, opts: Options = None,
+                     want_eigenvectors: bool = False) -> int:
+    t = ctypes.c_int64()
+    rc = load_library().dpt_serve_submit(srv.ptr, ctypes.byref(problem.struct),
+                                         ctypes.byref(opts) if opts is not None else None,
+                                         int(bool(want_eigenvectors)), ctypes.byref(t))
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_serve_submit")
+    srv.tickets[t.value] = (int(problem.struct.n), bool(want_eigenvectors))
+    return t.value
+
+
+def dpt_serve_poll(srv: Server, ticket: int, wait_ms: int = 0):
+    """None while pending; else dict(status, iters..., E, Z (or None), times)."""
+    n, want_z = srv.tickets[ticket]
+    e = np.empty(n, np.float64)
+    z = np.empty((n, n), np.float64) if want_z else None
+    r = Result()
+    times = ServeTimes()
+    rc = load_library().dpt_serve_poll(srv.ptr, int(ticket), int(wait_ms), ctypes.byref(r), e.ctypes.data,
+                                       z.ctypes.data if z is not None else None, DPT_DTYPE_F64,
+                                       ctypes.byref(times))
+    if rc == DPT_EAGAIN:
+        return None
+    del srv.tickets[ticket]
+    if rc < 0:
+        raise DptError(rc, "dpt_serve_poll")
+    return {"status": rc, "iters": r.iters, "iters_bf16": r.iters_bf16, "iters_fp32": r.iters_fp32,
+            "last_delta": r.last_delta, "E": e, "Z": z,
+            "times": {"submit": times.submit_s, "admit": times.admit_s,
+                      "first_step": times.first_step_s, "finish": times.finish_s}}
+
+
+def dpt_serve_stats_read(srv: Server) -> dict:
+    st = ServeStats()
+    rc = load_library().dpt_serve_stats_read(srv.ptr, ctypes.byref(st))
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_serve_stats_read")
+    return {k: getattr(st, k) for k, _ in ServeStats._fields_}
+
+
+def dpt_serve_close(srv: Server) -> None:
+    if srv.ptr:
+        load_library().dpt_serve_close(srv.ptr)
+        srv.ptr = None

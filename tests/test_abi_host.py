@@ -37,11 +37,10 @@ def test_library_exports_every_declared_function():
 
 def test_struct_layout_matches_header(tmp_path):
     probe = tmp_path / "probe.c"
-    fields = {
-        "dpt_problem": [f[0] for f in dpt.Problem._fields_],
-        "dpt_options": [f[0] for f in dpt.Options._fields_],
-        "dpt_result": [f[0] for f in dpt.Result._fields_],
-    }
+    classes = {"dpt_problem": dpt.Problem, "dpt_options": dpt.Options, "dpt_result": dpt.Result,
+               "dpt_profile": dpt.Profile, "dpt_serve_config": dpt.ServeConfig,
+               "dpt_serve_times": dpt.ServeTimes, "dpt_serve_stats": dpt.ServeStats}
+    fields = {k: [f[0] for f in c._fields_] for k, c in classes.items()}
     cname = {"lam": "lambda"}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dpt.h"', "int main(void){"]
     for st, fs in fields.items():
@@ -54,7 +53,7 @@ def test_struct_layout_matches_header(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(probe)], check=True)
     out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                       check=True).stdout.splitlines())
-    for st, cls in (("dpt_problem", dpt.Problem), ("dpt_options", dpt.Options), ("dpt_result", dpt.Result)):
+    for st, cls in classes.items():
         assert int(out[st]) == ctypes.sizeof(cls), st
         for f in fields[st]:
             assert int(out["%s.%s" % (st, f)]) == getattr(cls, f).offset, (st, f)

@@ -1,0 +1,141 @@
+"""Serving engine: continuous batching of uneven-size problems (C ABI through the binding).
+
+Every problem in a step is computed with the same 64x64 tiles and its own
+statistics, so a problem's result must not depend on the batch it shares:
+alone and in a mix the results are bitwise equal.  Each result is also checked
+against the FP64 oracle at the FP32 target (1e-5).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from helpers import rel_eig_error
+
+pytestmark = pytest.mark.gpu
+
+dpt = pytest.importorskip("paper_2002_12872_amd.dpt")
+
+OPTS = dict(tol=1e-5, max_iter=100, precision=2)
+
+
+def request(n, symmetric, seed):
+    return workloads.serving_request(np.random.default_rng(seed), n, symmetric)
+
+
+def run_all(srv, probs, want_z=True, opts=None):
+    o = dpt.options(**(opts or OPTS))
+    tickets = [dpt.dpt_serve_submit(srv, dpt.ProblemSpec(th, de, 1.0, stream=0), o, want_z) for th, de in probs]
+    return [dpt.dpt_serve_poll(srv, t, wait_ms=-1) for t in tickets]
+
+
+MIX = [(37, True, 1), (64, False, 2), (100, True, 3), (129, False, 4), (200, True, 5), (257, False, 6),
+       (33, False, 7), (311, True, 8), (64, True, 9), (500, False, 10)]
+
+
+def test_results_are_batch_invariant_and_match_oracle():
+    probs = [request(*m) for m in MIX]
+    srv = dpt.dpt_serve_open(4 << 30, max_slots=64)
+    target = 5
+    alone = run_all(srv, [probs[target]])[0]
+    mixed = run_all(srv, probs)
+    dpt.dpt_serve_close(srv)
+    assert alone["status"] == dpt.DPT_OK
+    assert np.array_equal(alone["E"], mixed[target]["E"])
+    assert np.array_equal(alone["Z"], mixed[target]["Z"])
+    assert alone["iters"] == mixed[target]["iters"]
+    for (th, de), res in zip(probs, mixed):
+        assert res["status"] == dpt.DPT_OK
+        assert res["iters_bf16"] >= 1 and res["iters_fp32"] >= 1
+        ref = oracle.iterate(th, de.astype(np.float64), 1.0, max_iter=200, tol=1e-14)
+        assert rel_eig_error(res["E"], ref["e"], th) <= 1e-5
+        assert np.max(np.abs(res["Z"] - ref["z"])) <= 1e-5 * max(1.0, np.abs(ref["z"]).max())
+
+
+def test_graph_and_direct_launches_agree():
+    probs = [request(*m) for m in MIX[:6]]
+    a = dpt.dpt_serve_open(2 << 30, max_slots=16, use_graph=True)
+    ra = run_all(a, probs)
+    dpt.dpt_serve_close(a)
+    b = dpt.dpt_serve_open(2 << 30, max_slots=16, use_graph=False)
+    rb = run_all(b, probs)
+    dpt.dpt_serve_close(b)
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x["E"], y["E"]) and np.array_equal(x["Z"], y["Z"])
+
+
+def test_matches_single_problem_solver():
+    th, de = request(300, False, 11)
+    srv = dpt.dpt_serve_open(1 << 30, max_slots=4)
+    res = run_all(srv, [(th, de)])[0]
+    dpt.dpt_serve_close(srv)
+    h = dpt.dpt_init(dpt.ProblemSpec(th, de, 1.0, stream=0), dpt.options(**OPTS))
+    r = dpt.dpt_solve(h)
+    e = dpt.dpt_eigenvalues(h)
+    assert abs(r["iters"] - res["iters"]) <= 1
+    assert rel_eig_error(res["E"], e, th) <= 1e-6
+
+
+def test_budget_limits_concurrency_and_everything_completes():
+    probs = [request(256, True, 20 + i) for i in range(6)]
+    one = 3 * 256 * 8 + 2 * 256 * 256 * 4 + 256 * 256 * 4 + 3 * 256 * 256 * 2   # BF16, symmetric
+    srv = dpt.dpt_serve_open(2 * one + 4096, max_slots=64)
+    res = run_all(srv, probs, want_z=False)
+    st = dpt.dpt_serve_stats_read(srv)
+    dpt.dpt_serve_close(srv)
+    assert all(r["status"] == dpt.DPT_OK for r in res)
+    assert st["peak_active"] == 2 and st["completed"] == 6
+    # FIFO admission: a later problem is never admitted before an earlier one
+    admits = [r["times"]["admit"] for r in res]
+    assert admits == sorted(admits)
+
+
+def test_per_problem_statuses_in_a_mix():
+    theta2, delta2 = workloads.two_by_two()
+    good = [request(80, True, 30), request(150, False, 31)]
+    nan_th, nan_de = request(60, False, 32)
+    nan_de = nan_de.copy()
+    nan_de[5, 9] = np.nan
+    srv = dpt.dpt_serve_open(1 << 30, max_slots=16)
+    o = dpt.options(**OPTS)
+    o_cap = dpt.options(tol=1e-9, max_iter=40, precision=1)
+    t = [dpt.dpt_serve_submit(srv, dpt.ProblemSpec(theta2, delta2.astype(np.float32), 3.0, stream=0), o),
+         dpt.dpt_serve_submit(srv, dpt.ProblemSpec(theta2, delta2.astype(np.float32), 0.9, stream=0), o_cap),
+         dpt.dpt_serve_submit(srv, dpt.ProblemSpec(nan_th, nan_de, 1.0, stream=0), o)]
+    t += [dpt.dpt_serve_submit(srv, dpt.ProblemSpec(th, de, 1.0, stream=0), o) for th, de in good]
+    res = [dpt.dpt_serve_poll(srv, x, wait_ms=-1) for x in t]
+    dpt.dpt_serve_close(srv)
+    assert res[0]["status"] == dpt.DPT_DIVERGED                     # 2x2 beyond the domain
+    assert res[1]["status"] == dpt.DPT_NOT_CONVERGED and res[1]["iters"] == 40   # 2-cycle
+    assert res[2]["status"] == dpt.DPT_DIVERGED                     # NaN in Delta
+    assert res[3]["status"] == dpt.DPT_OK and res[4]["status"] == dpt.DPT_OK
+    assert res[0]["iters"] < 40
+
+
+def test_submit_rejects_bad_problems():
+    srv = dpt.dpt_serve_open(64 << 20, max_slots=4)
+    th, de = request(64, True, 40)
+    bad_theta = th.copy()
+    bad_theta[3] = bad_theta[4]
+    with pytest.raises(dpt.DptError) as ei:
+        dpt.dpt_serve_submit(srv, dpt.ProblemSpec(bad_theta, de, 1.0, stream=0), dpt.options(**OPTS))
+    assert ei.value.code == dpt.DPT_EINVAL
+    big_th, big_de = request(2048, False, 41)
+    with pytest.raises(dpt.DptError) as ei:
+        dpt.dpt_serve_submit(srv, dpt.ProblemSpec(big_th, big_de, 1.0, stream=0), dpt.options(**OPTS))
+    assert ei.value.code == dpt.DPT_ENOMEM
+    with pytest.raises(dpt.DptError):
+        dpt.dpt_serve_submit(srv, dpt.ProblemSpec(th, de, 1.0, stream=0), dpt.options(precision=0))
+    t = dpt.dpt_serve_submit(srv, dpt.ProblemSpec(th, de, 1.0, stream=0), dpt.options(**OPTS))
+    assert dpt.dpt_serve_poll(srv, t, wait_ms=-1)["status"] == dpt.DPT_OK
+    dpt.dpt_serve_close(srv)
+
+
+def test_zero_iterations_retire_without_a_step():
+    th, de = request(40, True, 50)
+    srv = dpt.dpt_serve_open(64 << 20, max_slots=4)
+    res = run_all(srv, [(th, de)], opts=dict(tol=1e-5, max_iter=0, precision=2))[0]
+    dpt.dpt_serve_close(srv)
+    assert res["status"] == dpt.DPT_NOT_CONVERGED and res["iters"] == 0
+    assert np.array_equal(res["Z"], np.eye(40))
+    assert np.allclose(res["E"], th, rtol=0, atol=1e-12)
