@@ -418,17 +418,6 @@ struct dpt_server_ctx {
                 std::unique_lock<std::mutex> lk(mu);
                 if (stop) break;
             }
-            if (active.empty()) {
-                std::unique_lock<std::mutex> lk(mu);
-                if (!pending.empty() && free_slots.size() == (size_t)cfg.max_slots) {
-                    // the head problem cannot be admitted even into an empty arena
-                    Request *r = pending.front();
-                    pending.pop_front();
-                    r->status = DPT_ENOMEM;
-                    done[r->id] = r;
-                    cv_done.notify_all();
-                }
-            }
         }
     }
 };
