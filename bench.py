@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="serving trace length (0 skips the serving measurement)")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--skip-secondary", action="store_true",
+                    help="skip the small/unsymmetric/sparse configuration lines")
     return ap.parse_args()
 
 
@@ -101,28 +103,129 @@ def serving_bench(args):
             "p50_ms": round(1e3 * percentile(lat_base, 50), 3),
             "p99_ms": round(1e3 * percentile(lat_base, 99), 3),
             "mean_service_ms": round(1e3 * svc.mean(), 3), "converged": int(ok)}
-    # engine in real time on the same arrivals
-    srv = dpt.dpt_serve_open(int(args.serve_budget_gib * (1 << 30)), max_slots=1024, use_graph=True)
-    tickets = []
-    t0 = time.perf_counter()
-    for i, sp in enumerate(specs):
-        delay = arrivals[i] - (time.perf_counter() - t0)
-        if delay > 0:
-            time.sleep(delay)
-        tickets.append(dpt.dpt_serve_submit(srv, sp, o_mixed))
-    res = [dpt.dpt_serve_poll(srv, t, wait_ms=-1) for t in tickets]
-    st = dpt.dpt_serve_stats_read(srv)
-    dpt.dpt_serve_close(srv)
-    lat = np.array([r["times"]["finish"] - r["times"]["submit"] for r in res])
-    span = max(r["times"]["finish"] for r in res) - min(r["times"]["submit"] for r in res)
-    eng = {"solves_per_s": round(count / span, 2), "p50_ms": round(1e3 * percentile(lat, 50), 3),
-           "p99_ms": round(1e3 * percentile(lat, 99), 3),
-           "converged": int(sum(r["status"] == dpt.DPT_OK for r in res)),
-           "steps": st["steps"], "peak_active": st["peak_active"],
-           "peak_arena_gib": round(st["peak_bytes"] / 2 ** 30, 3)}
+    def engine_run(arr):
+        """Engine in real time on the arrival times arr (None: all at t = 0)."""
+        srv = dpt.dpt_serve_open(int(args.serve_budget_gib * (1 << 30)), max_slots=1024, use_graph=True)
+        tickets = []
+        t0 = time.perf_counter()
+        for i, sp in enumerate(specs):
+            if arr is not None:
+                delay = arr[i] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(dpt.dpt_serve_submit(srv, sp, o_mixed))
+        res = [dpt.dpt_serve_poll(srv, t, wait_ms=-1) for t in tickets]
+        st = dpt.dpt_serve_stats_read(srv)
+        dpt.dpt_serve_close(srv)
+        lat = np.array([r["times"]["finish"] - r["times"]["submit"] for r in res])
+        span = max(r["times"]["finish"] for r in res) - min(r["times"]["submit"] for r in res)
+        return {"solves_per_s": round(count / span, 2), "p50_ms": round(1e3 * percentile(lat, 50), 3),
+                "p99_ms": round(1e3 * percentile(lat, 99), 3),
+                "converged": int(sum(r["status"] == dpt.DPT_OK for r in res)),
+                "steps": st["steps"], "peak_active": st["peak_active"],
+                "peak_arena_gib": round(st["peak_bytes"] / 2 ** 30, 3)}
+
+    def base_at(rate_mult):
+        arr = arrivals / rate_mult
+        fin = np.empty(count)
+        prev = 0.0
+        for i in range(count):
+            prev = max(arr[i], prev) + svc[i]
+            fin[i] = prev
+        lat_b = fin - arr
+        return {"solves_per_s": round(count / (fin[-1] - arr[0]), 2),
+                "p50_ms": round(1e3 * percentile(lat_b, 50), 3), "p99_ms": round(1e3 * percentile(lat_b, 99), 3)}
+
+    eng = engine_run(arrivals)
+    eng2 = engine_run(arrivals / 2.0)
+    burst = engine_run(None)
+    base2 = base_at(2.0)
     return {"requests": count, "arrival_rate_per_s": round(mu1, 2), "tol": 1e-5,
             "engine_bf16_fp32": eng, "one_at_a_time_fp32": base,
-            "p99_speedup": round(base["p99_ms"] / eng["p99_ms"], 2)}
+            "p99_speedup": round(base["p99_ms"] / eng["p99_ms"], 2),
+            "at_2x_rate": {"engine_bf16_fp32": eng2, "one_at_a_time_fp32": base2},
+            "burst_all_at_t0": {"engine_solves_per_s": burst["solves_per_s"],
+                                "one_at_a_time_solves_per_s": round(mu1, 2),
+                                "engine_p99_ms": burst["p99_ms"], "peak_active": burst["peak_active"]}}
+
+
+def secondary_bench(args):
+    """The other measured configurations, one line each (not the headline)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2002_12872_amd import dpt
+    out = {}
+    # small dense symmetric FP64, N = 64, to max|dZ| < 1e-12
+    th, de = workloads.dense_sym_small(0)
+    spec = dpt.ProblemSpec(torch.from_numpy(th).cuda(), torch.from_numpy(de).cuda(), 1.0)
+    o = dpt.options(tol=1e-12, max_iter=200, precision=dpt.DPT_FP64)
+    for _ in range(3):
+        dpt.dpt_destroy(dpt.dpt_init(spec, o))
+    t = time.perf_counter()
+    reps = 50
+    for _ in range(reps):
+        h = dpt.dpt_init(spec, o)
+        r = dpt.dpt_solve(h, history_cap=0)
+        dpt.dpt_eigenvalues(h)
+        dpt.dpt_destroy(h)
+    out["dense_sym_n64_fp64"] = {"us_per_solve": round(1e6 * (time.perf_counter() - t) / reps, 1),
+                                 "iters": r["iters"], "status": r["status"]}
+    # dense unsymmetric FP32, N = 4096, 30 steps
+    n = 4096
+    th, de = workloads.dense_unsym(0, n=n)
+    spec = dpt.ProblemSpec(torch.from_numpy(th).cuda(), torch.from_numpy(de).cuda(), 1.0)
+    h = dpt.dpt_init(spec, dpt.options(precision=dpt.DPT_FP32))
+    dpt.dpt_step(h, 2)
+    dpt.dpt_profile_enable(h, True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    dpt.dpt_step(h, 30)
+    el = time.perf_counter() - t
+    pr = dpt.dpt_profile_read(h)
+    gms = pr["gemm_fp32"][0] / pr["gemm_fp32"][1]
+    out["dense_unsym_n4096_fp32"] = {"iter_s": round(30 / el, 2), "ms_per_step": round(1e3 * el / 30, 3),
+                                     "gemm_fp32_ms": round(gms, 4),
+                                     "gemm_tflops": round(2.0 * n ** 3 / (gms * 1e-3) / 1e12, 2),
+                                     "frac_fp32_peak": round(2.0 * n ** 3 / (gms * 1e-3) / 1e12 / 157.3, 3)}
+    dpt.dpt_destroy(h)
+    # sparse symmetric N = 32768: SpMM full update and dominant eigenvector
+    n = 32768
+    th, ip, ix, v = workloads.sparse_sym(0, n=n)
+    csr = (torch.from_numpy(ip).cuda(), torch.from_numpy(ix).cuda(), torch.from_numpy(v).cuda())
+    spec = dpt.ProblemSpec(torch.from_numpy(th).cuda(), csr, 1.0)
+    h = dpt.dpt_init(spec, dpt.options(precision=dpt.DPT_FP32))
+    dpt.dpt_step(h, 4)                                   # the state is dense after a few steps
+    dpt.dpt_profile_enable(h, True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    dpt.dpt_step(h, 20)
+    el = time.perf_counter() - t
+    pr = dpt.dpt_profile_read(h)
+    sms = pr["spmm"][0] / pr["spmm"][1]
+    nnz = int(v.shape[0])
+    step_bytes = 2 * 4 * n * n + 8 * nnz + 4 * (n + 1)   # Z in + Z' out + CSR
+    gather = 4 * nnz * n
+    out["sparse_sym_n32768_spmm_fp32"] = {
+        "nnz": nnz, "ms_per_step": round(1e3 * el / 20, 3), "spmm_ms": round(sms, 4),
+        "hbm_gbs": round(step_bytes / (sms * 1e-3) / 1e9, 1),
+        "frac_hbm_peak": round(step_bytes / (sms * 1e-3) / 1e9 / PEAK_HBM_GBS, 3),
+        "l2_gather_gbs": round(gather / (sms * 1e-3) / 1e9, 1),
+        "algorithmic_bytes_per_step": step_bytes}
+    dpt.dpt_destroy(h)
+    o = dpt.options(tol=1e-6, max_iter=50, precision=dpt.DPT_FP32)
+    for _ in range(3):
+        dpt.dpt_dominant(spec, o)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        ev, vec, r = dpt.dpt_dominant(spec, o)
+    torch.cuda.synchronize()
+    out["sparse_sym_n32768_dominant_fp32"] = {"us_per_solve": round(1e6 * (time.perf_counter() - t) / reps, 1),
+                                              "iters": r["iters"], "eigenvalue": ev}
+    return out
 
 
 def kernel_only(args):
@@ -330,6 +433,9 @@ def main():
     if args.serve_requests > 0:
         print("# serving trace of %d requests" % args.serve_requests, file=sys.stderr, flush=True)
         out["serving"] = serving_bench(args)
+    if not args.skip_secondary:
+        print("# secondary configurations", file=sys.stderr, flush=True)
+        out["secondary"] = secondary_bench(args)
     print(json.dumps(out), flush=True)
 
 
