@@ -105,7 +105,19 @@ typedef struct dpt_options {
     int32_t precision;      /* DPT_FP64, DPT_FP32 or DPT_BF16_FP32                         */
     int32_t stall_patience; /* ... for this many consecutive checks (>= 1), or delta_k = 0 */
     int32_t check_every;    /* read delta back every this many steps (>= 1)                */
+    int32_t stop_rule;      /* DPT_STOP_DELTA (default) or DPT_STOP_ESTIMATE               */
+    int32_t reserved;       /* must be 0                                                  */
 } dpt_options;
+
+/* Stopping rules.  DPT_STOP_DELTA: converged when delta_k < tol.
+ * DPT_STOP_ESTIMATE: converged when the a-posteriori bound of a contraction,
+ * rho * delta_k / (1 - rho), is below tol, with rho the larger of the last two
+ * step ratios delta_j / delta_{j-1} measured inside one precision phase (the
+ * ratios of the BF16 phase carry over to the first FP32 sweep, whose own delta
+ * measures the correction of the BF16 bias).  Without two ratios below 0.5 it
+ * falls back to delta_k < tol. */
+#define DPT_STOP_DELTA 0
+#define DPT_STOP_ESTIMATE 1
 
 typedef struct dpt_result {
     double last_delta;      /* delta_k of the last application of F (NaN if none)          */
@@ -119,7 +131,7 @@ typedef struct dpt_result {
 } dpt_result;
 
 /* Fill *o with defaults: tol 1e-6, max_iter 200, DPT_FP32, fp64_final_tol 0,
- * stall_ratio 0.5, stall_patience 2, check_every 1, blowup 1e6. */
+ * stall_ratio 0.5, stall_patience 2, check_every 1, blowup 1e6, DPT_STOP_DELTA. */
 void dpt_options_default(dpt_options *o);
 
 /* Host-only argument check (no device call): pointer/size/enum sanity and, for

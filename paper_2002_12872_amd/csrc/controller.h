@@ -1,8 +1,9 @@
 // Step control shared by dpt_solve and the serving engine: precision phases,
 // stopping rule and statuses (host code).
 //
-// delta_k = max |Z_k - Z_{k-1}| after the k-th application of the map.  The
-// BF16 phase runs until delta_k < tol or a stall and then always hands over to
+// delta_k = max |Z_k - Z_{k-1}| after the k-th application of the map, compared
+// with tol directly or through the contraction bound (DPT_STOP_ESTIMATE).  The
+// BF16 phase runs until that test passes or a stall and then always hands over to
 // FP32 sweeps (its fixed point is biased by the BF16 product); FP32 ends with
 // OK when delta_k < tol, optionally followed by FP64 sweeps to fp64_final_tol.
 // A stall is a rounding floor: no progress by stall_ratio for stall_patience
@@ -31,6 +32,17 @@ struct Controller {
     double best = std::numeric_limits<double>::infinity();
     int stall_run = 0;
     double last = std::numeric_limits<double>::quiet_NaN();
+    // step ratios delta_k / delta_{k-1} inside one phase (r1 the most recent)
+    double prev = std::numeric_limits<double>::quiet_NaN();
+    double r1 = std::numeric_limits<double>::quiet_NaN(), r2 = std::numeric_limits<double>::quiet_NaN();
+
+    // Distance-to-fixed-point proxy compared with tol.
+    double error_measure(double dl) const {
+        if (o.stop_rule != DPT_STOP_ESTIMATE || dl == 0.0) return dl;
+        if (!(r1 < 0.5) || !(r2 < 0.5)) return dl;  // contraction not established: delta rule
+        const double rho = std::max(r1, r2);
+        return rho * dl / (1.0 - rho);
+    }
 
     void start(const dpt_options &opt, int initial_phase, bool fp64_allowed) {
         o = opt;
@@ -55,6 +67,12 @@ struct Controller {
             status = DPT_DIVERGED;
             return DONE;
         }
+        if (prev > 0.0 && std::isfinite(prev)) {
+            r2 = r1;
+            r1 = dl / prev;
+        }
+        prev = dl;
+        const double err = error_measure(dl);
         bool stalled = false;
         if (dl == 0.0) {
             stalled = true;
@@ -65,13 +83,13 @@ struct Controller {
         }
         best = std::min(best, dl);
         if (phase == PH_BF16) {
-            if (dl < o.tol || stalled) {
+            if (err < o.tol || stalled) {
                 phase = PH_FP32;
                 reset_progress();
                 return TO_FP32;
             }
         } else if (phase == PH_FP32) {
-            if (dl < o.tol) {
+            if (err < o.tol) {
                 if (o.fp64_final_tol > 0.0 && allow_fp64) {
                     phase = PH_FP64;
                     reset_progress();
@@ -86,7 +104,7 @@ struct Controller {
             }
         } else {
             const double target = (o.precision == DPT_FP64) ? o.tol : o.fp64_final_tol;
-            if (dl < target) {
+            if (err < target) {
                 status = DPT_OK;
                 return DONE;
             }
@@ -109,9 +127,13 @@ struct Controller {
     }
 
   private:
+    // New phase: restart stall tracking; the next delta measures the change of
+    // fixed point (rounding bias), not contraction, so no ratio is formed with it
+    // while the previous phase's ratios stay as the contraction estimate.
     void reset_progress() {
         best = std::numeric_limits<double>::infinity();
         stall_run = 0;
+        prev = std::numeric_limits<double>::quiet_NaN();
     }
 };
 

@@ -58,6 +58,8 @@ bool valid_options(const dpt_options *o) {
     if (!(o->stall_ratio >= 0.0) || !(o->stall_ratio <= 1.0)) return false;
     if (o->stall_patience < 1 || o->check_every < 1) return false;
     if (!(o->blowup > 0.0)) return false;
+    if (o->stop_rule != DPT_STOP_DELTA && o->stop_rule != DPT_STOP_ESTIMATE) return false;
+    if (o->reserved != 0) return false;
     return true;
 }
 
@@ -518,6 +520,8 @@ void dpt_options_default(dpt_options *o) {
     o->precision = DPT_FP32;
     o->stall_patience = 2;
     o->check_every = 1;
+    o->stop_rule = DPT_STOP_DELTA;
+    o->reserved = 0;
 }
 
 int dpt_validate(const dpt_problem *p, const dpt_options *o) {

@@ -24,6 +24,7 @@ DPT_FP64, DPT_FP32, DPT_BF16_FP32 = 0, 1, 2
 DPT_DENSE, DPT_CSR = 0, 1
 DPT_MEM_HOST, DPT_MEM_DEVICE = 0, 1
 DPT_DTYPE_F64, DPT_DTYPE_F32 = 0, 1
+DPT_STOP_DELTA, DPT_STOP_ESTIMATE = 0, 1
 
 
 class DptError(RuntimeError):
@@ -59,6 +60,8 @@ class Options(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("stall_patience", ctypes.c_int32),
         ("check_every", ctypes.c_int32),
+        ("stop_rule", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -243,12 +246,12 @@ class ProblemSpec:
 
 
 def options(tol=1e-6, max_iter=200, precision=DPT_FP32, fp64_final_tol=0.0, stall_ratio=0.5,
-            stall_patience=2, check_every=1, blowup=1e6):
+            stall_patience=2, check_every=1, blowup=1e6, stop_rule=DPT_STOP_DELTA):
     o = Options()
     load_library().dpt_options_default(ctypes.byref(o))
     o.tol, o.max_iter, o.precision = tol, max_iter, precision
     o.fp64_final_tol, o.stall_ratio, o.stall_patience = fp64_final_tol, stall_ratio, stall_patience
-    o.check_every, o.blowup = check_every, blowup
+    o.check_every, o.blowup, o.stop_rule = check_every, blowup, stop_rule
     return o
 
 

@@ -71,6 +71,7 @@ def test_options_default():
     assert o.tol == 1e-6 and o.max_iter == 200 and o.precision == dpt.DPT_FP32
     assert o.stall_ratio == 0.5 and o.stall_patience == 2 and o.check_every == 1
     assert o.blowup == 1e6 and o.fp64_final_tol == 0.0
+    assert o.stop_rule == dpt.DPT_STOP_DELTA and o.reserved == 0
 
 
 def _spec(n=4, theta=None, delta=None, lam=0.1):
@@ -136,7 +137,7 @@ def test_validate_rejects_bad_csr(bad):
 @pytest.mark.parametrize("field,value", [
     ("tol", 0.0), ("tol", -1.0), ("tol", float("nan")), ("max_iter", -1), ("precision", 5),
     ("fp64_final_tol", -1.0), ("stall_ratio", 1.5), ("stall_patience", 0), ("check_every", 0),
-    ("blowup", 0.0),
+    ("blowup", 0.0), ("stop_rule", 2), ("reserved", 1),
 ])
 def test_validate_rejects_bad_options(field, value):
     o = dpt.options()

@@ -272,3 +272,27 @@ def test_device_rejects_duplicate_theta():
     with pytest.raises(dpt.DptError) as ei:
         dpt.dpt_init(dpt.ProblemSpec(theta, delta, 0.1))
     assert ei.value.code == dpt.DPT_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("sym", [False, True])
+def test_estimate_stop_rule_certifies_accuracy_with_fewer_products(precision, sym):
+    n = 1100
+    theta, delta = small_problem(n, 13, symmetric=sym)
+    delta32 = delta.astype(np.float32)
+    prec = dpt.DPT_FP32 if precision == "fp32" else dpt.DPT_BF16_FP32
+    runs = {}
+    for rule in (dpt.DPT_STOP_DELTA, dpt.DPT_STOP_ESTIMATE):
+        spec = dpt.ProblemSpec(theta, delta32, 1.0, stream=0)
+        h = dpt.dpt_init(spec, dpt.options(tol=1e-6, max_iter=100, precision=prec, stop_rule=rule))
+        runs[rule] = (dpt.dpt_solve(h), dpt.dpt_eigenvalues(h), dpt.dpt_eigenvectors(h))
+    (rd, ed, zd), (re_, ee, ze) = runs[dpt.DPT_STOP_DELTA], runs[dpt.DPT_STOP_ESTIMATE]
+    assert rd["status"] == dpt.DPT_OK and re_["status"] == dpt.DPT_OK
+    assert re_["iters"] <= rd["iters"]
+    if precision == "bf16":
+        assert re_["iters_fp32"] >= 1
+    rows = workloads.sample_rows(n, 64)
+    ref = oracle.iterate(theta, delta32.astype(np.float64), 1.0, rows=rows, max_iter=200, tol=1e-14)
+    # the certified distance to the fixed point (tol) plus FP32 rounding of the state
+    assert np.max(np.abs(ze[rows] - ref["z"])) <= 1e-6 + 1e-6 * np.max(np.abs(ref["z"] - np.eye(n)[rows]))
+    assert rel_eig_error(ee[rows], ref["e"], theta) <= 1e-5
