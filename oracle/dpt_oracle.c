@@ -97,13 +97,28 @@ static int cmp_double(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
-static int validate(const or_problem *p)
+/* Number of entries equal to x in the ascending array a[0..n). */
+static int64_t count_equal(const double *a, int64_t n, double x)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) { /* first index with a[i] >= x */
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    int64_t c = 0;
+    while (lo + c < n && a[lo + c] == x) ++c;
+    return c;
+}
+
+static int validate(const or_problem *p, int64_t nrows, const int64_t *rows)
 {
     if (!p || p->n < 1 || !p->theta) return OR_EINVAL;
     if (!p->dense && !(p->indptr && p->indices && p->values)) return OR_EINVAL;
     if (!isfinite(p->lambda)) return OR_EINVAL;
-    /* The unperturbed eigenvalues must be simple (Sec. II.B): reject exact
-     * duplicates (sort a copy, compare neighbours). */
+    /* Each requested row n is iterated with its own single-line map, which
+     * divides by theta_n - theta_m for every m != n (Sec. II.B, Sec. II.H):
+     * theta_n must be simple.  Values of rows not requested may coincide.
+     * Sort a copy and count the occurrences of each requested theta_n. */
     double *sorted = (double *)malloc(sizeof(double) * (size_t)p->n);
     if (!sorted) return OR_ENOMEM;
     for (int64_t i = 0; i < p->n; ++i) {
@@ -114,8 +129,8 @@ static int validate(const or_problem *p)
         sorted[i] = p->theta[i];
     }
     qsort(sorted, (size_t)p->n, sizeof(double), cmp_double);
-    for (int64_t i = 1; i < p->n; ++i) {
-        if (sorted[i] == sorted[i - 1]) {
+    for (int64_t r = 0; r < nrows; ++r) {
+        if (rows[r] < 0 || rows[r] >= p->n || count_equal(sorted, p->n, p->theta[rows[r]]) != 1) {
             free(sorted);
             return OR_EINVAL;
         }
@@ -152,9 +167,9 @@ int or_iterate(const or_problem *p, int64_t nrows, const int64_t *rows, const do
                int max_iter, double tol, int fixed_steps, double blowup, int nthreads,
                double *z, double *e, double *delta_hist, int *iters)
 {
-    int rc = validate(p);
-    if (rc != OR_OK) return rc;
     if (nrows < 1 || !rows || !z || !e || !iters || max_iter < 0) return OR_EINVAL;
+    int rc = validate(p, nrows, rows);
+    if (rc != OR_OK) return rc;
     if (!fixed_steps && !(tol > 0.0)) return OR_EINVAL;
     const int64_t n = p->n;
     for (int64_t r = 0; r < nrows; ++r)

@@ -376,6 +376,27 @@ def test_rejects_degenerate_and_bad_inputs():
     assert r["e"][0] == 2.0 + 0.3 * 0.5 and r["z"][0, 0] == 1.0
 
 
+def test_degenerate_theta_away_from_requested_rows():
+    """Row n's single-line map divides only by theta_n - theta_m (Sec. II.H): a
+    repeated value elsewhere is accepted and the converged row is still an
+    eigenvector of M (checked by the plain eigen-equation); asking for one of
+    the repeated rows is rejected."""
+    n = 40
+    rng = np.random.default_rng(5)
+    theta = np.arange(n, dtype=np.float64)
+    theta[3] = theta[4]
+    delta = rng.normal(0.0, 0.05, (n, n))
+    delta = 0.5 * (delta + delta.T)
+    r = oracle.iterate(theta, delta, 1.0, rows=[n - 1, 20], max_iter=500, tol=1e-14)
+    assert r["status"] == 0
+    res, mz, zn = oracle.residual(theta, delta, 1.0, r["z"], r["e"])
+    assert np.max(res / mz) <= 1e-12
+    with pytest.raises(ValueError):
+        oracle.iterate(theta, delta, 1.0, rows=[3], max_iter=5, tol=1e-12)
+    with pytest.raises(ValueError):
+        oracle.iterate(theta, delta, 1.0, max_iter=5, tol=1e-12)
+
+
 # ---------------------------------------------------------------- planted mistakes
 MUTANTS = {
     "bracket_sign": ("(c[m] - cn * z[m])", "(cn * z[m] - c[m])"),
