@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--skip-secondary", action="store_true",
                     help="skip the small/unsymmetric/sparse configuration lines")
+    ap.add_argument("--secondary-only", action="store_true",
+                    help="run only the small/unsymmetric/sparse configuration lines")
     return ap.parse_args()
 
 
@@ -296,13 +298,16 @@ def solve_once(dpt, spec, opts, n, profile):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the D-PT hot path on a single "
-              "MI355X (no multi-GPU path); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the D-PT path runs on a single MI355X "
+              "(no multi-GPU path); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.kernel_only:
         return kernel_only(args)
     if args.copy_probe:
         return copy_probe(args)
+    if args.secondary_only:
+        print(json.dumps({"mode": "secondary-only", "secondary": secondary_bench(args)}), flush=True)
+        return
     import numpy as np
     import torch
 

@@ -144,9 +144,13 @@ int dpt_validate(const dpt_problem *p, const dpt_options *o);
  * z0 == NULL starts from A^(0) = I (Sec. II.B); otherwise z0 holds an n*n start
  * in the eigenvector layout above, same dtype and memory kind as the problem
  * (its diagonal is taken as 1: the chart z_k[k] = 1).  This warm start is the
- * paper's refinement of approximate eigenvectors (Sec. II.H, last paragraph).
- * Returns DPT_OK, or DPT_EINVAL (bad argument, duplicate theta), DPT_ENOMEM,
- * DPT_EDEVICE; *h is set only on success. */
+ * paper's refinement of approximate eigenvectors (Sec. II.H, last paragraph);
+ * dense problems only (z0 must be NULL for a CSR Delta).  A CSR Delta in device
+ * memory is structure-checked on the device (same rules as dpt_validate) and
+ * borrowed: row pointers and indices always, values when their dtype is the
+ * state's (FP64 for DPT_FP64, else FP32).
+ * Returns DPT_OK, or DPT_EINVAL (bad argument, duplicate theta, malformed CSR),
+ * DPT_ENOMEM, DPT_EDEVICE; *h is set only on success. */
 int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const void *z0);
 
 /* Apply F exactly nsteps (>= 0) times in the handle's current precision phase,
@@ -179,7 +183,11 @@ int dpt_residuals(dpt_handle h, int64_t nrows, const int64_t *rows, double *res)
  * selects argmax theta.  Uses o->tol, o->max_iter, o->blowup and o->precision
  * (DPT_FP64 -> FP64, otherwise FP32).  eigvec: n values of p->dtype in p->mem
  * (eigvec[index] = 1).  *eigval receives theta_index + lambda (Delta z)[index].
- * Returns the numerical status or an error. */
+ * Only theta_index has to be simple here (the map divides by theta_index -
+ * theta_m alone); other theta values may coincide.  A CSR Delta in device
+ * memory is checked on the device and borrowed for the call.  Returns the
+ * numerical status, or DPT_EINVAL (bad arguments, non-finite theta, theta_index
+ * repeated, malformed CSR), DPT_ENOMEM, DPT_EDEVICE. */
 int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval,
                  void *eigvec, dpt_result *r);
 

@@ -524,7 +524,10 @@ void dpt_options_default(dpt_options *o) {
     o->reserved = 0;
 }
 
-int dpt_validate(const dpt_problem *p, const dpt_options *o) {
+namespace {
+// Host-side argument checks; full = also the host-memory theta and CSR content
+// (the dominant mode checks those itself).
+int validate_args(const dpt_problem *p, const dpt_options *o, bool full) {
     if (!p || p->n < 1 || !p->theta || !p->delta) return DPT_EINVAL;
     if (p->format != DPT_DENSE && p->format != DPT_CSR) return DPT_EINVAL;
     if (p->dtype != DPT_DTYPE_F64 && p->dtype != DPT_DTYPE_F32) return DPT_EINVAL;
@@ -533,12 +536,15 @@ int dpt_validate(const dpt_problem *p, const dpt_options *o) {
     if (p->n > (int64_t)1 << 31) return DPT_EINVAL;
     if (p->format == DPT_CSR) {
         if (!p->indptr || !p->indices || p->nnz < 0 || p->nnz >= ((int64_t)1 << 31)) return DPT_EINVAL;
-        if (p->mem == DPT_MEM_HOST && !csr_ok(p->indptr, p->indices, p->n, p->nnz)) return DPT_EINVAL;
+        if (full && p->mem == DPT_MEM_HOST && !csr_ok(p->indptr, p->indices, p->n, p->nnz)) return DPT_EINVAL;
     }
-    if (p->mem == DPT_MEM_HOST && !theta_ok(p->theta, p->n)) return DPT_EINVAL;
+    if (full && p->mem == DPT_MEM_HOST && !theta_ok(p->theta, p->n)) return DPT_EINVAL;
     if (!valid_options(o)) return DPT_EINVAL;
     return DPT_OK;
 }
+}  // namespace
+
+int dpt_validate(const dpt_problem *p, const dpt_options *o) { return validate_args(p, o, true); }
 
 int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const void *z0) {
     if (!h) return DPT_EINVAL;
@@ -591,7 +597,7 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
         return fail(DPT_EDEVICE);
 
     if (p->format == DPT_CSR) {
-        rc = map_err(sparse_create(&c->sp, p, c->opt.precision == DPT_FP64, c->ld, c->stream));
+        rc = sparse_create(&c->sp, p, c->opt.precision == DPT_FP64, c->ld, c->stream);
         if (rc == DPT_OK && !c->sp) rc = DPT_ENOMEM;
         if (rc == DPT_OK) c->phase = c->opt.precision == DPT_FP64 ? PH_FP64 : PH_FP32;
     } else {
@@ -740,7 +746,7 @@ int dpt_residuals(dpt_handle h, int64_t nrows, const int64_t *rows, double *res)
 
 int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval, void *eigvec,
                  dpt_result *r) {
-    int rc = dpt_validate(p, o);
+    int rc = validate_args(p, o, false);  // the CSR content is checked where it is staged
     if (rc != DPT_OK) return rc;
     if (!eigval || !eigvec || index >= p->n) return DPT_EINVAL;
     rc = check_device();
@@ -756,11 +762,16 @@ int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, doub
     if (p->mem == DPT_MEM_DEVICE) {
         if (hipMemcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost) != hipSuccess)
             return DPT_EDEVICE;
-        if (!theta_ok(th.data(), p->n)) return DPT_EINVAL;
     } else {
         std::memcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n);
     }
+    for (double v : th)
+        if (!std::isfinite(v)) return DPT_EINVAL;
     if (index < 0) index = (int64_t)(std::max_element(th.begin(), th.end()) - th.begin());
+    // the single-line map divides only by theta_index - theta_m: theta_index must
+    // be simple, other values may coincide (Sec. II.H)
+    for (int64_t m = 0; m < p->n; ++m)
+        if (m != index && th[(size_t)m] == th[(size_t)index]) return DPT_EINVAL;
     return dominant_solve(p, &opt, th.data(), index, eigval, eigvec, r);
 }
 

@@ -12,12 +12,16 @@ namespace dpt {
 
 struct SparseState;
 
-// Padded order of the transposed sparse-path state (multiple of the SpMM panel).
+// Padded order of the transposed sparse-path state (a multiple of 64).
 int64_t sparse_pad_order(int64_t n);
 
-// Stage the CSR Delta of p (host or device) and allocate the transposed state
-// WT[m * ld + n] = W[n][m] (two buffers, FP32 or FP64).  *out is NULL on failure.
-hipError_t sparse_create(SparseState **out, const dpt_problem *p, bool fp64, int64_t ld, hipStream_t s);
+// Stage the CSR Delta of p and allocate the transposed state ZT (Z[n][m] at
+// panel-major offset, unit diagonal included; two buffers, FP32 or FP64, both
+// starting as the identity).  Device CSR arrays are checked on the device and
+// borrowed (values too when their dtype matches the state); host arrays are
+// checked on the host and copied.  Returns DPT_OK, DPT_EINVAL for a malformed
+// CSR, DPT_ENOMEM or DPT_EDEVICE; *out is NULL on failure.
+int sparse_create(SparseState **out, const dpt_problem *p, bool fp64, int64_t ld, hipStream_t s);
 void sparse_destroy(SparseState *sp);
 
 // One application of eq. (dyn) with the CSR product; stats go to ring slot *k

@@ -2,11 +2,17 @@
 //
 // Paper: Kenmoe, Smerlak, Zadorin, arXiv:2002.12872.
 //  * Full sparse solve: eq. (dyn) with a CSR Delta.  The state is stored
-//    transposed, WT[m][n] = W[n][m] (W = A - I), so that
-//        (A Delta')[n][m] = (Delta z_n)[m] = Delta[m][n] + sum_l Delta[m][l] WT[l][n]
-//    reads, for every non-zero Delta[m][l], one contiguous run WT[l][n0 .. n0+P)
+//    transposed and with its unit diagonal, ZT[m][n] = Z[n][m] = z_n[m], so that
+//        (A Delta')[n][m] = (Delta z_n)[m] = sum_l Delta[m][l] ZT[l][n]
+//    reads, for every non-zero Delta[m][l], one contiguous run ZT[l][n0 .. n0+P)
 //    covering P eigenvectors at once (coalesced gathers; the random sparsity
-//    offers no other reuse).
+//    offers no other reuse).  Off-diagonal entries of Z equal those of
+//    W = Z - I exactly, so storing Z loses nothing.
+//    Layout: panel-major.  The columns n of ZT are cut into panels of P, and each
+//    panel is one contiguous ld x P block (element (l, n) at
+//    (n / P) * ld * P + l * P + n % P), so the gathers of one panel stay inside a
+//    few MiB of address space (a handful of TLB pages) instead of striding
+//    through the whole ld x ld array.
 //  * Dominant mode (Sec. II.H): the single-line map F_{n*} of eq.
 //    (single_line_dyn) on one vector, z' = e + lambda g * (Delta z - (Delta z)[n*] z),
 //    one SpMV (or GEMV) per iteration; every block recomputes the scalar
@@ -27,7 +33,25 @@ namespace dpt {
 
 namespace {
 
-constexpr int kPanel = 256;  // eigenvectors per SpMM wave (4 per lane)
+// SpMM lane-group size: LANES lanes x 16 bytes form one gathered run, so the
+// panel width is P = LANES * 16 / sizeof(T) values.
+#ifndef DPT_SPMM_LANES
+#define DPT_SPMM_LANES 32
+#endif
+constexpr int kSpmmLanes = DPT_SPMM_LANES;
+static_assert(kSpmmLanes >= 1 && 64 % kSpmmLanes == 0, "lane groups tile a wave");
+
+// Padding of the sparse-path state: a multiple of the rows per SpMM block and of
+// the export tiles (64) and of the widest panel (FP32).
+constexpr int kPad = 4 * kSpmmLanes > 64 ? 4 * kSpmmLanes : 64;
+
+template <typename T>
+struct Panel {
+    static constexpr int64_t P = kSpmmLanes * 16 / (int64_t)sizeof(T);
+    static_assert(kPad % P == 0, "panels tile the padded order");
+    // offset of element (l, n) of the ld x ld state
+    __host__ __device__ static int64_t at(int64_t l, int64_t n, int64_t ld) { return (n / P) * (ld * P) + l * P + n % P; }
+};
 inline unsigned int blocks_for(int64_t items, int per_block, int64_t cap = 1 << 20) {
     int64_t b = (items + per_block - 1) / per_block;
     return (unsigned int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
@@ -35,37 +59,60 @@ inline unsigned int blocks_for(int64_t items, int per_block, int64_t cap = 1 << 
 
 // ------------------------------------------------------------------ kernels
 template <typename T>
-__global__ void k_sp_diag(const int *__restrict__ rowptr, const int *__restrict__ col, const T *__restrict__ val,
-                          int64_t n, double *__restrict__ diag) {
-    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x) {
-        double dv = 0.0;
-        for (int e = rowptr[m]; e < rowptr[m + 1]; ++e)
-            if (col[e] == m) dv = (double)val[e];
-        diag[m] = dv;
-    }
-}
-
-template <typename T>
 __global__ void k_zero(T *__restrict__ p, int64_t count) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = (T)0;
 }
 
-// F(I): WT_1[m][n] = lambda Delta[m][n] / (theta_n - theta_m) on the pattern of Delta.
+// Structural check of a CSR matrix in device memory (the host-side rules of
+// dpt_validate): rowptr[0] = 0, rowptr[n] = nnz, non-decreasing row pointers,
+// column indices in [0, n) and strictly increasing within a row.  Any violation
+// sets *bad.  Column indices of a row are read only once its pointers are known
+// to lie inside [0, nnz].
+__global__ void k_csr_validate(const int64_t *__restrict__ rowptr, const int *__restrict__ col, int64_t n,
+                               int64_t nnz, unsigned int *bad) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool err = false;
+    if (i == 0) err = rowptr[0] != 0 || rowptr[n] != nnz;
+    if (i < n) {
+        const int64_t a = rowptr[i], b = rowptr[i + 1];
+        if (a < 0 || b > nnz || b < a) {
+            err = true;
+        } else {
+            int prev = -1;
+            for (int64_t e = a; e < b; ++e) {
+                const int c = col[e];
+                err |= c <= prev || c >= n;
+                prev = c;
+            }
+        }
+    }
+    if (err) atomicOr(bad, 1u);
+}
+
+// ZT[m][m] = 1 for m < n (the buffers start as the identity; the steps keep it).
 template <typename T>
-__global__ __launch_bounds__(256) void k_sp_first_iterate(const int *__restrict__ rowptr, const int *__restrict__ col,
+__global__ void k_set_unit_diag(T *__restrict__ ZT, int64_t n, int64_t ld) {
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x)
+        ZT[Panel<T>::at(m, m, ld)] = (T)1;
+}
+
+// F(I): ZT_1[m][n] = lambda Delta[m][n] / (theta_n - theta_m) on the off-diagonal
+// pattern of Delta, written into a buffer that holds the identity.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sp_first_iterate(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
                                                           const T *__restrict__ val, int64_t n, int64_t ld,
                                                           double lambda, const double *__restrict__ theta,
-                                                          T *__restrict__ WT, unsigned long long *stat) {
+                                                          T *__restrict__ ZT, unsigned long long *stat) {
     double dmax = 0.0;
     bool bad = false;
     for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x) {
         const double tm = theta[m];
-        for (int e = rowptr[m]; e < rowptr[m + 1]; ++e) {
+        for (int64_t e = rowptr[m]; e < rowptr[m + 1]; ++e) {
             const int64_t c = col[e];
             if (c == m) continue;
             const T w = (T)(lambda * (double)val[e] / (theta[c] - tm));
-            WT[m * ld + c] = w;
+            ZT[Panel<T>::at(m, c, ld)] = w;
             const double v = fabs((double)w);
             dmax = fmax(dmax, v);
             bad |= !(v <= DBL_MAX);
@@ -74,12 +121,12 @@ __global__ __launch_bounds__(256) void k_sp_first_iterate(const int *__restrict_
     publish_stats(stat, dmax, dmax, bad);
 }
 
-// d_n = Delta[n][n] + sum_{l in row n} Delta[n][l] WT[l][n]  (FP64 accumulation).
+// d_n = sum_{l in row n} Delta[n][l] ZT[l][n] = (Delta z_n)[n]  (FP64 accumulation).
 template <typename T>
-__global__ void k_sp_prepass(const int *__restrict__ rowptr, const int *__restrict__ col, const T *__restrict__ val,
-                             const double *__restrict__ diag, int64_t n, int64_t ld, const T *__restrict__ WT,
-                             double lambda, const double *__restrict__ theta, double *__restrict__ d,
-                             double *__restrict__ E, unsigned long long *stat_clear) {
+__global__ void k_sp_prepass(const int64_t *__restrict__ rowptr, const int *__restrict__ col, const T *__restrict__ val,
+                             int64_t n, int64_t ld, const T *__restrict__ ZT, double lambda,
+                             const double *__restrict__ theta, double *__restrict__ d, double *__restrict__ E,
+                             unsigned long long *stat_clear) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i == 0 && stat_clear) {
         stat_clear[0] = 0ull;
@@ -87,121 +134,155 @@ __global__ void k_sp_prepass(const int *__restrict__ rowptr, const int *__restri
     }
     if (i >= n) return;
     double s = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) s += (double)val[e] * (double)WT[(int64_t)col[e] * ld + i];
-    const double dn = diag[i] + s;
-    d[i] = dn;
-    if (E) E[i] = theta[i] + lambda * dn;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) s += (double)val[e] * (double)ZT[Panel<T>::at(col[e], i, ld)];
+    d[i] = s;
+    if (E) E[i] = theta[i] + lambda * s;
 }
 
+// One 16-byte vector of T (4 floats or 2 doubles).
 template <typename T>
-struct Vec4;
+struct Vec16;
 template <>
-struct Vec4<float> {
-    __device__ static void load(const float *p, double o[4]) {
-        const float4 v = *reinterpret_cast<const float4 *>(p);
-        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-    }
-    __device__ static void store(float *p, const double o[4]) {
-        *reinterpret_cast<float4 *>(p) = make_float4((float)o[0], (float)o[1], (float)o[2], (float)o[3]);
-    }
+struct Vec16<float> {
+    typedef float4 type;
+    static constexpr int count = 4;
+    __device__ static float get(const float4 &v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+    __device__ static float4 make(const float *o) { return make_float4(o[0], o[1], o[2], o[3]); }
 };
 template <>
-struct Vec4<double> {
-    __device__ static void load(const double *p, double o[4]) {
-        const double2 a = *reinterpret_cast<const double2 *>(p), b = *reinterpret_cast<const double2 *>(p + 2);
-        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
-    }
-    __device__ static void store(double *p, const double o[4]) {
-        *reinterpret_cast<double2 *>(p) = make_double2(o[0], o[1]);
-        *reinterpret_cast<double2 *>(p + 2) = make_double2(o[2], o[3]);
-    }
+struct Vec16<double> {
+    typedef double2 type;
+    static constexpr int count = 2;
+    __device__ static double get(const double2 &v, int i) { return i == 0 ? v.x : v.y; }
+    __device__ static double2 make(const double *o) { return make_double2(o[0], o[1]); }
 };
 
-// One wave per (row m of Delta, panel of kPanel eigenvectors); 4 rows per block.
-// Blocks are dispatched round-robin over the 8 XCDs; the remap gives every XCD
-// a contiguous run of panels so its L2 holds the panel being gathered.
+// CSR product + update.  Lanes form groups of LANES; each group owns one row m
+// of Delta and each lane a 16-byte run of the panel of P = LANES * VEC
+// eigenvectors (VEC = values per 16 bytes).  A lane walks the non-zeros of its
+// own row, so a wave load instruction gathers 64 / LANES different rows l of the
+// panel and no cross-lane reduction is needed; groups whose rows are shorter
+// idle for the difference.  Blocks are dispatched round-robin over the 8 XCDs;
+// the remap gives each XCD a contiguous run of panels, so the blocks resident on
+// one XCD share one panel in its L2.  Accumulation is in T, as the dense steps
+// accumulate in their own precision.
+#ifndef DPT_SPMM_UNROLL
+#define DPT_SPMM_UNROLL 8
+#endif
+constexpr int kSpmmUnroll = DPT_SPMM_UNROLL;  // gathers in flight per lane
+constexpr int kSpmmRowsPerBlock = 64;  // 4 waves x (64 / LANES) rows x passes
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_sp_spmm(const int *__restrict__ rowptr, const int *__restrict__ col,
+__global__ __launch_bounds__(256) void k_sp_spmm(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
                                                  const T *__restrict__ val, int64_t n, int64_t ld, double lambda,
                                                  const double *__restrict__ theta, const double *__restrict__ d,
-                                                 const T *__restrict__ WT, T *__restrict__ WTn,
+                                                 const T *__restrict__ ZT, T *__restrict__ ZTn,
                                                  unsigned long long *stat) {
+    typedef typename Vec16<T>::type V;
+    constexpr int VEC = Vec16<T>::count, LANES = kSpmmLanes, G = 64 / LANES;
+    constexpr int64_t P = Panel<T>::P;
+    static_assert(P == LANES * VEC, "panel width");
+    constexpr int PASSES = kSpmmRowsPerBlock / (4 * G), U = kSpmmUnroll;
+    static_assert(PASSES * 4 * G == kSpmmRowsPerBlock, "rows per block");
     const int64_t nb = gridDim.x;
     int64_t t = blockIdx.x;
     if ((nb & 7) == 0) t = (t & 7) * (nb >> 3) + (t >> 3);
-    const int64_t row_blocks = ld / 4;
+    const int64_t row_blocks = ld / kSpmmRowsPerBlock;
     const int64_t panel = t / row_blocks;
-    const int64_t m = (t - panel * row_blocks) * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int64_t n0 = panel * kPanel + lane * 4;
-    const T *base = WT + n0;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int e0 = m < n ? rowptr[m] : 0, e1 = m < n ? rowptr[m + 1] : 0;  // padded rows have no entries
-    for (int e = e0; e < e1; ++e) {
-        const int64_t l = col[e];
-        const double v = (double)val[e];
-        double w[4];
-        Vec4<T>::load(base + l * ld, w);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += v * w[q];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (l == n0 + q) acc[q] += v;  // identity part of Z = I + W
-    }
-    double wo[4], wn[4];
-    Vec4<T>::load(WT + m * ld + n0, wo);
-    const double tm = theta[m];
+    const int64_t rb = t - panel * row_blocks;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int group = lane / LANES, chunk = lane % LANES;
+    const int64_t n0 = panel * P + chunk * VEC;           // first eigenvector of this lane
+    const int64_t pbase = panel * (ld * P) + chunk * VEC;  // its offset in row 0 of the panel
+    const T *base = ZT + pbase;
+    const T lam = (T)lambda;
     double dmax = 0.0, wmax = 0.0;
     bool bad = false;
+#pragma unroll 1
+    for (int pass = 0; pass < PASSES; ++pass) {
+        int64_t m = rb * kSpmmRowsPerBlock + (pass * 4 + wave) * G + group;
+        // one row per wave: make it visibly wave-uniform so that the row's CSR
+        // entries come through scalar loads and the addresses through SALU
+        if constexpr (G == 1) m = __builtin_amdgcn_readfirstlane((int)m);
+        const int64_t e0 = m < n ? rowptr[m] : 0, e1 = m < n ? rowptr[m + 1] : 0;  // padded rows: no entries
+        T acc[VEC];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t nn = n0 + q;
-        double w = 0.0;
-        if (m < n && nn < n && nn != m) {
-            const T num = (T)acc[q] - (T)d[nn] * (T)wo[q];
-            w = (double)((T)lambda * num / (T)(theta[nn] - tm));
+        for (int q = 0; q < VEC; ++q) acc[q] = (T)0;
+        // U gathers in flight per lane; the last batch repeats the row's last
+        // entry with weight 0 instead of branching on the remainder
+        for (int64_t e = e0; e < e1; e += U) {
+            const T *ps[U];
+            T vs[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in = e + u < e1;
+                const int64_t idx = in ? e + u : e1 - 1;
+                ps[u] = base + (int64_t)col[idx] * P;
+                vs[u] = in ? val[idx] : (T)0;
+            }
+            V w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[u] = *reinterpret_cast<const V *>(ps[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] += vs[u] * Vec16<T>::get(w[u], q);
         }
-        wn[q] = w;
-        const double dv = fabs(w - wo[q]);
-        dmax = fmax(dmax, dv);
-        wmax = fmax(wmax, fabs(w));
-        bad |= !(dv <= DBL_MAX);
+        const V zo = *reinterpret_cast<const V *>(ZT + pbase + m * P);
+        const double tm = theta[m];
+        T wn[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            const int64_t nn = n0 + q;
+            const T old = Vec16<T>::get(zo, q);
+            T w = (T)0;
+            if (m < n && nn < n) {
+                if (nn == m) {
+                    w = (T)1;
+                } else {
+                    const T num = acc[q] - (T)d[nn] * old;
+                    w = lam * num / (T)(theta[nn] - tm);
+                }
+            }
+            wn[q] = w;
+            const double dv = fabs((double)w - (double)old);
+            dmax = fmax(dmax, dv);
+            if (nn != m) wmax = fmax(wmax, fabs((double)w));
+            bad |= !(dv <= DBL_MAX);
+        }
+        *reinterpret_cast<V *>(ZTn + pbase + m * P) = Vec16<T>::make(wn);
     }
-    Vec4<T>::store(WTn + m * ld + n0, wn);
     publish_stats(stat, dmax, wmax, bad);
 }
 
-// out[i][j] = Z[i][j] = (i == j) + WT[j][i]; 64x64 tiles through LDS.
+// out[i][j] = Z[i][j] = ZT[j][i]; 64x64 tiles through LDS.
 template <typename T, typename TO>
-__global__ __launch_bounds__(256) void k_sp_export(const T *__restrict__ WT, int64_t n, int64_t ld, TO *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_sp_export(const T *__restrict__ ZT, int64_t n, int64_t ld, TO *__restrict__ out) {
     __shared__ T tile[64][65];
-    const int64_t bx = blockIdx.x, by = blockIdx.y;  // tile of WT: rows by*64, cols bx*64
+    const int64_t bx = blockIdx.x, by = blockIdx.y;  // tile of ZT: rows by*64, cols bx*64
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < 64; r += 4) tile[r][tx] = WT[(by * 64 + r) * ld + bx * 64 + tx];
+    for (int r = ty; r < 64; r += 4) tile[r][tx] = ZT[Panel<T>::at(by * 64 + r, bx * 64 + tx, ld)];
     __syncthreads();
     for (int r = ty; r < 64; r += 4) {
-        const int64_t i = bx * 64 + r, j = by * 64 + tx;  // out[i][j] = WT[j][i]
-        if (i < n && j < n) out[i * n + j] = (i == j) ? (TO)1 : (TO)tile[tx][r];
+        const int64_t i = bx * 64 + r, j = by * 64 + tx;  // out[i][j] = ZT[j][i]
+        if (i < n && j < n) out[i * n + j] = (TO)tile[tx][r];
     }
 }
 
 // Residual of eigenvector j = rows[blockIdx.x]; partial sum of squares per block.
 template <typename T>
-__global__ __launch_bounds__(256) void k_sp_residual(const int *__restrict__ rowptr, const int *__restrict__ col,
+__global__ __launch_bounds__(256) void k_sp_residual(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
                                                      const T *__restrict__ val, int64_t n, int64_t ld, double lambda,
                                                      const double *__restrict__ theta, const double *__restrict__ E,
-                                                     const T *__restrict__ WT, const int64_t *__restrict__ rows,
+                                                     const T *__restrict__ ZT, const int64_t *__restrict__ rows,
                                                      double *__restrict__ out) {
     const int64_t j = rows[blockIdx.x];
     const double ej = E[j];
     double acc = 0.0;
     for (int64_t m = threadIdx.x; m < n; m += 256) {
         double c = 0.0;
-        for (int e = rowptr[m]; e < rowptr[m + 1]; ++e) {
-            const int64_t l = col[e];
-            c += (double)val[e] * ((l == j ? 1.0 : 0.0) + (double)WT[l * ld + j]);
-        }
-        const double zm = (m == j ? 1.0 : 0.0) + (double)WT[m * ld + j];
+        for (int64_t e = rowptr[m]; e < rowptr[m + 1]; ++e) c += (double)val[e] * (double)ZT[Panel<T>::at(col[e], j, ld)];
+        const double zm = (double)ZT[Panel<T>::at(m, j, ld)];
         const double r = theta[m] * zm + lambda * c - ej * zm;
         acc += r * r;
     }
@@ -216,24 +297,24 @@ __global__ __launch_bounds__(256) void k_sp_residual(const int *__restrict__ row
 // ---------------------------------------------------------- dominant mode
 // s = (Delta z)[nstar] for a CSR row, by one wave; result in *s_out (device).
 template <typename T>
-__device__ double csr_row_dot_wave(const int *rowptr, const int *col, const T *val, int64_t row, const T *z) {
+__device__ double csr_row_dot_wave(const int64_t *rowptr, const int *col, const T *val, int64_t row, const T *z) {
     const int lane = threadIdx.x & 63;
     double s = 0.0;
-    for (int e = rowptr[row] + lane; e < rowptr[row + 1]; e += 64) s += (double)val[e] * (double)z[col[e]];
+    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += 64) s += (double)val[e] * (double)z[col[e]];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     return s;
 }
 
 template <typename T>
-__global__ void k_csr_row_dot(const int *rowptr, const int *col, const T *val, int64_t row, const T *z, double *s_out) {
+__global__ void k_csr_row_dot(const int64_t *rowptr, const int *col, const T *val, int64_t row, const T *z, double *s_out) {
     const double s = csr_row_dot_wave(rowptr, col, val, row, z);
     if (threadIdx.x == 0) *s_out = s;
 }
 
 // One iteration of F_{nstar}: 8 lanes per row, 32 rows per block.
 template <typename T>
-__global__ __launch_bounds__(256) void k_dom_csr(const int *__restrict__ rowptr, const int *__restrict__ col,
+__global__ __launch_bounds__(256) void k_dom_csr(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
                                                  const T *__restrict__ val, int64_t n, int64_t nstar, double lambda,
                                                  const double *__restrict__ theta, const T *__restrict__ z,
                                                  T *__restrict__ zn, unsigned long long *stat) {
@@ -248,7 +329,7 @@ __global__ __launch_bounds__(256) void k_dom_csr(const int *__restrict__ rowptr,
     const int64_t m = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
     T c = (T)0;
     if (m < n)
-        for (int e = rowptr[m] + sub; e < rowptr[m + 1]; e += 8) c += val[e] * z[col[e]];
+        for (int64_t e = rowptr[m] + sub; e < rowptr[m + 1]; e += 8) c += val[e] * z[col[e]];
     c += __shfl_xor(c, 4);
     c += __shfl_xor(c, 2);
     c += __shfl_xor(c, 1);
@@ -330,54 +411,102 @@ int err_code(hipError_t e) {
     return DPT_EDEVICE;
 }
 
-// Host copy of a CSR matrix given in either memory kind, validated, int32 row pointers.
-struct HostCsr {
-    std::vector<int> rowptr, col;
-    std::vector<double> val;
+// CSR Delta on the device with values in T.  Device inputs are borrowed (row
+// pointers and indices always; values when their dtype is T) after a structural
+// check on the device; host inputs are checked on the host and uploaded.
+template <typename T>
+struct DevCsr {
+    const int64_t *rowptr = nullptr;
+    const int *col = nullptr;
+    const T *val = nullptr;
+    void *owned[3] = {nullptr, nullptr, nullptr};
+    void release() {
+        for (void *&q : owned)
+            if (q) {
+                (void)hipFree(q);
+                q = nullptr;
+            }
+    }
 };
 
-bool fetch_csr(const dpt_problem *p, HostCsr *h) {
-    const int64_t n = p->n, nnz = p->nnz;
-    std::vector<int64_t> ip((size_t)n + 1);
-    h->col.resize((size_t)nnz);
-    h->val.resize((size_t)nnz);
-    const hipMemcpyKind kind = p->mem == DPT_MEM_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
-    if (hipMemcpy(ip.data(), p->indptr, sizeof(int64_t) * (n + 1), kind) != hipSuccess) return false;
-    if (nnz > 0 && hipMemcpy(h->col.data(), p->indices, sizeof(int32_t) * nnz, kind) != hipSuccess) return false;
+bool host_csr_ok(const int64_t *ip, const int *col, int64_t n, int64_t nnz) {
     if (ip[0] != 0 || ip[n] != nnz) return false;
-    h->rowptr.resize((size_t)n + 1);
-    for (int64_t m = 0; m <= n; ++m) h->rowptr[m] = (int)ip[m];
     for (int64_t m = 0; m < n; ++m) {
-        if (ip[m + 1] < ip[m]) return false;
+        if (ip[m + 1] < ip[m] || ip[m] < 0 || ip[m + 1] > nnz) return false;
         for (int64_t e = ip[m]; e < ip[m + 1]; ++e) {
-            if (h->col[e] < 0 || h->col[e] >= n) return false;
-            if (e > ip[m] && h->col[e] <= h->col[e - 1]) return false;
-        }
-    }
-    if (nnz > 0) {
-        if (p->dtype == DPT_DTYPE_F64) {
-            if (hipMemcpy(h->val.data(), p->delta, sizeof(double) * nnz, kind) != hipSuccess) return false;
-        } else {
-            std::vector<float> tmp((size_t)nnz);
-            if (hipMemcpy(tmp.data(), p->delta, sizeof(float) * nnz, kind) != hipSuccess) return false;
-            for (int64_t e = 0; e < nnz; ++e) h->val[e] = tmp[e];
+            if (col[e] < 0 || col[e] >= n) return false;
+            if (e > ip[m] && col[e] <= col[e - 1]) return false;
         }
     }
     return true;
 }
 
+// Returns DPT_OK, DPT_EINVAL (bad structure) or a device error code; on
+// failure nothing stays allocated.
 template <typename T>
-hipError_t upload_csr(const HostCsr &h, int **rowptr, int **col, T **val) {
-    hipError_t e = hipMalloc((void **)rowptr, sizeof(int) * h.rowptr.size());
-    if (e == hipSuccess) e = hipMalloc((void **)col, sizeof(int) * std::max<size_t>(1, h.col.size()));
-    if (e == hipSuccess) e = hipMalloc((void **)val, sizeof(T) * std::max<size_t>(1, h.val.size()));
-    if (e != hipSuccess) return e;
-    std::vector<T> v(h.val.begin(), h.val.end());
-    e = hipMemcpy(*rowptr, h.rowptr.data(), sizeof(int) * h.rowptr.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !h.col.empty())
-        e = hipMemcpy(*col, h.col.data(), sizeof(int) * h.col.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !v.empty()) e = hipMemcpy(*val, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
-    return e;
+int stage_csr(const dpt_problem *p, DevCsr<T> *c, hipStream_t s) {
+    const int64_t n = p->n, nnz = p->nnz;
+    const bool vals64 = p->dtype == DPT_DTYPE_F64;
+    const size_t in_b = (size_t)std::max<int64_t>(1, nnz) * (vals64 ? 8 : 4);
+    hipError_t e = hipSuccess;
+    if (p->mem == DPT_MEM_HOST) {
+        const int64_t *ip = p->indptr;
+        if (!host_csr_ok(ip, p->indices, n, nnz)) return DPT_EINVAL;
+        e = hipMalloc(&c->owned[0], sizeof(int64_t) * (n + 1));
+        if (e == hipSuccess) e = hipMalloc(&c->owned[1], sizeof(int) * std::max<int64_t>(1, nnz));
+        if (e == hipSuccess) e = hipMalloc(&c->owned[2], in_b);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->owned[0], ip, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpyAsync(c->owned[1], p->indices, sizeof(int) * nnz, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpyAsync(c->owned[2], p->delta, (size_t)nnz * (vals64 ? 8 : 4), hipMemcpyHostToDevice, s);
+        c->rowptr = (const int64_t *)c->owned[0];
+        c->col = (const int *)c->owned[1];
+    } else {
+        c->rowptr = p->indptr;
+        c->col = p->indices;
+        unsigned int *flag = nullptr, hflag = 0;
+        e = hipMalloc((void **)&flag, sizeof(unsigned int));
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL((k_zero<unsigned int>), dim3(1), dim3(64), 0, s, flag, (int64_t)1);
+            hipLaunchKernelGGL(k_csr_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->indptr, p->indices, n,
+                               nnz, flag);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            (void)hipFree(flag);
+        }
+        if (e == hipSuccess && hflag) return DPT_EINVAL;
+        if (e == hipSuccess && vals64 == (sizeof(T) == 8)) {
+            c->val = (const T *)p->delta;  // borrowed
+            return DPT_OK;
+        }
+    }
+    // values of the other width: convert (from the staged copy or the caller's array)
+    if (e == hipSuccess && vals64 != (sizeof(T) == 8)) {
+        const void *src = p->mem == DPT_MEM_HOST ? c->owned[2] : p->delta;
+        void *conv = nullptr;
+        e = hipMalloc(&conv, sizeof(T) * std::max<int64_t>(1, nnz));
+        if (e == hipSuccess && nnz > 0) {
+            if (vals64)
+                hipLaunchKernelGGL((k_convert<double, T>), dim3(blocks_for(nnz, 256)), dim3(256), 0, s,
+                                   (const double *)src, (T *)conv, nnz);
+            else
+                hipLaunchKernelGGL((k_convert<float, T>), dim3(blocks_for(nnz, 256)), dim3(256), 0, s,
+                                   (const float *)src, (T *)conv, nnz);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (c->owned[2]) (void)hipFree(c->owned[2]);
+        c->owned[2] = conv;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host sources may be freed on return
+    c->val = (const T *)c->owned[2];
+    if (e != hipSuccess) {
+        c->release();
+        return err_code(e);
+    }
+    return DPT_OK;
 }
 
 }  // namespace
@@ -386,74 +515,79 @@ hipError_t upload_csr(const HostCsr &h, int **rowptr, int **col, T **val) {
 struct SparseState {
     int64_t n = 0, ld = 0, nnz = 0;
     bool fp64 = false;
-    int *rowptr = nullptr, *col = nullptr;
-    float *val32 = nullptr;
-    double *val64 = nullptr;
-    double *diag = nullptr;
-    float *WT32[2] = {nullptr, nullptr};
-    double *WT64[2] = {nullptr, nullptr};
+    DevCsr<float> csr32;   // FP32 state
+    DevCsr<double> csr64;  // FP64 state
+    const int64_t *rowptr = nullptr;
+    const int *col = nullptr;
+    const float *val32 = nullptr;
+    const double *val64 = nullptr;
+    float *ZT32[2] = {nullptr, nullptr};
+    double *ZT64[2] = {nullptr, nullptr};
     double *dvec = nullptr;
     int cur = 0;
     bool at_identity = true;
 };
 
-int64_t sparse_pad_order(int64_t n) { return (n + kPanel - 1) / kPanel * kPanel; }
+int64_t sparse_pad_order(int64_t n) { return (n + kPad - 1) / kPad * kPad; }
 
 void sparse_destroy(SparseState *sp) {
     if (!sp) return;
-    void *ps[] = {sp->rowptr, sp->col, sp->val32, sp->val64, sp->diag, sp->WT32[0], sp->WT32[1],
-                  sp->WT64[0], sp->WT64[1], sp->dvec};
+    sp->csr32.release();
+    sp->csr64.release();
+    void *ps[] = {sp->ZT32[0], sp->ZT32[1], sp->ZT64[0], sp->ZT64[1], sp->dvec};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete sp;
 }
 
-hipError_t sparse_create(SparseState **out, const dpt_problem *p, bool fp64, int64_t ld, hipStream_t s) {
+int sparse_create(SparseState **out, const dpt_problem *p, bool fp64, int64_t ld, hipStream_t s) {
     *out = nullptr;
-    HostCsr h;
-    if (!fetch_csr(p, &h)) return hipErrorInvalidValue;
     SparseState *sp = new SparseState();
     sp->n = p->n;
     sp->ld = ld;
     sp->nnz = p->nnz;
     sp->fp64 = fp64;
-    hipError_t e = fp64 ? upload_csr(h, &sp->rowptr, &sp->col, &sp->val64)
-                        : upload_csr(h, &sp->rowptr, &sp->col, &sp->val32);
-    if (e == hipSuccess) e = hipMalloc((void **)&sp->diag, sizeof(double) * ld);
-    if (e == hipSuccess) e = hipMalloc((void **)&sp->dvec, sizeof(double) * ld);
+    const int rc = fp64 ? stage_csr(p, &sp->csr64, s) : stage_csr(p, &sp->csr32, s);
+    if (rc != DPT_OK) {
+        delete sp;
+        return rc;
+    }
+    sp->rowptr = fp64 ? sp->csr64.rowptr : sp->csr32.rowptr;
+    sp->col = fp64 ? sp->csr64.col : sp->csr32.col;
+    sp->val32 = sp->csr32.val;
+    sp->val64 = sp->csr64.val;
+    hipError_t e = hipMalloc((void **)&sp->dvec, sizeof(double) * ld);
     const size_t elems = (size_t)(ld * ld);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         if (fp64)
-            e = hipMalloc((void **)&sp->WT64[i], sizeof(double) * elems);
+            e = hipMalloc((void **)&sp->ZT64[i], sizeof(double) * elems);
         else
-            e = hipMalloc((void **)&sp->WT32[i], sizeof(float) * elems);
+            e = hipMalloc((void **)&sp->ZT32[i], sizeof(float) * elems);
     }
     if (e != hipSuccess) {
         sparse_destroy(sp);
-        return e;
+        return err_code(e);
     }
     const unsigned int g = blocks_for((int64_t)elems, 256);
-    for (int i = 0; i < 2; ++i) {
-        if (fp64)
-            hipLaunchKernelGGL((k_zero<double>), dim3(g), dim3(256), 0, s, sp->WT64[i], (int64_t)elems);
-        else
-            hipLaunchKernelGGL((k_zero<float>), dim3(g), dim3(256), 0, s, sp->WT32[i], (int64_t)elems);
+    for (int i = 0; i < 2; ++i) {  // both buffers start as the identity
+        if (fp64) {
+            hipLaunchKernelGGL((k_zero<double>), dim3(g), dim3(256), 0, s, sp->ZT64[i], (int64_t)elems);
+            hipLaunchKernelGGL((k_set_unit_diag<double>), dim3(blocks_for(sp->n, 256)), dim3(256), 0, s, sp->ZT64[i],
+                               sp->n, ld);
+        } else {
+            hipLaunchKernelGGL((k_zero<float>), dim3(g), dim3(256), 0, s, sp->ZT32[i], (int64_t)elems);
+            hipLaunchKernelGGL((k_set_unit_diag<float>), dim3(blocks_for(sp->n, 256)), dim3(256), 0, s, sp->ZT32[i],
+                               sp->n, ld);
+        }
     }
     hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(ld, 256)), dim3(256), 0, s, sp->dvec, ld);
-    hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(ld, 256)), dim3(256), 0, s, sp->diag, ld);
-    if (fp64)
-        hipLaunchKernelGGL((k_sp_diag<double>), dim3(blocks_for(sp->n, 256)), dim3(256), 0, s, sp->rowptr, sp->col,
-                           sp->val64, sp->n, sp->diag);
-    else
-        hipLaunchKernelGGL((k_sp_diag<float>), dim3(blocks_for(sp->n, 256)), dim3(256), 0, s, sp->rowptr, sp->col,
-                           sp->val32, sp->n, sp->diag);
     e = hipGetLastError();
     if (e != hipSuccess) {
         sparse_destroy(sp);
-        return e;
+        return err_code(e);
     }
     *out = sp;
-    return hipSuccess;
+    return DPT_OK;
 }
 
 namespace {
@@ -463,7 +597,7 @@ struct NoProf : ProfHook {
 };
 
 template <typename T>
-hipError_t sparse_step_t(SparseState *sp, const T *val, T *const WT[2], double lambda, const double *theta,
+hipError_t sparse_step_t(SparseState *sp, const T *val, T *const ZT[2], double lambda, const double *theta,
                          unsigned long long *st, hipStream_t s, ProfHook *prof) {
     const int nx = sp->cur ^ 1;
     const int64_t n = sp->n, ld = sp->ld;
@@ -471,18 +605,18 @@ hipError_t sparse_step_t(SparseState *sp, const T *val, T *const WT[2], double l
         hipLaunchKernelGGL((k_zero<unsigned long long>), dim3(1), dim3(64), 0, s, st, (int64_t)2);
         prof->begin(DPT_PROF_FIRST, s);
         hipLaunchKernelGGL((k_sp_first_iterate<T>), dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, sp->rowptr,
-                           sp->col, val, n, ld, lambda, theta, WT[nx], st);
+                           sp->col, val, n, ld, lambda, theta, ZT[nx], st);
         prof->end(s);
         return hipGetLastError();
     }
     prof->begin(DPT_PROF_PREPASS, s);
     hipLaunchKernelGGL((k_sp_prepass<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, sp->rowptr, sp->col, val,
-                       sp->diag, n, ld, (const T *)WT[sp->cur], lambda, theta, sp->dvec, (double *)nullptr, st);
+                       n, ld, (const T *)ZT[sp->cur], lambda, theta, sp->dvec, (double *)nullptr, st);
     prof->end(s);
-    const int64_t blocks = (ld / kPanel) * (ld / 4);
+    const int64_t blocks = (ld / Panel<T>::P) * (ld / kSpmmRowsPerBlock);
     prof->begin(DPT_PROF_SPMM, s);
     hipLaunchKernelGGL((k_sp_spmm<T>), dim3((unsigned int)blocks), dim3(256), 0, s, sp->rowptr, sp->col, val, n, ld,
-                       lambda, theta, (const double *)sp->dvec, (const T *)WT[sp->cur], WT[nx], st);
+                       lambda, theta, (const double *)sp->dvec, (const T *)ZT[sp->cur], ZT[nx], st);
     prof->end(s);
     return hipGetLastError();
 }
@@ -495,8 +629,8 @@ int sparse_step(SparseState *sp, double lambda, const double *theta, unsigned lo
     const bool first = sp->at_identity;
     NoProf none;
     if (!prof) prof = &none;
-    hipError_t e = sp->fp64 ? sparse_step_t<double>(sp, sp->val64, sp->WT64, lambda, theta, st, s, prof)
-                            : sparse_step_t<float>(sp, sp->val32, sp->WT32, lambda, theta, st, s, prof);
+    hipError_t e = sp->fp64 ? sparse_step_t<double>(sp, sp->val64, sp->ZT64, lambda, theta, st, s, prof)
+                            : sparse_step_t<float>(sp, sp->val32, sp->ZT32, lambda, theta, st, s, prof);
     if (e != hipSuccess) return err_code(e);
     (void)first;  // the first iterate writes only the pattern of Delta into a zeroed buffer
     sp->cur = nx;
@@ -508,11 +642,11 @@ int sparse_step(SparseState *sp, double lambda, const double *theta, unsigned lo
 hipError_t sparse_eigenvalues(SparseState *sp, double lambda, const double *theta, double *evec, hipStream_t s) {
     if (sp->fp64)
         hipLaunchKernelGGL((k_sp_prepass<double>), dim3(blocks_for(sp->n, 256)), dim3(256), 0, s, sp->rowptr, sp->col,
-                           sp->val64, sp->diag, sp->n, sp->ld, (const double *)sp->WT64[sp->cur], lambda, theta,
+                           sp->val64, sp->n, sp->ld, (const double *)sp->ZT64[sp->cur], lambda, theta,
                            sp->dvec, evec, (unsigned long long *)nullptr);
     else
         hipLaunchKernelGGL((k_sp_prepass<float>), dim3(blocks_for(sp->n, 256)), dim3(256), 0, s, sp->rowptr, sp->col,
-                           sp->val32, sp->diag, sp->n, sp->ld, (const float *)sp->WT32[sp->cur], lambda, theta,
+                           sp->val32, sp->n, sp->ld, (const float *)sp->ZT32[sp->cur], lambda, theta,
                            sp->dvec, evec, (unsigned long long *)nullptr);
     return hipGetLastError();
 }
@@ -521,17 +655,17 @@ hipError_t sparse_export(SparseState *sp, int64_t n, void *out, int out_f64, hip
     const dim3 grid((unsigned int)(sp->ld / 64), (unsigned int)(sp->ld / 64));
     if (sp->fp64) {
         if (out_f64)
-            hipLaunchKernelGGL((k_sp_export<double, double>), grid, dim3(256), 0, s, sp->WT64[sp->cur], n, sp->ld,
+            hipLaunchKernelGGL((k_sp_export<double, double>), grid, dim3(256), 0, s, sp->ZT64[sp->cur], n, sp->ld,
                                (double *)out);
         else
-            hipLaunchKernelGGL((k_sp_export<double, float>), grid, dim3(256), 0, s, sp->WT64[sp->cur], n, sp->ld,
+            hipLaunchKernelGGL((k_sp_export<double, float>), grid, dim3(256), 0, s, sp->ZT64[sp->cur], n, sp->ld,
                                (float *)out);
     } else {
         if (out_f64)
-            hipLaunchKernelGGL((k_sp_export<float, double>), grid, dim3(256), 0, s, sp->WT32[sp->cur], n, sp->ld,
+            hipLaunchKernelGGL((k_sp_export<float, double>), grid, dim3(256), 0, s, sp->ZT32[sp->cur], n, sp->ld,
                                (double *)out);
         else
-            hipLaunchKernelGGL((k_sp_export<float, float>), grid, dim3(256), 0, s, sp->WT32[sp->cur], n, sp->ld,
+            hipLaunchKernelGGL((k_sp_export<float, float>), grid, dim3(256), 0, s, sp->ZT32[sp->cur], n, sp->ld,
                                (float *)out);
     }
     return hipGetLastError();
@@ -547,11 +681,11 @@ hipError_t sparse_residuals(SparseState *sp, double lambda, const double *theta,
     if (e == hipSuccess) {
         if (sp->fp64)
             hipLaunchKernelGGL((k_sp_residual<double>), dim3((unsigned int)nrows), dim3(256), 0, s, sp->rowptr, sp->col,
-                               sp->val64, sp->n, sp->ld, lambda, theta, evec, (const double *)sp->WT64[sp->cur], drows,
+                               sp->val64, sp->n, sp->ld, lambda, theta, evec, (const double *)sp->ZT64[sp->cur], drows,
                                part);
         else
             hipLaunchKernelGGL((k_sp_residual<float>), dim3((unsigned int)nrows), dim3(256), 0, s, sp->rowptr, sp->col,
-                               sp->val32, sp->n, sp->ld, lambda, theta, evec, (const float *)sp->WT32[sp->cur], drows,
+                               sp->val32, sp->n, sp->ld, lambda, theta, evec, (const float *)sp->ZT32[sp->cur], drows,
                                part);
         e = hipGetLastError();
     }
@@ -574,7 +708,7 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
     const int64_t n = p->n;
     hipStream_t s = (hipStream_t)p->stream;
     int rc = DPT_OK;
-    int *rowptr = nullptr, *col = nullptr;
+    DevCsr<T> csr;
     T *val = nullptr, *dense = nullptr;
     T *z[2] = {nullptr, nullptr};
     double *theta = nullptr, *s_dev = nullptr;
@@ -587,13 +721,8 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
     auto run = [&]() -> hipError_t {
         hipError_t e;
         if (p->format == DPT_CSR) {
-            HostCsr h;
-            if (!fetch_csr(p, &h)) {
-                rc = DPT_EINVAL;
-                return hipSuccess;
-            }
-            e = upload_csr(h, &rowptr, &col, &val);
-            if (e != hipSuccess) return e;
+            rc = stage_csr(p, &csr, s);
+            if (rc != DPT_OK) return hipSuccess;
         } else {
             const size_t nn = (size_t)(n * n);
             const bool same = (sizeof(T) == 8) == (p->dtype == DPT_DTYPE_F64);
@@ -640,8 +769,8 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
         while (iters < o->max_iter) {
             unsigned long long *st = stats + 2 * iters;
             if (p->format == DPT_CSR) {
-                hipLaunchKernelGGL((k_dom_csr<T>), dim3(blocks_for(n, 32)), dim3(256), 0, s, rowptr, col,
-                                   (const T *)val, n, nstar, p->lambda, (const double *)theta, (const T *)z[cur],
+                hipLaunchKernelGGL((k_dom_csr<T>), dim3(blocks_for(n, 32)), dim3(256), 0, s, csr.rowptr, csr.col,
+                                   csr.val, n, nstar, p->lambda, (const double *)theta, (const T *)z[cur],
                                    z[cur ^ 1], st);
             } else {
                 hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, (const T *)dense, n, nstar,
@@ -670,7 +799,7 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
         }
         // eigenvalue readout from the returned iterate
         if (p->format == DPT_CSR)
-            hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, rowptr, col, (const T *)val, nstar,
+            hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, csr.rowptr, csr.col, csr.val, nstar,
                                (const T *)z[cur], s_dev);
         else
             hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, (const T *)dense, n, nstar,
@@ -703,8 +832,7 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
     };
     hipError_t e = run();
     (void)hipStreamSynchronize(s);
-    if (rowptr) (void)hipFree(rowptr);
-    if (col) (void)hipFree(col);
+    csr.release();
     if (val) (void)hipFree(val);
     for (int i = 0; i < 2; ++i)
         if (z[i]) (void)hipFree(z[i]);

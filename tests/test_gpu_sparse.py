@@ -106,3 +106,74 @@ def test_dominant_device_inputs():
     ref = oracle.iterate(theta, (ip, ix, v.astype(np.float64)), 1.0, rows=[n - 1], max_iter=50, tol=1e-6)
     assert abs(ev - ref["e"][0]) <= 1e-6 * abs(ref["e"][0])
     assert np.max(np.abs(vec.cpu().numpy() - ref["z"][0])) <= 1e-6
+
+
+@pytest.mark.parametrize("vdtype", [np.float32, np.float64])
+def test_device_csr_is_borrowed_and_matches_host_input(vdtype):
+    """Device CSR arrays (checked on the device, values borrowed or converted)
+    give bitwise the iterates of the same matrix passed from the host."""
+    import torch
+    n = 700
+    theta, (ip, ix, v) = csr_problem(n, 6, vdtype)
+    o = dpt.options(precision=dpt.DPT_FP32)
+    h_host = dpt.dpt_init(dpt.ProblemSpec(theta, (ip, ix, v), 1.0, stream=0), o)
+    dpt.dpt_step(h_host, 5)
+    dev = (torch.from_numpy(ip).cuda(), torch.from_numpy(ix).cuda(), torch.from_numpy(v).cuda())
+    h_dev = dpt.dpt_init(dpt.ProblemSpec(torch.from_numpy(theta).cuda(), dev, 1.0), o)
+    dpt.dpt_step(h_dev, 5)
+    def host(x):
+        return x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+    assert np.array_equal(host(dpt.dpt_eigenvectors(h_host)), host(dpt.dpt_eigenvectors(h_dev)))
+    assert np.array_equal(host(dpt.dpt_eigenvalues(h_host)), host(dpt.dpt_eigenvalues(h_dev)))
+
+
+@pytest.mark.parametrize("bad", ["unsorted", "col_range", "ptr_past_nnz", "ptr_decreasing", "last_ptr"])
+@pytest.mark.parametrize("api", ["init", "dominant"])
+def test_malformed_device_csr_is_rejected(bad, api):
+    """The device-side structure check turns malformed CSR into DPT_EINVAL
+    (row entries are read only after their pointers are known to be in range)."""
+    import torch
+    theta = np.arange(4.0)
+    ip = np.array([0, 2, 3, 5, 6], np.int64)
+    ix = np.array([1, 2, 0, 0, 1, 2], np.int32)
+    v = np.full(6, 0.1, np.float32)
+    if bad == "unsorted":
+        ix = np.array([2, 1, 0, 0, 1, 2], np.int32)
+    elif bad == "col_range":
+        ix = np.array([1, 2, 0, 0, 4, 2], np.int32)
+    elif bad == "ptr_past_nnz":
+        ip = np.array([0, 2, 9, 5, 6], np.int64)
+    elif bad == "ptr_decreasing":
+        ip = np.array([0, 3, 2, 5, 6], np.int64)
+    elif bad == "last_ptr":
+        ip = np.array([0, 2, 3, 5, 5], np.int64)
+    dev = (torch.from_numpy(ip).cuda(), torch.from_numpy(ix).cuda(), torch.from_numpy(v).cuda())
+    spec = dpt.ProblemSpec(torch.from_numpy(theta).cuda(), dev, 0.1)
+    with pytest.raises(dpt.DptError) as ei:
+        if api == "init":
+            dpt.dpt_init(spec)
+        else:
+            dpt.dpt_dominant(spec)
+    assert ei.value.code == dpt.DPT_EINVAL
+    # the well-formed matrix is accepted
+    good = (torch.from_numpy(np.array([0, 2, 3, 5, 6], np.int64)).cuda(),
+            torch.from_numpy(np.array([1, 2, 0, 0, 1, 2], np.int32)).cuda(), torch.from_numpy(v).cuda())
+    dpt.dpt_destroy(dpt.dpt_init(dpt.ProblemSpec(torch.from_numpy(theta).cuda(), good, 0.1)))
+
+
+def test_dominant_needs_only_theta_index_simple():
+    """The single-line map divides by theta_index - theta_m only (Sec. II.H):
+    repeated theta values elsewhere are accepted, a repeated theta_index is not."""
+    n = 500
+    theta, (ip, ix, v) = csr_problem(n, 7, np.float64)
+    theta = theta.copy()
+    theta[10] = theta[11]                       # a degenerate pair away from the index
+    spec = dpt.ProblemSpec(theta, (ip, ix, v), 1.0, stream=0)
+    ev, vec, res = dpt.dpt_dominant(spec, dpt.options(tol=1e-14, max_iter=50, precision=dpt.DPT_FP64))
+    assert res["status"] == dpt.DPT_OK
+    ref = oracle.iterate(theta, (ip, ix, v), 1.0, rows=[n - 1], max_iter=50, tol=1e-14)
+    assert abs(ev - ref["e"][0]) <= 1e-12 * abs(ref["e"][0])
+    assert np.max(np.abs(vec - ref["z"][0])) <= 1e-12
+    with pytest.raises(dpt.DptError) as ei:
+        dpt.dpt_dominant(spec, index=10)
+    assert ei.value.code == dpt.DPT_EINVAL
