@@ -35,6 +35,7 @@ constexpr int EPI_PITCH = 264;
 constexpr int SMEM_BYTES = STAGES * STAGE_BYTES > 128 * EPI_PITCH * 4 ? STAGES * STAGE_BYTES : 128 * EPI_PITCH * 4;
 
 typedef __attribute__((address_space(3))) void lds_void;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const void gbl_void;
 
 // Swizzle key of tile row r, and byte offset of logical 16-byte chunk c (0..3)
@@ -534,9 +535,13 @@ __global__ __launch_bounds__(NT3) void k_step_bf16_v4(const __bf16 *__restrict__
 
     // Epilogue through LDS in two passes of 128 tile rows (128 x 256 FP32,
     // padded rows); the two waves owning those rows write their accumulators.
+    // Then thread t updates columns c4..c4+3 (c4 = 4 (t & 63)) of rows
+    // (t >> 6) + 4k, with the global loads of 8 rows issued before any use.
     float *tile = reinterpret_cast<float *>(smem);
-    constexpr int TP = EPI_PITCH;
+    constexpr int TP = EPI_PITCH, EU = 8;
     const float lam = (float)a.lambda;
+    const int c4 = (tid & 63) * 4;
+    const int64_t m0 = col0 + c4;
     double dmax = 0.0, wmax = 0.0;
     bool bad = false;
     __syncthreads();
@@ -554,39 +559,45 @@ __global__ __launch_bounds__(NT3) void k_step_bf16_v4(const __bf16 *__restrict__
                     }
         }
         __syncthreads();
-        for (int k = 0; k < (WTM3 * BN / 4) / NT3; ++k) {
-            const int q = tid + NT3 * k;
-            const int row = q / (BN / 4), c4 = (q % (BN / 4)) * 4;
-            const int64_t n = row0 + h * WTM3 + row, m0 = col0 + c4;
-            const int64_t idx = n * ld + m0;
-            const float4 cv = *reinterpret_cast<const float4 *>(&tile[row * TP + c4]);
-            const float4 dt = *reinterpret_cast<const float4 *>(&deltaT[idx]);
-            const float4 wo = *reinterpret_cast<const float4 *>(&Wold[idx]);
-            const double th_n = a.theta[n];
-            const float dn = (float)a.d[n];
-            const bool row_ok = n < a.n;
-            const float cs[4] = {cv.x + dt.x, cv.y + dt.y, cv.z + dt.z, cv.w + dt.w};
-            const float ws[4] = {wo.x, wo.y, wo.z, wo.w};
-            float w[4];
+        for (int k0 = 0; k0 < WTM3 / 4; k0 += EU) {
+            f32x4 dt[EU], wo[EU];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t m = m0 + e;
-                w[e] = 0.0f;
-                if (row_ok && m < a.n && m != n) {
-                    const float num = cs[e] - dn * ws[e];
-                    const float gap = (float)(th_n - a.theta[m]);
-                    w[e] = lam * num / gap;
-                }
-                const double dv = fabs((double)w[e] - (double)ws[e]), av = fabs((double)w[e]);
-                dmax = fmax(dmax, dv);
-                wmax = fmax(wmax, av);
-                bad |= !(dv <= DBL_MAX) || !(av <= DBL_MAX);
+            for (int u = 0; u < EU; ++u) {
+                const int64_t n = row0 + h * WTM3 + wave + 4 * (k0 + u);
+                dt[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(&deltaT[n * ld + m0]));
+                wo[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(&Wold[n * ld + m0]));
             }
-            *reinterpret_cast<float4 *>(&Wnew[idx]) = make_float4(w[0], w[1], w[2], w[3]);
-            const __bf16 b4[4] = {(__bf16)w[0], (__bf16)w[1], (__bf16)w[2], (__bf16)w[3]};
-            uint2 packed;
-            __builtin_memcpy(&packed, b4, sizeof(packed));
-            *reinterpret_cast<uint2 *>(&Wbnew[idx]) = packed;
+#pragma unroll
+            for (int u = 0; u < EU; ++u) {
+                const int row = wave + 4 * (k0 + u);
+                const int64_t n = row0 + h * WTM3 + row, idx = n * ld + m0;
+                const float4 cv = *reinterpret_cast<const float4 *>(&tile[row * TP + c4]);
+                const double th_n = a.theta[n];
+                const float dn = (float)a.d[n];
+                const bool row_ok = n < a.n;
+                const float cs[4] = {cv.x + dt[u][0], cv.y + dt[u][1], cv.z + dt[u][2], cv.w + dt[u][3]};
+                const float ws[4] = {wo[u][0], wo[u][1], wo[u][2], wo[u][3]};
+                f32x4 w;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t m = m0 + e;
+                    w[e] = 0.0f;
+                    if (row_ok && m < a.n && m != n) {
+                        const float num = cs[e] - dn * ws[e];
+                        const float gap = (float)(th_n - a.theta[m]);
+                        w[e] = lam * num / gap;
+                    }
+                    const double dv = fabs((double)w[e] - (double)ws[e]), av = fabs((double)w[e]);
+                    dmax = fmax(dmax, dv);
+                    wmax = fmax(wmax, av);
+                    bad |= !(dv <= DBL_MAX) || !(av <= DBL_MAX);
+                }
+                __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(&Wnew[idx]));
+                const __bf16 b4[4] = {(__bf16)w[0], (__bf16)w[1], (__bf16)w[2], (__bf16)w[3]};
+                uint2 packed;
+                __builtin_memcpy(&packed, b4, sizeof(packed));
+                *reinterpret_cast<uint2 *>(&Wbnew[idx]) = packed;
+            }
         }
         __syncthreads();
     }
