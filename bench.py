@@ -6,12 +6,15 @@ N = 16384, theta_i = i/4, Delta = (R + R^T)/2 with R off-diagonal iid
 N(0, (0.25/sqrt(N))^2), zero diagonal, lambda = 1, FP32 input values.  One
 "step" is one whole solve through the C ABI: dpt_init on device-resident
 inputs (staging, BF16 copy, symmetry test), dpt_solve in the BF16 -> FP32 form
-to tol 1e-6 on max|Z_k - Z_{k-1}|, and the eigenvalue readout.  The plain FP32
-solve of the same problem is timed beside it.
+to tol 1e-6, and the eigenvalue readout.  The stopping rule (default: the
+a-posteriori contraction bound, DPT_STOP_ESTIMATE) is the same for the plain
+FP32 solve timed beside it; the other rule is reported for context.
 
 Printed: one JSON line with value = D-PT iterations per second of the BF16 ->
-FP32 solve, the roofline of the dominant kernel (the fused BF16 MFMA step, HIP
-events on its stream), and the FP64 CPU oracle timed on a bounded row sample.
+FP32 solve, the roofline of the kernel that dominates the solve time (HIP
+events on its stream) and of both fused product kernels, the error of the
+result against the converged FP64 oracle on 64 sampled rows, and the FP64 CPU
+oracle timed on that sample.
 """
 from __future__ import annotations
 
@@ -28,8 +31,17 @@ sys.path.insert(0, ROOT)
 METRIC = "DPT iter/s + TFLOP/s at N=16384 (bf16→fp32 vs fp32); solves/s, p50/p99 lat"
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_bf16_n16384.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2002_12872_amd", "csrc", "kernels_gemm_bf16.hip")
+PEAK_FP32_TFLOPS = 157.3
+CSRC = os.path.join(ROOT, "paper_2002_12872_amd", "csrc")
+# per fused product kernel: profile class, traffic summary, source file, peak
+KERNELS = {
+    "gemm_bf16": {"name": "k_step_bf16_v4 (256x256 tile, 4 waves of 128x128, K-tiles of 64 via direct-to-LDS loads)",
+                  "traffic": os.path.join(ROOT, "profiles", "traffic_gemm_bf16_n16384.txt"),
+                  "source": os.path.join(CSRC, "kernels_gemm_bf16.hip"), "peak": PEAK_BF16_TFLOPS},
+    "gemm_fp32": {"name": "k_step_gemm<PolF32,128,128,16,2,2> (fused FP32 MFMA product + update)",
+                  "traffic": os.path.join(ROOT, "profiles", "traffic_gemm_fp32_n16384.txt"),
+                  "source": os.path.join(CSRC, "kernels_dense.hip"), "peak": PEAK_FP32_TFLOPS},
+}
 
 
 def parse():
@@ -39,6 +51,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--stop-rule", choices=["estimate", "delta"], default="estimate",
+                    help="stopping rule of the timed solves (both precision forms)")
+    ap.add_argument("--kernel-precision", choices=["bf16", "fp32"], default="bf16",
+                    help="precision of the --kernel-only steps")
     ap.add_argument("--fp32-solves", type=int, default=2)
     ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle work")
@@ -231,19 +247,22 @@ def secondary_bench(args):
 
 
 def kernel_only(args):
-    """BF16 fused steps at size n only (for counter collection with rocprofv3)."""
+    """Fused product steps of one precision at size n only (for counter
+    collection with rocprofv3): BF16 steps of the BF16 -> FP32 form, or FP32 steps."""
     import torch
 
     import workloads
     from paper_2002_12872_amd import dpt
     theta, delta = workloads.dense_sym_large(0, n=args.n)
     spec = dpt.ProblemSpec(torch.from_numpy(theta).cuda(), torch.from_numpy(delta).cuda(), 1.0)
-    h = dpt.dpt_init(spec, dpt.options(precision=dpt.DPT_BF16_FP32))
+    prec = dpt.DPT_BF16_FP32 if args.kernel_precision == "bf16" else dpt.DPT_FP32
+    h = dpt.dpt_init(spec, dpt.options(precision=prec))
     dpt.dpt_step(h, 1 + args.warmup)            # first iterate (no product) + warm-up steps
     dpt.dpt_profile_enable(h, True)
     last = dpt.dpt_step(h, args.steps)
     prof = dpt.dpt_profile_read(h)
-    print(json.dumps({"mode": "kernel-only", "n": args.n, "steps": args.steps, "last_delta": last,
+    print(json.dumps({"mode": "kernel-only", "precision": args.kernel_precision, "n": args.n,
+                      "steps": args.steps, "last_delta": last,
                       "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items()}}), flush=True)
 
 
@@ -261,22 +280,24 @@ def copy_probe(args):
                       "launches": args.steps}), flush=True)
 
 
-def kernel_hash():
-    with open(KERNEL_SOURCE, "rb") as fh:
+def source_hash(path):
+    with open(path, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def read_traffic(n):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
-    taken on the current kernel source; None otherwise."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(kind, n):
+    """HBM bytes per launch of a fused product kernel from its committed
+    rocprofv3 --pmc summary, if that was taken on the current kernel source at
+    this n; None otherwise."""
+    info = KERNELS[kind]
+    if not os.path.exists(info["traffic"]):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(info["traffic"]):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_hash() or int(vals.get("n", -1)) != n:
+    if vals.get("kernel_source_sha256_16") != source_hash(info["source"]) or int(vals.get("n", -1)) != n:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -293,6 +314,59 @@ def solve_once(dpt, spec, opts, n, profile):
     e = torch.empty(n, dtype=torch.float64, device="cuda")
     dpt.dpt_eigenvalues(h, e)
     return h, res, e
+
+
+def timed_solves(dpt, spec, opts, n, count, warmup):
+    """count solves after warmup ones; returns (elapsed s, results, handles, profile sums, last E)."""
+    import torch
+    for _ in range(warmup):
+        h, _, _ = solve_once(dpt, spec, opts, n, False)
+        dpt.dpt_destroy(h)
+    torch.cuda.synchronize()
+    handles, results = [], []
+    t0 = time.perf_counter()
+    for _ in range(count):
+        h, res, e = solve_once(dpt, spec, opts, n, True)
+        handles.append(h)
+        results.append(res)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {}
+    for h in handles:
+        for k, (ms, cnt) in dpt.dpt_profile_read(h).items():
+            acc = prof.setdefault(k, [0.0, 0])
+            acc[0] += ms
+            acc[1] += cnt
+    return elapsed, results, handles, prof, e
+
+
+def roofline_of(kind, prof, n):
+    ms, cnt = prof.get(kind, (0.0, 0))
+    if cnt == 0:
+        return None
+    info = KERNELS[kind]
+    avg = ms / cnt
+    flop = 2.0 * n ** 3
+    achieved = flop / (avg * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": info["peak"], "unit": "TFLOP/s",
+            "frac": round(achieved / info["peak"], 4), "traffic": read_traffic(kind, n), "kernel": info["name"],
+            "avg_launch_ms": round(avg, 4), "launches": cnt, "algorithmic_flop_per_launch": flop}
+
+
+def accuracy(dpt, h, e_dev, theta, ref, rows, z_scale):
+    """Errors of a handle's result against the converged FP64 oracle rows."""
+    import numpy as np
+    import torch
+    n = theta.shape[0]
+    z = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    dpt.dpt_eigenvectors(h, z)
+    zr = z[torch.as_tensor(rows, device="cuda")].double().cpu().numpy()
+    del z
+    e = e_dev.cpu().numpy()[rows]
+    e_e = float(np.max(np.abs(e - ref["e"]) / np.maximum(np.abs(ref["e"]), 1e-12 * np.abs(theta).max())))
+    e_z = float(np.max(np.abs(zr - ref["z"])) / z_scale)
+    return {"max_rel_eigenvalue": e_e, "max_abs_eigenvalue": float(np.max(np.abs(e - ref["e"]))),
+            "e_Z": e_z}
 
 
 def main():
@@ -321,74 +395,52 @@ def main():
     de_d = torch.from_numpy(delta).to(dev)
     torch.cuda.synchronize()
     spec = dpt.ProblemSpec(th_d, de_d, 1.0)
-    opt_mixed = dpt.options(tol=args.tol, max_iter=100, precision=dpt.DPT_BF16_FP32)
-    opt_fp32 = dpt.options(tol=args.tol, max_iter=100, precision=dpt.DPT_FP32)
+    rules = {"estimate": dpt.DPT_STOP_ESTIMATE, "delta": dpt.DPT_STOP_DELTA}
+    rule = rules[args.stop_rule]
+    other = "delta" if args.stop_rule == "estimate" else "estimate"
 
-    # ---- BF16 -> FP32 solves
-    for _ in range(args.warmup):
-        h, _, _ = solve_once(dpt, spec, opt_mixed, n, False)
-        dpt.dpt_destroy(h)
-    torch.cuda.synchronize()
-    handles, results = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        h, res, e = solve_once(dpt, spec, opt_mixed, n, True)
-        handles.append(h)
-        results.append(res)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def opts(precision, stop_rule):
+        return dpt.options(tol=args.tol, max_iter=100, precision=precision, stop_rule=stop_rule)
+
+    # ---- BF16 -> FP32 solves (the timed steps)
+    elapsed, results, handles, prof, e_mixed = timed_solves(dpt, spec, opts(dpt.DPT_BF16_FP32, rule), n,
+                                                            args.steps, args.warmup)
     print("# mixed solves: %d in %.3f s, iterations %s" % (args.steps, elapsed,
           [(r["iters_bf16"], r["iters_fp32"]) for r in results]), file=sys.stderr, flush=True)
-    prof = {}
-    for h in handles:
-        for k, (ms, cnt) in dpt.dpt_profile_read(h).items():
-            a = prof.setdefault(k, [0.0, 0])
-            a[0] += ms
-            a[1] += cnt
-    e_gpu = e.cpu().numpy()
     iters_total = sum(r["iters"] for r in results)
     gemm_steps = sum(r["iters"] - 1 for r in results)   # the first iterate needs no product
     flop = 2.0 * n ** 3
     value = iters_total / elapsed
     ms_per_solve = 1e3 * elapsed / args.steps
 
-    # roofline of the dominant kernel (fused BF16 step)
-    g_ms, g_cnt = prof.get("gemm_bf16", (float("nan"), 0))
-    avg_ms = g_ms / max(g_cnt, 1)
-    achieved = flop / (avg_ms * 1e-3) / 1e12
-    traffic = read_traffic(n)
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
-                "traffic": traffic, "kernel": "k_step_bf16_v2 (256x256 tile, 4-stage direct-to-LDS)",
-                "avg_launch_ms": round(avg_ms, 4), "launches": g_cnt,
-                "algorithmic_flop_per_launch": flop}
+    # roofline: the product kernel with the largest share of the solve time, plus both
+    by_kernel = {k: roofline_of(k, prof, n) for k in KERNELS}
+    dominant = max((k for k in KERNELS if by_kernel[k]), key=lambda k: prof[k][0])
+    roofline = dict(by_kernel[dominant])
+    roofline["share_of_solve_gpu_time"] = round(prof[dominant][0] / sum(v[0] for v in prof.values()), 3)
 
-    # ---- plain FP32 solves (comparison at the same tolerance)
+    # ---- plain FP32 solves, same tolerance and stopping rule
     fp32 = None
+    f_handles = []
     if args.fp32_solves > 0:
-        h, _, _ = solve_once(dpt, spec, opt_fp32, n, False)
-        dpt.dpt_destroy(h)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        f_res, f_handles = [], []
-        for _ in range(args.fp32_solves):
-            h, res, _ = solve_once(dpt, spec, opt_fp32, n, True)
-            f_res.append(res)
-            f_handles.append(h)
-        torch.cuda.synchronize()
-        f_el = time.perf_counter() - t1
-        f_prof = [0.0, 0]
-        for h in f_handles:
-            ms, cnt = dpt.dpt_profile_read(h).get("gemm_fp32", (0.0, 0))
-            f_prof[0] += ms
-            f_prof[1] += cnt
-            dpt.dpt_destroy(h)
-        f_avg = f_prof[0] / max(f_prof[1], 1)
+        f_el, f_res, f_handles, f_prof, e_fp32 = timed_solves(dpt, spec, opts(dpt.DPT_FP32, rule), n,
+                                                              args.fp32_solves, 1)
+        f_avg = f_prof["gemm_fp32"][0] / max(f_prof["gemm_fp32"][1], 1)
         fp32 = {"iter_s": round(sum(r["iters"] for r in f_res) / f_el, 3),
                 "ms_per_solve": round(1e3 * f_el / args.fp32_solves, 2),
                 "iters": f_res[0]["iters"],
                 "gemm_fp32_avg_ms": round(f_avg, 3),
                 "gemm_fp32_tflops": round(flop / (f_avg * 1e-3) / 1e12, 2)}
+
+    # ---- the other stopping rule, one solve of each form (context)
+    other_rule = {}
+    for name, prec in (("bf16_fp32", dpt.DPT_BF16_FP32), ("fp32", dpt.DPT_FP32)):
+        el, rs, hs, _, _ = timed_solves(dpt, spec, opts(prec, rules[other]), n, 1, 0)
+        other_rule[name] = {"ms_per_solve": round(1e3 * el, 2), "iters": [rs[0]["iters_bf16"], rs[0]["iters_fp32"]]}
+        for h in hs:
+            dpt.dpt_destroy(h)
+    other_rule["speedup_bf16_fp32_vs_fp32"] = round(other_rule["fp32"]["ms_per_solve"] /
+                                                    other_rule["bf16_fp32"]["ms_per_solve"], 3)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "iter/s", "n_gpus": 1,
@@ -397,43 +449,46 @@ def main():
         "dtype": "bf16->fp32", "data": "synthetic",
         "config": {"workload": "dense symmetric N=%d, theta_i=i/4, Delta=(R+R^T)/2, "
                                "R~N(0,(0.25/sqrt N)^2) zero diagonal, lambda=1; "
-                               "BF16->FP32 solve to max|dZ|<%g" % (n, args.tol),
-                   "n": n, "tol": args.tol, "step": "one full solve (init+solve+readout)"},
+                               "BF16->FP32 solve to tol %g (%s stopping rule)" % (n, args.tol, args.stop_rule),
+                   "n": n, "tol": args.tol, "stop_rule": args.stop_rule,
+                   "step": "one full solve (init+solve+readout)"},
         "iters_per_solve": [r["iters"] for r in results],
         "iters_bf16_fp32": [results[0]["iters_bf16"], results[0]["iters_fp32"]],
+        "delta_history": [float("%.3g" % x) for x in results[0]["history"]],
         "solve_tflops": round(gemm_steps * flop / elapsed / 1e12, 2),
         "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
         "roofline": roofline,
+        "roofline_by_kernel": by_kernel,
         "fp32": fp32,
         "speedup_vs_fp32": (round(fp32["ms_per_solve"] / ms_per_solve, 3) if fp32 else None),
+        "other_stop_rule": {"rule": other, **other_rule},
     }
 
-    # ---- CPU baseline: the FP64 oracle on a bounded sample of eigenvector rows
+    # ---- FP64 oracle on 64 sampled rows: converged reference and CPU baseline
     if not args.skip_cpu:
         import oracle
-        k = results[0]["iters"]
-        d64 = delta.astype(np.float64)
         threads = oracle.max_threads()
-        probe_rows = workloads.sample_rows(n, max(threads, 2))
+        rows = workloads.sample_rows(n, 64)
+        d64 = delta.astype(np.float64)
         t = time.perf_counter()
-        oracle.iterate(theta, d64, 1.0, rows=probe_rows, max_iter=1, fixed_steps=True)
-        per_row_iter = (time.perf_counter() - t) / len(probe_rows)
-        rows_n = int(max(threads, min(256, args.cpu_seconds / max(per_row_iter * k, 1e-9))))
-        rows = workloads.sample_rows(n, rows_n)
-        t = time.perf_counter()
-        ref = oracle.iterate(theta, d64, 1.0, rows=rows, max_iter=k, fixed_steps=True)
+        ref = oracle.iterate(theta, d64, 1.0, rows=rows, max_iter=40, tol=1e-14)
         cpu_t = time.perf_counter() - t
-        cpu_value = k * (len(rows) / n) / cpu_t
-        e_rel = float(np.max(np.abs(e_gpu[rows] - ref["e"]) /
-                             np.maximum(np.abs(ref["e"]), 1e-12 * np.abs(theta).max())))
-        out["cpu_baseline"] = {"value": round(cpu_value, 6), "unit": "iter/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": "%d of %d eigenvector rows x %d iterations of the FP64 "
-                                         "oracle (rows evolve independently), %.1f s, scaled "
-                                         "by rows/N" % (len(rows), n, k, cpu_t)}
-        out["error_vs_fp64_oracle"] = {"max_rel_eigenvalue": e_rel, "rows": len(rows),
-                                       "oracle_iterations": k}
-    for h in handles:
+        k = ref["iters"]
+        out["cpu_baseline"] = {"value": round(k * (len(rows) / n) / cpu_t, 6), "unit": "iter/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": "%d of %d eigenvector rows (rows evolve independently), %d FP64 "
+                                         "iterations to max|dz| < 1e-14 in %.1f s, scaled by rows/N"
+                                         % (len(rows), n, k, cpu_t)}
+        z_scale = float(np.max(np.abs(ref["z"] - np.eye(n)[rows])))
+        err = {"reference": "FP64 oracle, %d rows, %d iterations" % (len(rows), k),
+               "bf16_fp32": accuracy(dpt, handles[-1], e_mixed, theta, ref, rows, z_scale)}
+        res = dpt.dpt_residuals(handles[-1], rows)
+        norm_ub = np.abs(theta).max() + np.sqrt(np.sum(d64 ** 2))
+        err["bf16_fp32"]["residual_rel"] = float(np.max(res / norm_ub))
+        if f_handles:
+            err["fp32"] = accuracy(dpt, f_handles[-1], e_fp32, theta, ref, rows, z_scale)
+        out["error_vs_fp64_oracle"] = err
+    for h in handles + f_handles:
         dpt.dpt_destroy(h)
     if args.serve_requests > 0:
         print("# serving trace of %d requests" % args.serve_requests, file=sys.stderr, flush=True)
