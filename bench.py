@@ -35,12 +35,12 @@ PEAK_FP32_TFLOPS = 157.3
 CSRC = os.path.join(ROOT, "paper_2002_12872_amd", "csrc")
 # per fused product kernel: profile class, traffic summary, source file, peak
 KERNELS = {
-    "gemm_bf16": {"name": "k_step_bf16_v4 (256x256 tile, 4 waves of 128x128, K-tiles of 64 via direct-to-LDS loads)",
+    "gemm_bf16": {"name": "k_step_bf16_large (256x256 tile, 4 waves of 128x128, K-tiles of 64 via direct-to-LDS loads)",
                   "traffic": os.path.join(ROOT, "profiles", "traffic_gemm_bf16_n16384.txt"),
-                  "source": os.path.join(CSRC, "kernels_gemm_bf16.hip"), "peak": PEAK_BF16_TFLOPS},
-    "gemm_fp32": {"name": "k_step_gemm<PolF32,128,128,16,2,2> (fused FP32 MFMA product + update)",
+                  "source": os.path.join(CSRC, "kernels_gemm_large.hip"), "peak": PEAK_BF16_TFLOPS},
+    "gemm_fp32": {"name": "k_step_f32_large (256x256 tile, 4 waves of 128x128, K-tiles of 32 via direct-to-LDS loads)",
                   "traffic": os.path.join(ROOT, "profiles", "traffic_gemm_fp32_n16384.txt"),
-                  "source": os.path.join(CSRC, "kernels_dense.hip"), "peak": PEAK_FP32_TFLOPS},
+                  "source": os.path.join(CSRC, "kernels_gemm_large.hip"), "peak": PEAK_FP32_TFLOPS},
 }
 
 

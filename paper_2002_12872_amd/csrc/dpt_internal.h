@@ -78,11 +78,15 @@ hipError_t launch_prepass_f64_f64(const double *W, const double *D, const StepAr
 // deltaT (FP32); writes W' (FP32) and Wb' (BF16).
 hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                             const float *W, float *Wn, __bf16 *Wbn, hipStream_t s);
-// Large-problem BF16 step (kernels_gemm_bf16.hip): 256 x 256 tiles, direct
-// global->LDS 4-stage pipeline.  Requires ld % 256 == 0 and ld >= 1024.
-bool step_bf16_v2_supported(int64_t ld);
-hipError_t launch_step_bf16_v2(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
-                               const float *W, float *Wn, __bf16 *Wbn, hipStream_t s);
+// Large-problem BF16 and FP32 steps (kernels_gemm_large.hip): 256 x 256 tiles,
+// 4 waves of 128 x 128, K-tiles of 128 bytes per row through a 2-stage direct
+// global->LDS ring.  Require ld % 256 == 0 and ld >= 1024; the BF16 one also
+// writes the BF16 shadow (Wbn != NULL).
+bool step_large_supported(int64_t ld);
+hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
+                                  const float *W, float *Wn, __bf16 *Wbn, hipStream_t s);
+hipError_t launch_step_f32_large(const StepArgs &a, const float *W, const float *Delta, const float *deltaT,
+                                 float *Wn, hipStream_t s);
 hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta, const float *deltaT,
                            float *Wn, __bf16 *Wbn, hipStream_t s);
 hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT,

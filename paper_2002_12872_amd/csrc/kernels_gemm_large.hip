@@ -1,0 +1,374 @@
+// Fused D-PT steps for large dense problems on gfx950 (ld a multiple of 256,
+// ld >= 1024): the BF16 step and the FP32 step.
+//
+// One application of eq. (dyn) of Kenmoe, Smerlak, Zadorin (arXiv:2002.12872)
+// on the padded state W = A - I:
+//     C  = Delta^T + W Delta^T                               (MFMA, FP32 accumulate)
+//     W' = lambda (C - d_n W) / (theta_n - theta_m),  m != n  (FP32 epilogue, FP64 gaps)
+// plus max|W' - W| and max|W'| for the stopping rule.  The BF16 step multiplies
+// bf16(W) bf16(Delta)^T and also writes the BF16 shadow of W'.
+//
+// Shared structure.  A 256 x 256 output tile per workgroup of 4 waves (one per
+// SIMD); each wave owns a 128 x 128 wave tile as 4 x 4 blocks of 32 x 32 MFMA
+// accumulators (256 registers, held in the AGPR half of the register file).
+// K advances in tiles of 128 bytes per row (64 BF16 or 32 FP32 values), so each
+// tile row read from global memory is one whole cache line; tiles go through a
+// 2-stage LDS ring (64 KiB per stage: 256 rows of A, then 256 rows of B) filled
+// by direct global->LDS loads (global_load_lds_dwordx4, no staging registers).
+// In LDS the 16-byte chunk c of row r sits at slot c ^ key8(r), key8(r) =
+// (r ^ (r >> 3)) & 7: any 16 (and any 8) consecutive rows read at one logical
+// chunk fall on disjoint banks.  The epilogue stages the accumulators through
+// the freed LDS.
+#include <float.h>
+
+#include "device_common.h"
+#include "dpt_internal.h"
+
+namespace dpt {
+namespace {
+
+constexpr int BM = 256, BN = 256;
+constexpr int ROW = 128;                  // bytes of one tile row per K-tile
+constexpr int STAGE = (BM + BN) * ROW;    // 64 KiB: A tile, then B tile
+constexpr int NT = 256;                   // 4 waves
+constexpr int WM = 2, WN = 2;             // wave grid
+constexpr int WTM = BM / WM, WTN = BN / WN;  // 128 x 128 per wave
+constexpr int TM = WTM / 32, TN = WTN / 32;  // 4 x 4 MFMA blocks
+constexpr int LOADS = 16;                 // global->LDS instructions per thread per stage
+// Epilogue tile: 128 rows of 256 FP32 values, row pitch 264 so that the two
+// half-waves of an accumulator store (rows 4 apart) hit disjoint bank halves.
+constexpr int EPI_PITCH = 264;
+constexpr int SMEM = 2 * STAGE > 128 * EPI_PITCH * 4 ? 2 * STAGE : 128 * EPI_PITCH * 4;
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void gbl_void;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int key8(int r) { return (r ^ (r >> 3)) & 7; }
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Workgroup barrier without an implicit wait on outstanding vector-memory
+// operations (the prefetched stage must stay in flight); the memory clobber
+// keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void barrier_keep_loads() { asm volatile("s_barrier" ::: "memory"); }
+
+// Global->LDS loads of one K-tile into one ring slot.  Wave w fills tile rows
+// [64w, 64w + 64) of A and of B, 8 rows of 128 bytes per instruction; lane L
+// lands at byte 16 L of the instruction's 1 KiB: row 8i + (L >> 3), physical
+// slot L & 7, so it reads logical chunk (L & 7) ^ key8(row).  key8 of tile row
+// 64w + 8i + lr is lr ^ i, so the lane's byte offset inside instruction i is
+// lr * ldb + (((L & 7) ^ lr ^ i) << 4); ldb (a multiple of 512) leaves the
+// chunk bits free for the XOR with i << 4.
+struct TileLoader {
+    const unsigned char *ga, *gb;  // row 64w of the A and B tiles (bytes)
+    int64_t ldb;                   // bytes per matrix row
+    int lane_off;                  // lr * ldb + (((L & 7) ^ lr) << 4)
+    int lds_off;                   // 64 w * ROW
+
+    __device__ void init(const void *A, const void *B, int64_t row0, int64_t col0, int64_t ld_bytes, int wave,
+                         int lane) {
+        ldb = ld_bytes;
+        ga = (const unsigned char *)A + (row0 + 64 * wave) * ldb;
+        gb = (const unsigned char *)B + (col0 + 64 * wave) * ldb;
+        const int lr = lane >> 3;
+        lane_off = lr * (int)ldb + (((lane & 7) ^ lr) << 4);
+        lds_off = 64 * wave * ROW;
+    }
+    __device__ __forceinline__ void issue(unsigned char *smem, int kt, int slot) const {
+        unsigned char *sb = smem + slot * STAGE + lds_off;
+        const int64_t ko = (int64_t)kt * ROW;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t off = ko + 8 * i * ldb + (lane_off ^ (i << 4));
+            __builtin_amdgcn_global_load_lds((gbl_void *)(ga + off), (lds_void *)(sb + i * 8 * ROW), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((gbl_void *)(gb + off), (lds_void *)(sb + BM * ROW + i * 8 * ROW), 16,
+                                             0, 0);
+        }
+    }
+};
+
+// Epilogue of one tile: the accumulators (32x32 layout: register r of lane l is
+// C[(r & 3) + 4 (l >> 5) + 8 (r >> 2)][l & 31]) go through LDS in two passes of
+// 128 tile rows; then thread t updates columns c4..c4+3 (c4 = 4 (t & 63)) of
+// rows (t >> 6) + 4k, with the global loads of 8 rows issued before any use.
+template <bool WRITE_BF16>
+__device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[TM][TN], const float *__restrict__ deltaT,
+                                         const float *__restrict__ Wold, float *__restrict__ Wnew,
+                                         __bf16 *__restrict__ Wbnew, const StepArgs &a, int64_t row0, int64_t col0,
+                                         int tid, int lane, int wave, int wr, int wc) {
+    float *tile = reinterpret_cast<float *>(smem);
+    constexpr int TP = EPI_PITCH, EU = 8;
+    const int64_t ld = a.ld;
+    const float lam = (float)a.lambda;
+    const int c4 = (tid & 63) * 4;
+    const int64_t m0 = col0 + c4;
+    double dmax = 0.0, wmax = 0.0;
+    bool bad = false;
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < WM; ++h) {
+        if (wr == h) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = i * 32 + (r & 3) + ((lane >> 5) << 2) + ((r >> 2) << 3);
+                        tile[row * TP + wc * WTN + j * 32 + (lane & 31)] = acc[i][j][r];
+                    }
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < WTM / 4; k0 += EU) {
+            f32x4 dt[EU], wo[EU];
+#pragma unroll
+            for (int u = 0; u < EU; ++u) {
+                const int64_t n = row0 + h * WTM + wave + 4 * (k0 + u);
+                dt[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(&deltaT[n * ld + m0]));
+                wo[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(&Wold[n * ld + m0]));
+            }
+#pragma unroll
+            for (int u = 0; u < EU; ++u) {
+                const int row = wave + 4 * (k0 + u);
+                const int64_t n = row0 + h * WTM + row, idx = n * ld + m0;
+                const float4 cv = *reinterpret_cast<const float4 *>(&tile[row * TP + c4]);
+                const double th_n = a.theta[n];
+                const float dn = (float)a.d[n];
+                const bool row_ok = n < a.n;
+                const float cs[4] = {cv.x + dt[u][0], cv.y + dt[u][1], cv.z + dt[u][2], cv.w + dt[u][3]};
+                const float ws[4] = {wo[u][0], wo[u][1], wo[u][2], wo[u][3]};
+                f32x4 w;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t m = m0 + e;
+                    w[e] = 0.0f;
+                    if (row_ok && m < a.n && m != n) {
+                        const float num = cs[e] - dn * ws[e];
+                        const float gap = (float)(th_n - a.theta[m]);
+                        w[e] = lam * num / gap;
+                    }
+                    const double dv = fabs((double)w[e] - (double)ws[e]), av = fabs((double)w[e]);
+                    dmax = fmax(dmax, dv);
+                    wmax = fmax(wmax, av);
+                    bad |= !(dv <= DBL_MAX) || !(av <= DBL_MAX);
+                }
+                __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(&Wnew[idx]));
+                if (WRITE_BF16) {
+                    const __bf16 b4[4] = {(__bf16)w[0], (__bf16)w[1], (__bf16)w[2], (__bf16)w[3]};
+                    uint2 packed;
+                    __builtin_memcpy(&packed, b4, sizeof(packed));
+                    *reinterpret_cast<uint2 *>(&Wbnew[idx]) = packed;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    publish_stats(a.stat, dmax, wmax, bad);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 step.  A K-tile (64 values) is consumed as two halves of K = 32 whose
+// fragments go to two register sets (fa0/fb0, fa1/fb1): half 1 is read while
+// half 0 multiplies.  The barrier (tile kt+1 landed, tile kt fully read) sits
+// before the last substep, whose MFMAs cover the refill of tile kt's slot with
+// tile kt+2 and the reads of tile kt+1's first half.  Fragments: lane (fr, fg)
+// supplies row fr of a 32-row block and, at half h and substep s, logical chunk
+// 4h + 2fg + s; blocks 32 rows apart differ in key8 by 4 when the block index
+// is odd.
+__global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict__ A, const __bf16 *__restrict__ B,
+                                                        const float *__restrict__ deltaT,
+                                                        const float *__restrict__ Wold, float *__restrict__ Wnew,
+                                                        __bf16 *__restrict__ Wbnew, StepArgs a, int tiles_m,
+                                                        int tiles_n) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+    int tm, tn;
+    tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+    const int ktiles = (int)(a.ld * 2 / ROW);  // a multiple of 4
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave / WN, wc = wave % WN;
+    TileLoader ld;
+    ld.init(A, B, row0, col0, a.ld * 2, wave, lane);
+
+    floatx16_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    const int fr = lane & 31, fg = lane >> 5;
+    const int ra = wr * WTM + fr, rb = wc * WTN + fr;
+    const int a_base = ra * ROW + (((2 * fg) ^ key8(ra)) << 4);
+    const int b_base = BM * ROW + rb * ROW + (((2 * fg) ^ key8(rb)) << 4);
+    bf16x8_t fa0[2][TM], fb0[2][TN], fa1[2][TM], fb1[2][TN];
+#define DPT_FRAGS(FA, FB, SLOT, H)                                                                                   \
+    do {                                                                                                             \
+        const unsigned char *sb_ = smem + (SLOT) * STAGE;                                                            \
+        _Pragma("unroll") for (int s_ = 0; s_ < 2; ++s_) {                                                           \
+            _Pragma("unroll") for (int i_ = 0; i_ < TM; ++i_) FA[s_][i_] = *reinterpret_cast<const bf16x8_t *>(      \
+                sb_ + ((a_base + i_ * 32 * ROW) ^ (((((i_ & 1) ^ (H)) << 2) ^ s_) << 4)));                           \
+            _Pragma("unroll") for (int j_ = 0; j_ < TN; ++j_) FB[s_][j_] = *reinterpret_cast<const bf16x8_t *>(      \
+                sb_ + ((b_base + j_ * 32 * ROW) ^ (((((j_ & 1) ^ (H)) << 2) ^ s_) << 4)));                           \
+        }                                                                                                            \
+    } while (0)
+#define DPT_MMA(FA, FB, S)                                                                                           \
+    do {                                                                                                             \
+        _Pragma("unroll") for (int i_ = 0; i_ < TM; ++i_) _Pragma("unroll") for (int j_ = 0; j_ < TN; ++j_)          \
+            acc[i_][j_] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(FA[S][i_], FB[S][j_], acc[i_][j_], 0, 0, 0);       \
+    } while (0)
+#define DPT_INTERLEAVE(NVMEM)                                                                                        \
+    do {                                                                                                             \
+        _Pragma("unroll") for (int g_ = 0; g_ < 8; ++g_) {                                                           \
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                                       \
+            if ((NVMEM) > 0) __builtin_amdgcn_sched_group_barrier(0x020, (NVMEM) / 8, 0);                            \
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                                       \
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);                                                       \
+        }                                                                                                            \
+    } while (0)
+
+    // prologue: both slots in flight, wait for tile 0, read its first half
+    ld.issue(smem, 0, 0);
+    ld.issue(smem, 1, 1);
+    wait_vmcnt<LOADS>();
+    barrier_keep_loads();
+    DPT_FRAGS(fa0, fb0, 0, 0);
+    for (int kt = 0; kt < ktiles - 1; ++kt) {
+        const int slot = kt & 1;
+        DPT_MMA(fa0, fb0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA(fa0, fb0, 1);
+        DPT_FRAGS(fa1, fb1, slot, 1);
+        DPT_INTERLEAVE(0);
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA(fa1, fb1, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        // every fragment of tile kt is in registers; tile kt+1 must have landed
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        wait_vmcnt<0>();
+        barrier_keep_loads();
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA(fa1, fb1, 1);
+        // refill the freed slot (past the end: the last tile again, never read)
+        ld.issue(smem, min(kt + 2, ktiles - 1), slot);
+        DPT_FRAGS(fa0, fb0, slot ^ 1, 0);
+        DPT_INTERLEAVE(16);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    DPT_MMA(fa0, fb0, 0);
+    DPT_MMA(fa0, fb0, 1);
+    DPT_FRAGS(fa1, fb1, (ktiles - 1) & 1, 1);
+    DPT_MMA(fa1, fb1, 0);
+    DPT_MMA(fa1, fb1, 1);
+    wait_vmcnt<0>();
+#undef DPT_INTERLEAVE
+#undef DPT_MMA
+#undef DPT_FRAGS
+    epilogue<true>(smem, acc, deltaT, Wold, Wnew, Wbnew, a, row0, col0, tid, lane, wave, wr, wc);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 step with v_mfma_f32_32x32x2_f32 (K = 2 per MFMA).  The K order inside a
+// group of 8 values is permuted, identically for both operands: lane (fr, fg)
+// loads 4 consecutive values k0 + 4 fg .. k0 + 4 fg + 3 of its row with one
+// 16-byte read, and MFMA j of the group takes element j, so MFMA j sums over
+// k0 + j and k0 + 4 + j and the four MFMAs cover the group once.  A K-tile (32
+// values) is 4 groups of 64 MFMAs per wave; the next group's fragments are read
+// while the current group multiplies.  With 256 MFMAs of 64 cycles per wave and
+// K-tile, the 2-stage ring has a whole K-tile of time to land the next tile.
+__global__ __launch_bounds__(NT) void k_step_f32_large(const float *__restrict__ A, const float *__restrict__ B,
+                                                       const float *__restrict__ deltaT, const float *__restrict__ Wold,
+                                                       float *__restrict__ Wnew, StepArgs a, int tiles_m,
+                                                       int tiles_n) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+    int tm, tn;
+    tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+    const int ktiles = (int)(a.ld * 4 / ROW);  // a multiple of 8
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave / WN, wc = wave % WN;
+    TileLoader ld;
+    ld.init(A, B, row0, col0, a.ld * 4, wave, lane);
+
+    floatx16_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    // group g of a K-tile = logical chunks 2g + fg of the row
+    const int fr = lane & 31, fg = lane >> 5;
+    const int ra = wr * WTM + fr, rb = wc * WTN + fr;
+    const int a_base = ra * ROW + ((fg ^ key8(ra)) << 4);
+    const int b_base = BM * ROW + rb * ROW + ((fg ^ key8(rb)) << 4);
+    f32x4 fa[2][TM], fb[2][TN];
+#define DPT_FRAGS32(BUF, SLOT, G)                                                                                    \
+    do {                                                                                                             \
+        const unsigned char *sb_ = smem + (SLOT) * STAGE;                                                            \
+        _Pragma("unroll") for (int i_ = 0; i_ < TM; ++i_) fa[BUF][i_] = *reinterpret_cast<const f32x4 *>(           \
+            sb_ + ((a_base + i_ * 32 * ROW) ^ ((((i_ & 1) << 2) ^ (2 * (G))) << 4)));                                \
+        _Pragma("unroll") for (int j_ = 0; j_ < TN; ++j_) fb[BUF][j_] = *reinterpret_cast<const f32x4 *>(           \
+            sb_ + ((b_base + j_ * 32 * ROW) ^ ((((j_ & 1) << 2) ^ (2 * (G))) << 4)));                                \
+    } while (0)
+#define DPT_MMA32(BUF)                                                                                               \
+    do {                                                                                                             \
+        _Pragma("unroll") for (int e_ = 0; e_ < 4; ++e_) _Pragma("unroll") for (int i_ = 0; i_ < TM; ++i_)          \
+            _Pragma("unroll") for (int j_ = 0; j_ < TN; ++j_) acc[i_][j_] =                                          \
+                __builtin_amdgcn_mfma_f32_32x32x2f32(fa[BUF][i_][e_], fb[BUF][j_][e_], acc[i_][j_], 0, 0, 0);        \
+    } while (0)
+
+    ld.issue(smem, 0, 0);
+    for (int kt = 0; kt < ktiles; ++kt) {
+        const int slot = kt & 1;
+        // tile kt landed everywhere; every wave is done with tile kt-1, whose
+        // slot now takes tile kt+1
+        wait_vmcnt<0>();
+        barrier_keep_loads();
+        if (kt + 1 < ktiles) ld.issue(smem, kt + 1, slot ^ 1);
+        DPT_FRAGS32(0, slot, 0);
+        DPT_FRAGS32(1, slot, 1);
+        DPT_MMA32(0);
+        DPT_FRAGS32(0, slot, 2);
+        DPT_MMA32(1);
+        DPT_FRAGS32(1, slot, 3);
+        DPT_MMA32(0);
+        DPT_MMA32(1);
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    }
+#undef DPT_MMA32
+#undef DPT_FRAGS32
+    epilogue<false>(smem, acc, deltaT, Wold, Wnew, nullptr, a, row0, col0, tid, lane, wave, wr, wc);
+}
+
+}  // namespace
+
+bool step_large_supported(int64_t ld) { return ld % BM == 0 && ld % BN == 0 && ld >= 1024; }
+
+hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
+                                  const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
+    if (!step_large_supported(a.ld) || !Wbn) return hipErrorInvalidValue;
+    const int tiles_m = (int)(a.ld / BM), tiles_n = (int)(a.ld / BN);
+    hipLaunchKernelGGL(k_step_bf16_large, dim3((unsigned int)(tiles_m * tiles_n)), dim3(NT), 0, s, Wb, Deltab,
+                       deltaT, W, Wn, Wbn, a, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_f32_large(const StepArgs &a, const float *W, const float *Delta, const float *deltaT,
+                                 float *Wn, hipStream_t s) {
+    if (!step_large_supported(a.ld)) return hipErrorInvalidValue;
+    const int tiles_m = (int)(a.ld / BM), tiles_n = (int)(a.ld / BN);
+    hipLaunchKernelGGL(k_step_f32_large, dim3((unsigned int)(tiles_m * tiles_n)), dim3(NT), 0, s, W, Delta, deltaT,
+                       W, Wn, a, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
+}  // namespace dpt
