@@ -17,7 +17,11 @@ __device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned
 
 // Wave-wide max of (delta, |w|) plus a non-finite flag; lane 0 of every wave
 // publishes with one atomicMax per value (max is order-independent, so the
-// result is deterministic).  Must be reached by all 64 lanes of the wave.
+// result is deterministic).  The current value is read first (device scope,
+// past the non-coherent L1) and the atomic skipped when it cannot raise it:
+// the slot only grows during a launch, so a skipped update is never lost, and
+// kernels with 10^5-10^6 waves do not serialise on two addresses.  Must be
+// reached by all 64 lanes of the wave.
 __device__ __forceinline__ void publish_stats(unsigned long long *stat, double dmax, double wmax, bool bad) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -26,8 +30,9 @@ __device__ __forceinline__ void publish_stats(unsigned long long *stat, double d
     }
     const bool any_bad = __any(bad ? 1 : 0);
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(stat, any_bad ? kNanBits : dbits(dmax));
-        atomicMax(stat + 1, any_bad ? kNanBits : dbits(wmax));
+        const unsigned long long vd = any_bad ? kNanBits : dbits(dmax), vw = any_bad ? kNanBits : dbits(wmax);
+        if (vd > __hip_atomic_load(stat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(stat, vd);
+        if (vw > __hip_atomic_load(stat + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(stat + 1, vw);
     }
 }
 

@@ -758,21 +758,21 @@ int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, doub
     } else {
         dpt_options_default(&opt);
     }
-    std::vector<double> th((size_t)p->n);
-    if (p->mem == DPT_MEM_DEVICE) {
-        if (hipMemcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost) != hipSuccess)
-            return DPT_EDEVICE;
-    } else {
-        std::memcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n);
-    }
-    for (double v : th)
-        if (!std::isfinite(v)) return DPT_EINVAL;
-    if (index < 0) index = (int64_t)(std::max_element(th.begin(), th.end()) - th.begin());
     // the single-line map divides only by theta_index - theta_m: theta_index must
     // be simple, other values may coincide (Sec. II.H)
+    if (p->mem == DPT_MEM_DEVICE) {
+        double th_index = 0.0;
+        rc = dominant_theta_check_device(p->theta, p->n, &index, &th_index, (hipStream_t)p->stream);
+        if (rc != DPT_OK) return rc;
+        return dominant_solve(p, &opt, nullptr, th_index, index, eigval, eigvec, r);
+    }
+    const double *th = p->theta;
     for (int64_t m = 0; m < p->n; ++m)
-        if (m != index && th[(size_t)m] == th[(size_t)index]) return DPT_EINVAL;
-    return dominant_solve(p, &opt, th.data(), index, eigval, eigvec, r);
+        if (!std::isfinite(th[m])) return DPT_EINVAL;
+    if (index < 0) index = (int64_t)(std::max_element(th, th + p->n) - th);
+    for (int64_t m = 0; m < p->n; ++m)
+        if (m != index && th[m] == th[index]) return DPT_EINVAL;
+    return dominant_solve(p, &opt, th, th[index], index, eigval, eigvec, r);
 }
 
 int dpt_profile_enable(dpt_handle h, int on) {

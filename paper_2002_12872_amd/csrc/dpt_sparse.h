@@ -40,7 +40,16 @@ hipError_t sparse_residuals(SparseState *sp, double lambda, const double *theta,
                             const int64_t *rows, int64_t nrows, double *res, hipStream_t s);
 
 // Dominant-eigenvector mode: iterate the single-line map F_index from e_index.
-int dominant_solve(const dpt_problem *p, const dpt_options *o, const double *theta_host, int64_t index,
-                   double *eigval, void *eigvec, dpt_result *r);
+// theta_host: the host copy of theta for host inputs (uploaded), NULL for device
+// inputs (p->theta is used in place); theta_index = theta[index].
+int dominant_solve(const dpt_problem *p, const dpt_options *o, const double *theta_host, double theta_index,
+                   int64_t index, double *eigval, void *eigvec, dpt_result *r);
+
+// Checks of a device-resident theta for the dominant mode without copying it to
+// the host: all values finite and theta[*index] occurring once; *index < 0 is
+// replaced by the first index of the largest value.  *theta_index receives the
+// value.  Returns DPT_OK, DPT_EINVAL or a device error.
+int dominant_theta_check_device(const double *theta, int64_t n, int64_t *index, double *theta_index,
+                                hipStream_t s);
 
 }  // namespace dpt

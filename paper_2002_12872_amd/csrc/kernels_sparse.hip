@@ -399,6 +399,68 @@ __global__ void k_set_one(float *zf, double *zd, int64_t idx) {
     if (zd) zd[idx] = 1.0;
 }
 
+// Device-side theta checks of the dominant mode (device inputs, no copy of
+// theta to the host): finiteness, the index of the largest value when none is
+// given, and how often theta_index occurs.  Keys order doubles like integers.
+struct ThetaScan {
+    unsigned long long maxkey, index, count, bad, value_bits;
+};
+
+__device__ __forceinline__ unsigned long long order_key(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+
+__global__ void k_theta_scan_init(ThetaScan *sc, int64_t n, int64_t index) {
+    if (threadIdx.x == 0) {
+        sc->maxkey = 0ull;
+        sc->index = index >= 0 ? (unsigned long long)index : (unsigned long long)n;  // n: not found yet
+        sc->count = 0ull;
+        sc->bad = 0ull;
+        sc->value_bits = 0ull;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_theta_max(const double *__restrict__ theta, int64_t n, ThetaScan *sc) {
+    unsigned long long key = 0ull;
+    bool bad = false;
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x) {
+        const double t = theta[m];
+        bad |= !isfinite(t);
+        key = max(key, order_key(t));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) key = max(key, (unsigned long long)__shfl_xor((long long)key, o));
+    bad = __any(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&sc->maxkey, key);
+        if (bad) atomicOr(&sc->bad, 1ull);
+    }
+}
+
+// First index holding the maximum (only when no index was given).
+__global__ __launch_bounds__(256) void k_theta_argmax(const double *__restrict__ theta, int64_t n, ThetaScan *sc,
+                                                      int64_t index) {
+    if (index >= 0) return;
+    const unsigned long long target = sc->maxkey;
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x)
+        if (order_key(theta[m]) == target) atomicMin(&sc->index, (unsigned long long)m);
+}
+
+// Occurrences of theta_index (bitwise-equal values), and theta_index itself.
+__global__ __launch_bounds__(256) void k_theta_count(const double *__restrict__ theta, int64_t n, ThetaScan *sc) {
+    const unsigned long long idx = sc->index;
+    if (idx >= (unsigned long long)n) return;
+    const double t = theta[idx];
+    unsigned long long c = 0ull;
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x)
+        c += theta[m] == t ? 1ull : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += (unsigned long long)__shfl_xor((long long)c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&sc->count, c);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->value_bits = (unsigned long long)__double_as_longlong(t);
+}
+
 double bits_to_double(unsigned long long b) {
     double x;
     std::memcpy(&x, &b, sizeof(x));
@@ -703,15 +765,16 @@ hipError_t sparse_residuals(SparseState *sp, double lambda, const double *theta,
 namespace {
 
 template <typename T>
-int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_host, int64_t nstar, double *eigval,
-               void *eigvec, dpt_result *r) {
+int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_host, double theta_star,
+               int64_t nstar, double *eigval, void *eigvec, dpt_result *r) {
     const int64_t n = p->n;
     hipStream_t s = (hipStream_t)p->stream;
     int rc = DPT_OK;
     DevCsr<T> csr;
     T *val = nullptr, *dense = nullptr;
     T *z[2] = {nullptr, nullptr};
-    double *theta = nullptr, *s_dev = nullptr;
+    const double *theta = nullptr;
+    double *theta_own = nullptr, *s_dev = nullptr;
     unsigned long long *stats = nullptr;
     void *out_tmp = nullptr;
     const int cap = std::max(1, o->max_iter);
@@ -751,13 +814,19 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
                 if (e != hipSuccess) return e;
             }
         }
-        e = hipMalloc((void **)&theta, sizeof(double) * n);
-        if (e == hipSuccess) e = hipMalloc((void **)&s_dev, sizeof(double));
+        e = hipMalloc((void **)&s_dev, sizeof(double));
         if (e == hipSuccess) e = hipMalloc((void **)&stats, sizeof(unsigned long long) * 2 * (cap + 1));
         for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc((void **)&z[i], sizeof(T) * n);
         if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(theta, theta_host, sizeof(double) * n, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return e;
+        if (theta_host) {  // host inputs: upload theta; device inputs: borrow it
+            e = hipMalloc((void **)&theta_own, sizeof(double) * n);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(theta_own, theta_host, sizeof(double) * n, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return e;
+            theta = theta_own;
+        } else {
+            theta = p->theta;
+        }
         hipLaunchKernelGGL((k_zero<unsigned long long>), dim3(blocks_for(2 * (cap + 1), 256)), dim3(256), 0, s, stats,
                            (int64_t)2 * (cap + 1));
         hipLaunchKernelGGL((k_zero<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, z[0], n);
@@ -809,7 +878,7 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
         if (e == hipSuccess) e = hipMemcpyAsync(&sv, s_dev, sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
-        *eigval = theta_host[nstar] + p->lambda * sv;
+        *eigval = theta_star + p->lambda * sv;
         // eigenvector in the problem's dtype and memory kind
         const bool out64 = p->dtype == DPT_DTYPE_F64;
         const size_t ob = (size_t)n * (out64 ? 8 : 4);
@@ -836,7 +905,7 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
     if (val) (void)hipFree(val);
     for (int i = 0; i < 2; ++i)
         if (z[i]) (void)hipFree(z[i]);
-    if (theta) (void)hipFree(theta);
+    if (theta_own) (void)hipFree(theta_own);
     if (s_dev) (void)hipFree(s_dev);
     if (stats) (void)hipFree(stats);
     if (out_tmp) (void)hipFree(out_tmp);
@@ -855,10 +924,31 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
 
 }  // namespace
 
-int dominant_solve(const dpt_problem *p, const dpt_options *o, const double *theta_host, int64_t index,
-                   double *eigval, void *eigvec, dpt_result *r) {
-    if (o->precision == DPT_FP64) return dominant_t<double>(p, o, theta_host, index, eigval, eigvec, r);
-    return dominant_t<float>(p, o, theta_host, index, eigval, eigvec, r);
+int dominant_solve(const dpt_problem *p, const dpt_options *o, const double *theta_host, double theta_index,
+                   int64_t index, double *eigval, void *eigvec, dpt_result *r) {
+    if (o->precision == DPT_FP64) return dominant_t<double>(p, o, theta_host, theta_index, index, eigval, eigvec, r);
+    return dominant_t<float>(p, o, theta_host, theta_index, index, eigval, eigvec, r);
+}
+
+int dominant_theta_check_device(const double *theta, int64_t n, int64_t *index, double *theta_index, hipStream_t s) {
+    ThetaScan *sc = nullptr;
+    ThetaScan h{};
+    hipError_t e = hipMalloc((void **)&sc, sizeof(ThetaScan));
+    if (e != hipSuccess) return err_code(e);
+    const unsigned int g = blocks_for(n, 256, 1024);
+    hipLaunchKernelGGL(k_theta_scan_init, dim3(1), dim3(64), 0, s, sc, n, *index);
+    hipLaunchKernelGGL(k_theta_max, dim3(g), dim3(256), 0, s, theta, n, sc);
+    hipLaunchKernelGGL(k_theta_argmax, dim3(g), dim3(256), 0, s, theta, n, sc, *index);
+    hipLaunchKernelGGL(k_theta_count, dim3(g), dim3(256), 0, s, theta, n, sc);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, sc, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(sc);
+    if (e != hipSuccess) return err_code(e);
+    if (h.bad || h.index >= (unsigned long long)n || h.count != 1) return DPT_EINVAL;
+    *index = (int64_t)h.index;
+    *theta_index = bits_to_double(h.value_bits);
+    return DPT_OK;
 }
 
 }  // namespace dpt

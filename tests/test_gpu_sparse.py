@@ -161,19 +161,58 @@ def test_malformed_device_csr_is_rejected(bad, api):
     dpt.dpt_destroy(dpt.dpt_init(dpt.ProblemSpec(torch.from_numpy(theta).cuda(), good, 0.1)))
 
 
-def test_dominant_needs_only_theta_index_simple():
+@pytest.mark.parametrize("mem", ["host", "device"])
+def test_dominant_needs_only_theta_index_simple(mem):
     """The single-line map divides by theta_index - theta_m only (Sec. II.H):
-    repeated theta values elsewhere are accepted, a repeated theta_index is not."""
+    repeated theta values elsewhere are accepted, a repeated theta_index is not
+    (checked on the host, or by kernels for device-resident theta)."""
+    import torch
     n = 500
     theta, (ip, ix, v) = csr_problem(n, 7, np.float64)
     theta = theta.copy()
     theta[10] = theta[11]                       # a degenerate pair away from the index
-    spec = dpt.ProblemSpec(theta, (ip, ix, v), 1.0, stream=0)
+    if mem == "host":
+        spec = dpt.ProblemSpec(theta, (ip, ix, v), 1.0, stream=0)
+    else:
+        spec = dpt.ProblemSpec(torch.from_numpy(theta).cuda(), tuple(torch.from_numpy(a).cuda() for a in (ip, ix, v)),
+                               1.0)
     ev, vec, res = dpt.dpt_dominant(spec, dpt.options(tol=1e-14, max_iter=50, precision=dpt.DPT_FP64))
     assert res["status"] == dpt.DPT_OK
     ref = oracle.iterate(theta, (ip, ix, v), 1.0, rows=[n - 1], max_iter=50, tol=1e-14)
+    vec = vec.cpu().numpy() if hasattr(vec, "cpu") else vec
     assert abs(ev - ref["e"][0]) <= 1e-12 * abs(ref["e"][0])
     assert np.max(np.abs(vec - ref["z"][0])) <= 1e-12
     with pytest.raises(dpt.DptError) as ei:
         dpt.dpt_dominant(spec, index=10)
     assert ei.value.code == dpt.DPT_EINVAL
+    # an explicit index and a non-finite theta
+    ev2, _, _ = dpt.dpt_dominant(spec, dpt.options(tol=1e-14, max_iter=50, precision=dpt.DPT_FP64), index=200)
+    ref2 = oracle.iterate(theta, (ip, ix, v), 1.0, rows=[200], max_iter=50, tol=1e-14)
+    assert abs(ev2 - ref2["e"][0]) <= 1e-12 * abs(ref2["e"][0])
+    bad = theta.copy()
+    bad[7] = np.inf
+    if mem == "host":
+        spec_bad = dpt.ProblemSpec(bad, (ip, ix, v), 1.0, stream=0)
+    else:
+        spec_bad = dpt.ProblemSpec(torch.from_numpy(bad).cuda(),
+                                   tuple(torch.from_numpy(a).cuda() for a in (ip, ix, v)), 1.0)
+    with pytest.raises(dpt.DptError) as ei:
+        dpt.dpt_dominant(spec_bad)
+    assert ei.value.code == dpt.DPT_EINVAL
+
+
+@pytest.mark.slow
+def test_paper_scale_dominant_pair():
+    """Dominant pair of the 1.34e8-nonzero matrix (N = 2^22, the size of the
+    paper's Sec. II.H example) against the FP64 oracle row n - 1."""
+    import torch
+    n = 1 << 22
+    theta, ip, ix, v = workloads.sparse_sym(0, n=n)
+    spec = dpt.ProblemSpec(torch.from_numpy(theta).cuda(),
+                           tuple(torch.from_numpy(a).cuda() for a in (ip, ix, v)), 1.0)
+    ev, vec, res = dpt.dpt_dominant(spec, dpt.options(tol=1e-6, max_iter=50, precision=dpt.DPT_FP32))
+    assert res["status"] == dpt.DPT_OK and res["iters"] <= 6
+    ref = oracle.iterate(theta, (ip, ix, v.astype(np.float64)), 1.0, rows=[n - 1], max_iter=50, tol=1e-6)
+    assert abs(res["iters"] - ref["iters"]) <= 1
+    assert abs(ev - ref["e"][0]) <= 1e-6 * abs(ref["e"][0])
+    assert np.max(np.abs(vec.cpu().numpy() - ref["z"][0])) <= 1e-6
