@@ -32,6 +32,7 @@ METRIC = "DPT iter/s + TFLOP/s at N=16384 (bf16→fp32 vs fp32); solves/s, p50/p
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP8_TFLOPS = 5000.0
 CSRC = os.path.join(ROOT, "paper_2002_12872_amd", "csrc")
 # per fused product kernel: profile class, traffic summary, source file, peak
 KERNELS = {
@@ -504,6 +505,14 @@ def main():
     other_rule["speedup_bf16_fp32_vs_fp32"] = round(other_rule["fp32"]["ms_per_solve"] /
                                                     other_rule["bf16_fp32"]["ms_per_solve"], 3)
 
+    # ---- FP8 experiment: block-scaled E4M3 products until stall, then FP32 (same rule)
+    el8, rs8, hs8, prof8, e_fp8 = timed_solves(dpt, spec, opts(dpt.DPT_FP8_FP32, rule), n, 1, 1)
+    g8 = prof8.get("gemm_fp8", (float("nan"), 1))
+    fp8 = {"ms_per_solve": round(1e3 * el8, 2), "iters": [rs8[0]["iters_bf16"], rs8[0]["iters_fp32"]],
+           "gemm_fp8_ms": round(g8[0] / max(g8[1], 1), 4),
+           "gemm_fp8_tflops": round(flop / (g8[0] / max(g8[1], 1) * 1e-3) / 1e12, 2),
+           "frac_fp8_peak": round(flop / (g8[0] / max(g8[1], 1) * 1e-3) / 1e12 / PEAK_FP8_TFLOPS, 4)}
+
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_solve, 3),
@@ -524,6 +533,7 @@ def main():
         "fp32": fp32,
         "speedup_vs_fp32": (round(fp32["ms_per_solve"] / ms_per_solve, 3) if fp32 else None),
         "other_stop_rule": {"rule": other, **other_rule},
+        "fp8_fp32_experiment": fp8,
     }
 
     # ---- FP64 oracle on 64 sampled rows: converged reference and CPU baseline
@@ -549,8 +559,9 @@ def main():
         err["bf16_fp32"]["residual_rel"] = float(np.max(res / norm_ub))
         if f_handles:
             err["fp32"] = accuracy(dpt, f_handles[-1], e_fp32, theta, ref, rows, z_scale)
+        err["fp8_fp32"] = accuracy(dpt, hs8[-1], e_fp8, theta, ref, rows, z_scale)
         out["error_vs_fp64_oracle"] = err
-    for h in handles + f_handles:
+    for h in handles + f_handles + hs8:
         dpt.dpt_destroy(h)
     if args.serve_requests > 0:
         print("# serving trace of %d requests" % args.serve_requests, file=sys.stderr, flush=True)

@@ -53,7 +53,9 @@ bool valid_options(const dpt_options *o) {
     if (!o) return true;
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return false;
     if (o->max_iter < 0) return false;
-    if (o->precision != DPT_FP64 && o->precision != DPT_FP32 && o->precision != DPT_BF16_FP32) return false;
+    if (o->precision != DPT_FP64 && o->precision != DPT_FP32 && o->precision != DPT_BF16_FP32 &&
+        o->precision != DPT_FP8_FP32)
+        return false;
     if (!(o->fp64_final_tol >= 0.0) || !std::isfinite(o->fp64_final_tol)) return false;
     if (!(o->stall_ratio >= 0.0) || !(o->stall_ratio <= 1.0)) return false;
     if (o->stall_patience < 1 || o->check_every < 1) return false;
@@ -209,6 +211,10 @@ struct dpt_ctx {
     __bf16 *db16 = nullptr;
     bool d32_own = false, d64_own = false;
 
+    // block-scaled FP8 copies (DPT_FP8_FP32): values and E8M0 scales per 32 values
+    unsigned char *dq8 = nullptr, *ds8 = nullptr;
+    unsigned char *Wq8[2] = {nullptr, nullptr}, *Ws8[2] = {nullptr, nullptr};
+
     // state
     float *W32[2] = {nullptr, nullptr};
     __bf16 *Wb[2] = {nullptr, nullptr};
@@ -223,7 +229,8 @@ struct dpt_ctx {
 
     ~dpt_ctx() {
         if (sp) sparse_destroy(sp);
-        void *own[] = {theta, dvec, evec, stats, db16, W32[0], W32[1], Wb[0], Wb[1], W64[0], W64[1]};
+        void *own[] = {theta, dvec, evec, stats, db16, W32[0], W32[1], Wb[0], Wb[1], W64[0], W64[1],
+                       dq8, ds8, Wq8[0], Wq8[1], Ws8[0], Ws8[1]};
         for (void *p : own)
             if (p) (void)hipFree(p);
         if (dT32 && dT32 != d32) (void)hipFree(dT32);
@@ -348,10 +355,13 @@ int dense_step(dpt_ctx *c) {
     if (c->at_identity) {
         DPT_TRY(launch_zero_u64(st, 2, s));
         pf.begin(DPT_PROF_FIRST, s);
+        const bool fp8 = c->phase == PH_BF16 && c->opt.precision == DPT_FP8_FP32;
         if (c->phase == PH_FP64)
             e = launch_first_iterate_f64(a, c->dT64, c->W64[nx], s);
         else
-            e = launch_first_iterate_f32(a, c->dT32, c->W32[nx], c->phase == PH_BF16 ? c->Wb[nx] : nullptr, s);
+            e = launch_first_iterate_f32(a, c->dT32, c->W32[nx], c->phase == PH_BF16 && !fp8 ? c->Wb[nx] : nullptr,
+                                         s);
+        if (e == hipSuccess && fp8) e = launch_quant_fp8(c->W32[nx], c->ld, c->Wq8[nx], c->Ws8[nx], s);
         pf.end(s);
         DPT_TRY(e);
     } else {
@@ -368,6 +378,10 @@ int dense_step(dpt_ctx *c) {
         } else if (c->phase == PH_FP32) {
             pf.begin(DPT_PROF_GEMM_FP32, s);
             e = launch_step_f32(a, c->W32[c->cur], c->d32, c->dT32, c->W32[nx], nullptr, s);
+        } else if (c->opt.precision == DPT_FP8_FP32) {
+            pf.begin(DPT_PROF_GEMM_FP8, s);
+            e = launch_step_fp8_large(a, c->Wq8[c->cur], c->Ws8[c->cur], c->dq8, c->ds8, c->dT32, c->W32[c->cur],
+                                      c->W32[nx], c->Wq8[nx], c->Ws8[nx], s);
         } else {
             pf.begin(DPT_PROF_GEMM_BF16, s);
             e = launch_step_bf16(a, c->Wb[c->cur], c->db16, c->dT32, c->W32[c->cur], c->W32[nx], c->Wb[nx], s);
@@ -478,12 +492,23 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
                 DPT_TRY(launch_fill_zero(c->Wb[i], nn * 2, s));
             }
             c->phase = PH_BF16;
+        } else if (prec == DPT_FP8_FP32) {
+            DPT_TRY(dalloc(&c->dq8, nn));
+            DPT_TRY(dalloc(&c->ds8, nn / 32));
+            DPT_TRY(launch_quant_fp8(c->d32, ld, c->dq8, c->ds8, s));
+            for (int i = 0; i < 2; ++i) {
+                DPT_TRY(dalloc(&c->Wq8[i], nn));
+                DPT_TRY(dalloc(&c->Ws8[i], nn / 32));
+                DPT_TRY(launch_quant_fp8(c->W32[i], ld, c->Wq8[i], c->Ws8[i], s));  // of the zero state
+            }
+            c->phase = PH_BF16;  // the reduced-precision phase
         } else {
             c->phase = PH_FP32;
         }
         if (z0) {
             DPT_TRY(launch_load_state_f32(c->W32[0], z0, p->dtype == DPT_DTYPE_F64, c->n, ld, s));
-            if (c->phase == PH_BF16) DPT_TRY(launch_cvt_f32_to_bf16(c->Wb[0], c->W32[0], (int64_t)nn, s));
+            if (prec == DPT_BF16_FP32) DPT_TRY(launch_cvt_f32_to_bf16(c->Wb[0], c->W32[0], (int64_t)nn, s));
+            if (prec == DPT_FP8_FP32) DPT_TRY(launch_quant_fp8(c->W32[0], ld, c->Wq8[0], c->Ws8[0], s));
             c->at_identity = false;
         }
     }
@@ -551,6 +576,9 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
     int rc = dpt_validate(p, o);
     if (rc != DPT_OK) return rc;
     if (p->format == DPT_CSR && z0) return DPT_EINVAL;  // warm start: dense problems only
+    if (o && o->precision == DPT_FP8_FP32 &&
+        (p->format != DPT_DENSE || !step_large_supported(pad_order(p->n))))
+        return DPT_EINVAL;  // the FP8 product exists for large dense problems only
     rc = check_device();
     if (rc != DPT_OK) return rc;
     if (!device_inputs_ok(p, z0)) return DPT_EINVAL;

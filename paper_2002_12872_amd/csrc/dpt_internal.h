@@ -87,6 +87,15 @@ hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __b
                                   const float *W, float *Wn, __bf16 *Wbn, hipStream_t s);
 hipError_t launch_step_f32_large(const StepArgs &a, const float *W, const float *Delta, const float *deltaT,
                                  float *Wn, hipStream_t s);
+// FP8 step (large problems only): A = block-scaled FP8 copy of W (Wq values,
+// Ws E8M0 scales per 32 values of a row), B = the same of Delta; epilogue in
+// FP32 with W; writes W' (FP32) and its FP8 copy (Wqn, Wsn).
+hipError_t launch_step_fp8_large(const StepArgs &a, const unsigned char *Wq, const unsigned char *Ws,
+                                 const unsigned char *Dq, const unsigned char *Ds, const float *deltaT, const float *W,
+                                 float *Wn, unsigned char *Wqn, unsigned char *Wsn, hipStream_t s);
+// Block-scaled FP8 copy (E4M3 values, E8M0 scale per 32 values) of an FP32
+// ld x ld matrix; ld a multiple of 32.
+hipError_t launch_quant_fp8(const float *src, int64_t ld, unsigned char *q, unsigned char *sc, hipStream_t s);
 hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta, const float *deltaT,
                            float *Wn, __bf16 *Wbn, hipStream_t s);
 hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT,

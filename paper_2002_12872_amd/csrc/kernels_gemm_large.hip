@@ -6,7 +6,9 @@
 //     C  = Delta^T + W Delta^T                               (MFMA, FP32 accumulate)
 //     W' = lambda (C - d_n W) / (theta_n - theta_m),  m != n  (FP32 epilogue, FP64 gaps)
 // plus max|W' - W| and max|W'| for the stopping rule.  The BF16 step multiplies
-// bf16(W) bf16(Delta)^T and also writes the BF16 shadow of W'.
+// bf16(W) bf16(Delta)^T and also writes the BF16 shadow of W'; the FP8 step
+// multiplies block-scaled FP8 copies (OCP E4M3 values, one E8M0 power-of-two
+// scale per 32 consecutive values of a row) and writes the FP8 copy of W'.
 //
 // Shared structure.  A 256 x 256 output tile per workgroup of 4 waves (one per
 // SIMD); each wave owns a 128 x 128 wave tile as 4 x 4 blocks of 32 x 32 MFMA
@@ -20,6 +22,8 @@
 // chunk fall on disjoint banks.  The epilogue stages the accumulators through
 // the freed LDS.
 #include <float.h>
+
+#include <algorithm>
 
 #include "device_common.h"
 #include "dpt_internal.h"
@@ -95,11 +99,40 @@ struct TileLoader {
 // C[(r & 3) + 4 (l >> 5) + 8 (r >> 2)][l & 31]) go through LDS in two passes of
 // 128 tile rows; then thread t updates columns c4..c4+3 (c4 = 4 (t & 63)) of
 // rows (t >> 6) + 4k, with the global loads of 8 rows issued before any use.
-template <bool WRITE_BF16>
+// Block-scaled FP8 (OCP E4M3) quantisation of 32 consecutive values held 4 per
+// lane by 8 consecutive lanes: the E8M0 scale 2^X is the smallest power of two
+// with amax <= 448 * 2^X (448 = 0.875 * 2^9, the largest E4M3 value), so with
+// amax = f 2^e, f in [0.5, 1): X = e - 9 if f <= 0.875, else e - 8 (clamped to
+// the E8M0 range).  Values v / 2^X are rounded to nearest-even E4M3 by the
+// hardware conversion (clamped to +-448 first: the conversion does not
+// saturate).  Returns the 4 FP8 bytes packed in one word; *scale gets X + 127.
+__device__ __forceinline__ unsigned quant_fp8_x4(const float v[4], unsigned *scale) {
+    float amax = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+    amax = fmaxf(amax, __shfl_xor(amax, 1));
+    amax = fmaxf(amax, __shfl_xor(amax, 2));
+    amax = fmaxf(amax, __shfl_xor(amax, 4));
+    int e = 0;
+    const float f = frexpf(amax, &e);
+    int x = amax > 0.0f ? (f <= 0.875f ? e - 9 : e - 8) : -127;
+    x = min(max(x, -127), 127);
+    float q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = fminf(fmaxf(ldexpf(v[k], -x), -448.0f), 448.0f);
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], w, true);
+    *scale = (unsigned)(x + 127);
+    return (unsigned)w;
+}
+
+// Output forms of the shared epilogue.
+enum EpiOut { EPI_F32 = 0, EPI_BF16 = 1, EPI_FP8 = 2 };
+
+template <int OUT>
 __device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[TM][TN], const float *__restrict__ deltaT,
                                          const float *__restrict__ Wold, float *__restrict__ Wnew,
-                                         __bf16 *__restrict__ Wbnew, const StepArgs &a, int64_t row0, int64_t col0,
-                                         int tid, int lane, int wave, int wr, int wc) {
+                                         __bf16 *__restrict__ Wbnew, unsigned char *__restrict__ Wqnew,
+                                         unsigned char *__restrict__ Wsnew, const StepArgs &a, int64_t row0,
+                                         int64_t col0, int tid, int lane, int wave, int wr, int wc) {
     float *tile = reinterpret_cast<float *>(smem);
     constexpr int TP = EPI_PITCH, EU = 8;
     const int64_t ld = a.ld;
@@ -157,11 +190,16 @@ __device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[
                     bad |= !(dv <= DBL_MAX) || !(av <= DBL_MAX);
                 }
                 __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(&Wnew[idx]));
-                if (WRITE_BF16) {
+                if (OUT == EPI_BF16) {
                     const __bf16 b4[4] = {(__bf16)w[0], (__bf16)w[1], (__bf16)w[2], (__bf16)w[3]};
                     uint2 packed;
                     __builtin_memcpy(&packed, b4, sizeof(packed));
                     *reinterpret_cast<uint2 *>(&Wbnew[idx]) = packed;
+                } else if (OUT == EPI_FP8) {  // 8 lanes = the 32 columns of one scale block
+                    const float v4[4] = {w[0], w[1], w[2], w[3]};
+                    unsigned sc;
+                    *reinterpret_cast<unsigned *>(&Wqnew[idx]) = quant_fp8_x4(v4, &sc);
+                    if ((lane & 7) == 0) Wsnew[n * (ld / 32) + m0 / 32] = (unsigned char)sc;
                 }
             }
         }
@@ -270,7 +308,7 @@ __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict
 #undef DPT_INTERLEAVE
 #undef DPT_MMA
 #undef DPT_FRAGS
-    epilogue<true>(smem, acc, deltaT, Wold, Wnew, Wbnew, a, row0, col0, tid, lane, wave, wr, wc);
+    epilogue<EPI_BF16>(smem, acc, deltaT, Wold, Wnew, Wbnew, nullptr, nullptr, a, row0, col0, tid, lane, wave, wr, wc);
 }
 
 // ---------------------------------------------------------------------------
@@ -346,7 +384,144 @@ __global__ __launch_bounds__(NT) void k_step_f32_large(const float *__restrict__
     }
 #undef DPT_MMA32
 #undef DPT_FRAGS32
-    epilogue<false>(smem, acc, deltaT, Wold, Wnew, nullptr, a, row0, col0, tid, lane, wave, wr, wc);
+    epilogue<EPI_F32>(smem, acc, deltaT, Wold, Wnew, nullptr, nullptr, nullptr, a, row0, col0, tid, lane, wave, wr, wc);
+}
+
+// ---------------------------------------------------------------------------
+// FP8 step with the block-scaled v_mfma_scale_f32_32x32x64_f8f6f4 (E4M3 x E4M3,
+// FP32 accumulate).  A K-tile is 128 values (one 128-byte line per row) plus
+// the row's four E8M0 scales (one 4-byte word per row, kept after the A and B
+// tiles of the stage).  Operand layout of one 64-value MFMA window: lane (r, g)
+// (r = lane & 31, g = lane >> 5) holds values 16g .. 16g + 15 and 32 + 16g ..
+// 32 + 16g + 15 of row r (chunks g and 2 + g of the window), and supplies the
+// scale of its row's 32-value block g; each scale multiplies the values of its
+// (row, block) wherever they sit.  The two windows of a K-tile go to two
+// register sets, scheduled like the BF16 step's halves.
+constexpr int STAGE8 = STAGE + (BM + BN) * 4;  // + 4 scale bytes per row
+constexpr int LOADS8 = LOADS + 2;
+static_assert(2 * STAGE8 <= SMEM, "two FP8 stages fit the epilogue tile");
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(NT) void k_step_fp8_large(const unsigned char *__restrict__ Aq,
+                                                       const unsigned char *__restrict__ As,
+                                                       const unsigned char *__restrict__ Bq,
+                                                       const unsigned char *__restrict__ Bs,
+                                                       const float *__restrict__ deltaT, const float *__restrict__ Wold,
+                                                       float *__restrict__ Wnew, unsigned char *__restrict__ Wqnew,
+                                                       unsigned char *__restrict__ Wsnew, StepArgs a, int tiles_m,
+                                                       int tiles_n) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+    int tm, tn;
+    tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+    const int64_t ldsc = a.ld / 32;             // scale bytes per row
+    const int ktiles = (int)(a.ld / ROW);        // a multiple of 2
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave / WN, wc = wave % WN;
+    TileLoader ld;
+    ld.init(Aq, Bq, row0, col0, a.ld, wave, lane);
+    // scale words: wave w loads rows 64w + lane of A and of B (4 bytes each)
+    const unsigned char *gsa = As + (row0 + 64 * wave + lane) * ldsc, *gsb = Bs + (col0 + 64 * wave + lane) * ldsc;
+    auto issue8 = [&](int kt, int slot) {
+        ld.issue(smem + slot * (STAGE8 - STAGE), kt, slot);  // tiles at smem + slot * STAGE8
+        unsigned char *sc = smem + slot * STAGE8 + STAGE + 64 * wave * 4;
+        __builtin_amdgcn_global_load_lds((gbl_void *)(gsa + 4 * kt), (lds_void *)sc, 4, 0, 0);
+        __builtin_amdgcn_global_load_lds((gbl_void *)(gsb + 4 * kt), (lds_void *)(sc + BM * 4), 4, 0, 0);
+    };
+
+    floatx16_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    const int fr = lane & 31, fg = lane >> 5;
+    const int ra = wr * WTM + fr, rb = wc * WTN + fr;
+    const int a_base = ra * ROW + ((fg ^ key8(ra)) << 4);
+    const int b_base = BM * ROW + rb * ROW + ((fg ^ key8(rb)) << 4);
+    i32x8 fa0[TM], fb0[TN], fa1[TM], fb1[TN];
+    int sa0[TM], sb0[TN], sa1[TM], sb1[TN];
+    // Fragments and scales of window W of the K-tile in SLOT: chunks 4W + fg and
+    // 4W + 2 + fg of the lane's row; scale byte 2W + fg of the row's word.
+#define DPT_FRAGS8(FA, FB, SA, SB, SLOT, W)                                                                          \
+    do {                                                                                                             \
+        const unsigned char *sb_ = smem + (SLOT) * STAGE8;                                                           \
+        _Pragma("unroll") for (int i_ = 0; i_ < TM; ++i_) {                                                          \
+            const int o_ = a_base + i_ * 32 * ROW, x_ = ((i_ & 1) << 2) ^ (4 * (W));                                 \
+            const u32x4_t lo_ = *reinterpret_cast<const u32x4_t *>(sb_ + (o_ ^ (x_ << 4)));                          \
+            const u32x4_t hi_ = *reinterpret_cast<const u32x4_t *>(sb_ + (o_ ^ ((x_ ^ 2) << 4)));                    \
+            FA[i_] = i32x8{(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                                       \
+                           (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};                                      \
+            SA[i_] = (int)((*reinterpret_cast<const unsigned *>(sb_ + STAGE + 4 * (ra + 32 * i_)) >>                 \
+                            (8 * (2 * (W) + fg))) & 0xffu);                                                          \
+        }                                                                                                            \
+        _Pragma("unroll") for (int j_ = 0; j_ < TN; ++j_) {                                                          \
+            const int o_ = b_base + j_ * 32 * ROW, x_ = ((j_ & 1) << 2) ^ (4 * (W));                                 \
+            const u32x4_t lo_ = *reinterpret_cast<const u32x4_t *>(sb_ + (o_ ^ (x_ << 4)));                          \
+            const u32x4_t hi_ = *reinterpret_cast<const u32x4_t *>(sb_ + (o_ ^ ((x_ ^ 2) << 4)));                    \
+            FB[j_] = i32x8{(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                                       \
+                           (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};                                      \
+            SB[j_] = (int)((*reinterpret_cast<const unsigned *>(sb_ + STAGE + BM * 4 + 4 * (rb + 32 * j_)) >>        \
+                            (8 * (2 * (W) + fg))) & 0xffu);                                                          \
+        }                                                                                                            \
+    } while (0)
+#define DPT_MMA8(FA, FB, SA, SB, I0)                                                                                 \
+    do {                                                                                                             \
+        _Pragma("unroll") for (int i_ = (I0); i_ < (I0) + 2; ++i_) _Pragma("unroll") for (int j_ = 0; j_ < TN; ++j_) \
+            acc[i_][j_] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(FA[i_], FB[j_], acc[i_][j_], 0, 0, 0,      \
+                                                                          SA[i_], 0, SB[j_]);                        \
+    } while (0)
+
+    issue8(0, 0);
+    issue8(1, 1);
+    wait_vmcnt<LOADS8>();
+    barrier_keep_loads();
+    DPT_FRAGS8(fa0, fb0, sa0, sb0, 0, 0);
+    for (int kt = 0; kt < ktiles - 1; ++kt) {
+        const int slot = kt & 1;
+        DPT_MMA8(fa0, fb0, sa0, sb0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA8(fa0, fb0, sa0, sb0, 2);
+        DPT_FRAGS8(fa1, fb1, sa1, sb1, slot, 1);
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA8(fa1, fb1, sa1, sb1, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        // every fragment of tile kt is in registers; tile kt+1 must have landed
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        wait_vmcnt<0>();
+        barrier_keep_loads();
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA8(fa1, fb1, sa1, sb1, 2);
+        issue8(min(kt + 2, ktiles - 1), slot);  // past the end: the last tile again, never read
+        DPT_FRAGS8(fa0, fb0, sa0, sb0, slot ^ 1, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    DPT_MMA8(fa0, fb0, sa0, sb0, 0);
+    DPT_MMA8(fa0, fb0, sa0, sb0, 2);
+    DPT_FRAGS8(fa1, fb1, sa1, sb1, (ktiles - 1) & 1, 1);
+    DPT_MMA8(fa1, fb1, sa1, sb1, 0);
+    DPT_MMA8(fa1, fb1, sa1, sb1, 2);
+    wait_vmcnt<0>();
+#undef DPT_MMA8
+#undef DPT_FRAGS8
+    epilogue<EPI_FP8>(smem, acc, deltaT, Wold, Wnew, nullptr, Wqnew, Wsnew, a, row0, col0, tid, lane, wave, wr, wc);
+}
+
+// Block-scaled FP8 copy of an FP32 ld x ld matrix (rows of the padded layout);
+// thread t quantises 4 consecutive values, 8 lanes one 32-value block.
+__global__ __launch_bounds__(256) void k_quant_fp8(const float *__restrict__ src, int64_t ld,
+                                                   unsigned char *__restrict__ q, unsigned char *__restrict__ sc) {
+    const int64_t quads = ld * ld / 4;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < quads; t += (int64_t)gridDim.x * blockDim.x) {
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(src + 4 * t);
+        const float v4[4] = {v[0], v[1], v[2], v[3]};
+        unsigned s;
+        *reinterpret_cast<unsigned *>(q + 4 * t) = quant_fp8_x4(v4, &s);
+        if ((threadIdx.x & 7) == 0) sc[t / 8] = (unsigned char)s;
+    }
 }
 
 }  // namespace
@@ -359,6 +534,24 @@ hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __b
     const int tiles_m = (int)(a.ld / BM), tiles_n = (int)(a.ld / BN);
     hipLaunchKernelGGL(k_step_bf16_large, dim3((unsigned int)(tiles_m * tiles_n)), dim3(NT), 0, s, Wb, Deltab,
                        deltaT, W, Wn, Wbn, a, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_fp8_large(const StepArgs &a, const unsigned char *Wq, const unsigned char *Ws,
+                                 const unsigned char *Dq, const unsigned char *Ds, const float *deltaT, const float *W,
+                                 float *Wn, unsigned char *Wqn, unsigned char *Wsn, hipStream_t s) {
+    if (!step_large_supported(a.ld)) return hipErrorInvalidValue;
+    const int tiles_m = (int)(a.ld / BM), tiles_n = (int)(a.ld / BN);
+    hipLaunchKernelGGL(k_step_fp8_large, dim3((unsigned int)(tiles_m * tiles_n)), dim3(NT), 0, s, Wq, Ws, Dq, Ds,
+                       deltaT, W, Wn, Wqn, Wsn, a, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_quant_fp8(const float *src, int64_t ld, unsigned char *q, unsigned char *sc, hipStream_t s) {
+    if (ld % 32 != 0) return hipErrorInvalidValue;
+    const int64_t quads = ld * ld / 4;
+    const int64_t blocks = std::min<int64_t>((quads + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(k_quant_fp8, dim3((unsigned int)blocks), dim3(256), 0, s, src, ld, q, sc);
     return hipGetLastError();
 }
 
