@@ -84,7 +84,8 @@ def serving_bench(args):
     """Continuous batching vs one-at-a-time FP32 solves on the serving trace.
 
     Trace: N log-uniform in [32, 2048], half symmetric, theta_i = i + U(0, 0.5),
-    Delta ~ N(0, (0.4/sqrt N)^2), tol 1e-5, BF16->FP32 in the engine.  The
+    Delta ~ N(0, (0.4/sqrt N)^2), tol 1e-5, BF16->FP32 in the engine (tile
+    shapes of the grouped step chosen by the autotuner when it opens).  The
     one-at-a-time FP32 service rate mu_1 is measured first on the trace's
     problems; arrivals are Poisson at rate mu_1.  Engine latencies come from its
     own submit/finish timestamps; the one-at-a-time latencies from its measured
@@ -126,7 +127,8 @@ def serving_bench(args):
             "mean_service_ms": round(1e3 * svc.mean(), 3), "converged": int(ok)}
     def engine_run(arr):
         """Engine in real time on the arrival times arr (None: all at t = 0)."""
-        srv = dpt.dpt_serve_open(int(args.serve_budget_gib * (1 << 30)), max_slots=1024, use_graph=True)
+        srv = dpt.dpt_serve_open(int(args.serve_budget_gib * (1 << 30)), max_slots=1024, use_graph=True,
+                                 autotune=True)
         tickets = []
         t0 = time.perf_counter()
         for i, sp in enumerate(specs):
@@ -144,7 +146,8 @@ def serving_bench(args):
                 "p99_ms": round(1e3 * percentile(lat, 99), 3),
                 "converged": int(sum(r["status"] == dpt.DPT_OK for r in res)),
                 "steps": st["steps"], "peak_active": st["peak_active"],
-                "peak_arena_gib": round(st["peak_bytes"] / 2 ** 30, 3)}
+                "peak_arena_gib": round(st["peak_bytes"] / 2 ** 30, 3),
+                "tile128_min_ld_bf16_fp32": st["tile128_min_ld"]}
 
     def base_at(rate_mult):
         arr = arrivals / rate_mult

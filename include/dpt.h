@@ -235,7 +235,9 @@ typedef struct dpt_serve_config {
     int32_t max_slots;      /* concurrent problems, 1 .. 1024                         */
     int32_t use_graph;      /* 1: replay the grouped step as a HIP graph              */
     int32_t grid_blocks;    /* persistent grid of the grouped kernels; 0 = 1024       */
-    int32_t reserved;       /* must be 0                                              */
+    int32_t autotune;       /* 1: time 64x64 against 128x128 fused-step tiles per     *
+                             * phase and size at open and keep the faster; 0: 128x128 *
+                             * tiles from padded order 1024 up                       */
 } dpt_serve_config;
 
 /* Seconds since dpt_serve_open on a monotonic clock. */
@@ -248,6 +250,8 @@ typedef struct dpt_serve_stats {
     int64_t peak_active, peak_bytes;       /* largest concurrent set and arena use  */
     int64_t active, pending;               /* current counts                        */
     double busy_s;                         /* wall time spent inside engine steps   */
+    int64_t tile128_min_ld[2];             /* smallest padded order run with 128x128 *
+                                            * tiles in the BF16 / FP32 phase; -1: none */
 } dpt_serve_stats;
 
 /* Start a server on the current device (creates its own stream).  Returns

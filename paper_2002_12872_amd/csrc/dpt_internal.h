@@ -134,22 +134,26 @@ struct GroupReq {
 constexpr int kServeMaxSlots = 1024;
 
 // Work lists of one serving step, rewritten by the host before every step.
-// counts = {requests, BF16-phase requests, FP32-phase requests}; prefix arrays
-// hold running sums of rows (pre-pass) and of 64x64 tiles (step kernels).
+// The fused-step work is split into kGroupLists lists by (phase, tile edge):
+// list 2 * (phase == PH_FP32) + (tile == 128).  counts[0] = requests,
+// counts[1 + L] = requests in list L; prefix arrays hold running sums of rows
+// (pre-pass) and of output tiles (step kernels).
+constexpr int kGroupLists = 4;
+inline int group_list(int phase, int tile) { return 2 * (phase == PH_FP32 ? 1 : 0) + (tile == 128 ? 1 : 0); }
+
 struct GroupTable {
-    int32_t counts[4];
+    int32_t counts[1 + kGroupLists];
     int32_t pre_prefix[kServeMaxSlots + 1];
-    int32_t bf_idx[kServeMaxSlots];
-    int32_t bf_prefix[kServeMaxSlots + 1];
-    int32_t fp_idx[kServeMaxSlots];
-    int32_t fp_prefix[kServeMaxSlots + 1];
+    int32_t idx[kGroupLists][kServeMaxSlots];
+    int32_t prefix[kGroupLists][kServeMaxSlots + 1];
     GroupReq reqs[kServeMaxSlots];
 };
 
 // Persistent grouped launches with a fixed grid (graph-capturable): the
 // pre-pass (also clears each request's stats) and the fused step for the
-// requests in one phase (PH_BF16 or PH_FP32).
+// requests of one phase (PH_BF16 or PH_FP32) with one tile edge (64 or 128;
+// 128 needs ld % 128 == 0).
 hipError_t launch_group_prepass(const GroupTable *t, int grid, hipStream_t s);
-hipError_t launch_group_step(const GroupTable *t, int phase, int grid, hipStream_t s);
+hipError_t launch_group_step(const GroupTable *t, int phase, int tile, int grid, hipStream_t s);
 
 }  // namespace dpt

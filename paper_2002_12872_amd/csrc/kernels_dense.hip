@@ -434,18 +434,19 @@ __global__ __launch_bounds__(256) void k_group_prepass(const GroupTable *__restr
     }
 }
 
-// One 64x64 output tile of one request per work item; blocks stride over the
-// items of every request in the phase (persistent grid, fixed size).
-template <int PHASE>
+// One TILE x TILE output tile of one request per work item; blocks stride over
+// the items of every request in the list (persistent grid, fixed size).
+template <int PHASE, int TILE>
 __global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict__ t) {
-    const int cnt = PHASE == PH_BF16 ? t->counts[1] : t->counts[2];
-    const int32_t *idx = PHASE == PH_BF16 ? t->bf_idx : t->fp_idx;
-    const int32_t *prefix = PHASE == PH_BF16 ? t->bf_prefix : t->fp_prefix;
+    constexpr int L = 2 * (PHASE == PH_FP32 ? 1 : 0) + (TILE == 128 ? 1 : 0);
+    const int cnt = t->counts[1 + L];
+    const int32_t *idx = t->idx[L];
+    const int32_t *prefix = t->prefix[L];
     const int total = cnt > 0 ? prefix[cnt] : 0;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int j = find_segment(prefix, cnt, item);
         const GroupReq &q = t->reqs[idx[j]];
-        const int tpr = (int)(q.ld / 64);
+        const int tpr = (int)(q.ld / TILE);
         const int local = item - prefix[j];
         const int tm = local / tpr, tn = local - tm * tpr;
         StepArgs a;
@@ -456,9 +457,9 @@ __global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict
         a.d = q.d;
         a.stat = q.stat;
         if (PHASE == PH_BF16)
-            step_tile<PolBF16, 64, 64, 32, 2, 2, float>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
+            step_tile<PolBF16, TILE, TILE, 32, 2, 2, float>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
         else
-            step_tile<PolF32, 64, 64, 16, 2, 2, float>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a, tm, tn);
+            step_tile<PolF32, TILE, TILE, 16, 2, 2, float>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a, tm, tn);
     }
 }
 
@@ -678,11 +679,16 @@ hipError_t launch_group_prepass(const GroupTable *t, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_group_step(const GroupTable *t, int phase, int grid, hipStream_t s) {
-    if (phase == PH_BF16)
-        hipLaunchKernelGGL(k_group_step<PH_BF16>, dim3((unsigned int)grid), dim3(256), 0, s, t);
+hipError_t launch_group_step(const GroupTable *t, int phase, int tile, int grid, hipStream_t s) {
+    if (tile != 64 && tile != 128) return hipErrorInvalidValue;
+    if (phase == PH_BF16 && tile == 64)
+        hipLaunchKernelGGL((k_group_step<PH_BF16, 64>), dim3((unsigned int)grid), dim3(256), 0, s, t);
+    else if (phase == PH_BF16)
+        hipLaunchKernelGGL((k_group_step<PH_BF16, 128>), dim3((unsigned int)grid), dim3(256), 0, s, t);
+    else if (phase == PH_FP32 && tile == 64)
+        hipLaunchKernelGGL((k_group_step<PH_FP32, 64>), dim3((unsigned int)grid), dim3(256), 0, s, t);
     else if (phase == PH_FP32)
-        hipLaunchKernelGGL(k_group_step<PH_FP32>, dim3((unsigned int)grid), dim3(256), 0, s, t);
+        hipLaunchKernelGGL((k_group_step<PH_FP32, 128>), dim3((unsigned int)grid), dim3(256), 0, s, t);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -130,6 +132,9 @@ struct dpt_server_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::chrono::steady_clock::time_point t0;
+    // smallest padded order that uses 128 x 128 tiles, per phase (BF16, FP32);
+    // set by the autotuner at open, else the defaults below
+    int64_t min_ld_128[2] = {1024, 1024};
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -159,11 +164,107 @@ struct dpt_server_ctx {
     }
 
     // ------------------------------------------------------------ worker
+    // The launches of one engine step: the pre-pass and the fused step for every
+    // (phase, tile) list; lists without work exit at once.
+    hipError_t launch_all(hipStream_t s) const {
+        hipError_t e = launch_group_prepass(table_d, grid, s);
+        for (int ph : {PH_BF16, PH_FP32})
+            for (int tile : {64, 128})
+                if (e == hipSuccess) e = launch_group_step(table_d, ph, tile, grid, s);
+        return e;
+    }
+
     hipError_t launch_grouped() {
         if (cfg.use_graph) return hipGraphLaunch(graph_exec, stream);
-        hipError_t e = launch_group_prepass(table_d, grid, stream);
-        if (e == hipSuccess) e = launch_group_step(table_d, PH_BF16, grid, stream);
-        if (e == hipSuccess) e = launch_group_step(table_d, PH_FP32, grid, stream);
+        return launch_all(stream);
+    }
+
+    int tile_for(int64_t ld, int phase) const {
+        return (ld % 128 == 0 && ld >= min_ld_128[phase == PH_BF16 ? 0 : 1]) ? 128 : 64;
+    }
+
+    // Tile-shape autotuner.  For padded orders 256 .. 2048 and each phase, time
+    // the grouped fused step over a batch of synthetic problems (about four
+    // grid-fulls of 64x64 tiles, distinct buffers, zero state, theta_i = i) with
+    // 64x64 and with 128x128 tiles; 128x128 is used from the smallest order
+    // from which it is at least 3 % faster at every larger order measured.
+    hipError_t autotune() {
+        const int64_t orders[] = {256, 512, 1024, 2048};
+        constexpr int kOrders = 4, kReps = 3;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        hipError_t e = hipEventCreate(&ev0);
+        if (e == hipSuccess) e = hipEventCreate(&ev1);
+        bool wins[2][kOrders] = {};
+        for (int oi = 0; oi < kOrders && e == hipSuccess; ++oi) {
+            const int64_t ld = orders[oi], l2 = ld * ld;
+            const int batch = (int)std::min<int64_t>(64, std::max<int64_t>(1, 4 * (int64_t)grid * 4096 / l2));
+            // per problem: theta, d, W[2], D, Wb[2], Db (D doubles as D^T)
+            const size_t per = round_up(2 * (size_t)ld * 8) + round_up(3 * (size_t)l2 * 4) + round_up(3 * (size_t)l2 * 2);
+            unsigned char *buf = nullptr;
+            e = hipMalloc((void **)&buf, per * (size_t)batch);
+            if (e != hipSuccess) break;
+            std::vector<double> th((size_t)ld);
+            for (int64_t i = 0; i < ld; ++i) th[(size_t)i] = (double)i;
+            e = launch_fill_zero(buf, per * (size_t)batch, stream);
+            GroupTable &t = *table_h;
+            for (int b = 0; b < batch && e == hipSuccess; ++b) {
+                unsigned char *p = buf + per * (size_t)b;
+                GroupReq &g = t.reqs[b];
+                double *theta_b = (double *)p;
+                g.theta = theta_b;
+                g.d = (double *)p + ld;
+                p += round_up(2 * (size_t)ld * 8);
+                g.W = (float *)p;
+                g.Wn = (float *)p + l2;
+                g.D = g.DT = (float *)p + 2 * l2;
+                p += round_up(3 * (size_t)l2 * 4);
+                g.Wb = (__bf16 *)p;
+                g.Wbn = (__bf16 *)p + l2;
+                g.Db = (__bf16 *)p + 2 * l2;
+                g.stat = stats_d;
+                g.n = ld;
+                g.ld = ld;
+                g.lambda = 1.0;
+                e = hipMemcpyAsync(theta_b, th.data(), (size_t)ld * 8, hipMemcpyHostToDevice, stream);
+            }
+            for (int pi = 0; pi < 2 && e == hipSuccess; ++pi) {
+                const int phase = pi == 0 ? PH_BF16 : PH_FP32;
+                float ms[2] = {0.0f, 0.0f};
+                for (int ti = 0; ti < 2 && e == hipSuccess; ++ti) {
+                    const int tile = ti == 0 ? 64 : 128, L = group_list(phase, tile);
+                    std::memset(t.counts, 0, sizeof(t.counts));
+                    t.counts[0] = batch;
+                    t.counts[1 + L] = batch;
+                    const int32_t tiles = (int32_t)((ld / tile) * (ld / tile));
+                    for (int b = 0; b <= batch; ++b) {
+                        t.prefix[L][b] = b * tiles;
+                        if (b < batch) t.idx[L][b] = b;
+                    }
+                    e = hipMemcpyAsync(table_d, table_h, sizeof(GroupTable), hipMemcpyHostToDevice, stream);
+                    if (e == hipSuccess) e = launch_group_step(table_d, phase, tile, grid, stream);  // warm-up
+                    if (e == hipSuccess) e = hipEventRecord(ev0, stream);
+                    for (int r = 0; r < kReps && e == hipSuccess; ++r)
+                        e = launch_group_step(table_d, phase, tile, grid, stream);
+                    if (e == hipSuccess) e = hipEventRecord(ev1, stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms[ti], ev0, ev1);
+                }
+                wins[pi][oi] = ms[1] < 0.97f * ms[0];
+            }
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(buf);
+        }
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        std::memset(table_h, 0, sizeof(GroupTable));
+        if (e == hipSuccess) e = hipMemcpyAsync(table_d, table_h, sizeof(GroupTable), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess)
+            for (int pi = 0; pi < 2; ++pi) {
+                int64_t m = INT64_MAX;
+                for (int oi = kOrders - 1; oi >= 0 && wins[pi][oi]; --oi) m = orders[oi];
+                min_ld_128[pi] = m;
+            }
         return e;
     }
 
@@ -242,8 +343,9 @@ struct dpt_server_ctx {
 
     hipError_t step() {
         GroupTable &t = *table_h;
-        int nreq = 0, nbf = 0, nfp = 0;
-        int32_t rows = 0, bft = 0, fpt = 0;
+        int nreq = 0;
+        int cnt[kGroupLists] = {};
+        int32_t rows = 0, tiles_sum[kGroupLists] = {};
         std::vector<Request *> first, stepping;
         for (Request *r : active) {
             if (finished(r)) continue;  // e.g. max_iter = 0: retired without a step
@@ -270,25 +372,19 @@ struct dpt_server_ctx {
             g.lambda = r->lambda;
             t.pre_prefix[nreq] = rows;
             rows += (int32_t)r->n;
-            const int32_t tiles = (int32_t)((r->ld / 64) * (r->ld / 64));
-            if (bf) {
-                t.bf_idx[nbf] = nreq;
-                t.bf_prefix[nbf++] = bft;
-                bft += tiles;
-            } else {
-                t.fp_idx[nfp] = nreq;
-                t.fp_prefix[nfp++] = fpt;
-                fpt += tiles;
-            }
+            const int phase = bf ? PH_BF16 : PH_FP32, tile = tile_for(r->ld, phase);
+            const int L = group_list(phase, tile);
+            t.idx[L][cnt[L]] = nreq;
+            t.prefix[L][cnt[L]++] = tiles_sum[L];
+            tiles_sum[L] += (int32_t)((r->ld / tile) * (r->ld / tile));
             ++nreq;
         }
         t.pre_prefix[nreq] = rows;
-        t.bf_prefix[nbf] = bft;
-        t.fp_prefix[nfp] = fpt;
         t.counts[0] = nreq;
-        t.counts[1] = nbf;
-        t.counts[2] = nfp;
-        t.counts[3] = 0;
+        for (int L = 0; L < kGroupLists; ++L) {
+            t.prefix[L][cnt[L]] = tiles_sum[L];
+            t.counts[1 + L] = cnt[L];
+        }
         hipError_t e = hipSuccess;
         for (Request *r : first) {
             StepArgs a;
@@ -426,7 +522,7 @@ extern "C" {
 
 int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     if (!srv || !cfg || cfg->budget_bytes <= 0 || cfg->max_slots < 1 || cfg->max_slots > kServeMaxSlots ||
-        cfg->grid_blocks < 0 || cfg->reserved != 0)
+        cfg->grid_blocks < 0 || (cfg->autotune != 0 && cfg->autotune != 1))
         return DPT_EINVAL;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return DPT_EDEVICE;
@@ -449,19 +545,20 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     if (e == hipSuccess && cfg->use_graph) {
         e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t e1 = launch_group_prepass(c->table_d, c->grid, c->stream);
-            hipError_t e2 = launch_group_step(c->table_d, PH_BF16, c->grid, c->stream);
-            hipError_t e3 = launch_group_step(c->table_d, PH_FP32, c->grid, c->stream);
+            const hipError_t e1 = c->launch_all(c->stream);
             e = hipStreamEndCapture(c->stream, &c->graph);
-            if (e == hipSuccess) e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
+            if (e == hipSuccess) e = e1;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
     }
+    if (e == hipSuccess && cfg->autotune) e = c->autotune();
     if (e != hipSuccess) {
         const int code = (e == hipErrorOutOfMemory) ? DPT_ENOMEM : DPT_EDEVICE;
         delete c;
         return code;
     }
+    c->st.tile128_min_ld[0] = c->min_ld_128[0] == INT64_MAX ? -1 : c->min_ld_128[0];
+    c->st.tile128_min_ld[1] = c->min_ld_128[1] == INT64_MAX ? -1 : c->min_ld_128[1];
     c->arena.init((size_t)cfg->budget_bytes);
     for (int i = cfg->max_slots - 1; i >= 0; --i) c->free_slots.push_back(i);
     c->worker = std::thread([c] { c->run(); });

@@ -89,7 +89,7 @@ class Profile(ctypes.Structure):
 class ServeConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32)]
 
 
 class ServeTimes(ctypes.Structure):
@@ -100,7 +100,8 @@ class ServeTimes(ctypes.Structure):
 class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("peak_active", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
-                ("active", ctypes.c_int64), ("pending", ctypes.c_int64), ("busy_s", ctypes.c_double)]
+                ("active", ctypes.c_int64), ("pending", ctypes.c_int64), ("busy_s", ctypes.c_double),
+                ("tile128_min_ld", ctypes.c_int64 * 2)]
 
 
 _FUNCS = {
@@ -408,8 +409,8 @@ class Server:
             self.ptr = None
 
 
-def dpt_serve_open(budget_bytes, max_slots=256, use_graph=True, grid_blocks=0) -> Server:
-    cfg = ServeConfig(int(budget_bytes), int(max_slots), int(bool(use_graph)), int(grid_blocks), 0)
+def dpt_serve_open(budget_bytes, max_slots=256, use_graph=True, grid_blocks=0, autotune=False) -> Server:
+    cfg = ServeConfig(int(budget_bytes), int(max_slots), int(bool(use_graph)), int(grid_blocks), int(bool(autotune)))
     h = ctypes.c_void_p()
     rc = load_library().dpt_serve_open(ctypes.byref(h), ctypes.byref(cfg))
     if rc != DPT_OK:
@@ -455,7 +456,9 @@ def dpt_serve_stats_read(srv: Server) -> dict:
     rc = load_library().dpt_serve_stats_read(srv.ptr, ctypes.byref(st))
     if rc != DPT_OK:
         raise DptError(rc, "dpt_serve_stats_read")
-    return {k: getattr(st, k) for k, _ in ServeStats._fields_}
+    out = {k: getattr(st, k) for k, _ in ServeStats._fields_}
+    out["tile128_min_ld"] = list(st.tile128_min_ld)
+    return out
 
 
 def dpt_serve_close(srv: Server) -> None:

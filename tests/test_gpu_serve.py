@@ -1,9 +1,10 @@
 """Serving engine: continuous batching of uneven-size problems (C ABI through the binding).
 
-Every problem in a step is computed with the same 64x64 tiles and its own
-statistics, so a problem's result must not depend on the batch it shares:
-alone and in a mix the results are bitwise equal.  Each result is also checked
-against the FP64 oracle at the FP32 target (1e-5).
+Every problem is computed with tiles chosen from its own padded order and
+phase (64x64, or 128x128 from a threshold fixed when the server opens) and
+with its own statistics, so a problem's result must not depend on the batch it
+shares: alone and in a mix the results are bitwise equal.  Each result is also
+checked against the FP64 oracle at the FP32 target (1e-5).
 """
 import numpy as np
 import pytest
@@ -139,3 +140,28 @@ def test_zero_iterations_retire_without_a_step():
     assert res["status"] == dpt.DPT_NOT_CONVERGED and res["iters"] == 0
     assert np.array_equal(res["Z"], np.eye(40))
     assert np.allclose(res["E"], th, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_large_problems_and_tile_autotuner(autotune):
+    """Padded orders >= 1024 run with 128x128 tiles by default; the autotuner
+    picks the threshold per phase by timing at open.  Either way results are
+    batch invariant and reach the FP32 target."""
+    probs = [request(1100, True, 30), request(1030, False, 31), request(300, True, 32), request(64, False, 33)]
+    srv = dpt.dpt_serve_open(8 << 30, max_slots=16, autotune=autotune)
+    st = dpt.dpt_serve_stats_read(srv)
+    for m in st["tile128_min_ld"]:
+        assert m in (-1, 256, 512, 1024, 2048)
+    if not autotune:
+        assert st["tile128_min_ld"] == [1024, 1024]
+    alone = run_all(srv, [probs[0]])[0]
+    mixed = run_all(srv, probs)
+    dpt.dpt_serve_close(srv)
+    assert np.array_equal(alone["E"], mixed[0]["E"]) and np.array_equal(alone["Z"], mixed[0]["Z"])
+    for (th, de), res in zip(probs, mixed):
+        assert res["status"] == dpt.DPT_OK
+        n = th.shape[0]
+        rows = workloads.sample_rows(n, 32)
+        ref = oracle.iterate(th, de.astype(np.float64), 1.0, rows=rows, max_iter=200, tol=1e-14)
+        assert rel_eig_error(res["E"][rows], ref["e"], th) <= 1e-5
+        assert np.max(np.abs(res["Z"][rows] - ref["z"])) <= 1e-5 * max(1.0, np.abs(ref["z"]).max())
