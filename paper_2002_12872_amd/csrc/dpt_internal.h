@@ -83,6 +83,8 @@ hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *D
 // global->LDS ring.  Require ld % 256 == 0 and ld >= 1024; the BF16 one also
 // writes the BF16 shadow (Wbn != NULL).
 bool step_large_supported(int64_t ld);
+// Whether the BF16 / FP32 steps use them (enough tiles to fill the chip).
+bool step_large_preferred(int64_t ld);
 hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                                   const float *W, float *Wn, __bf16 *Wbn, hipStream_t s);
 hipError_t launch_step_f32_large(const StepArgs &a, const float *W, const float *Delta, const float *deltaT,

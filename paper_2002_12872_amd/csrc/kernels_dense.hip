@@ -635,7 +635,7 @@ hipError_t launch_prepass_f64_f64(const double *W, const double *D, const StepAr
 // everything else the 64x64 tiles.
 hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                             const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
-    if (Wbn && step_large_supported(a.ld)) return launch_step_bf16_large(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
+    if (Wbn && step_large_preferred(a.ld)) return launch_step_bf16_large(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
     if (a.ld % 256 == 0 && a.ld >= 1024)
         return launch_gemm<PolBF16, 256, 128, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
     return launch_gemm<PolBF16, 64, 64, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
@@ -643,7 +643,7 @@ hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *D
 
 hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta, const float *deltaT, float *Wn,
                            __bf16 *Wbn, hipStream_t s) {
-    if (!Wbn && step_large_supported(a.ld)) return launch_step_f32_large(a, W, Delta, deltaT, Wn, s);
+    if (!Wbn && step_large_preferred(a.ld)) return launch_step_f32_large(a, W, Delta, deltaT, Wn, s);
     if (a.ld % 256 == 0 && a.ld >= 1024)
         return launch_gemm<PolF32, 128, 128, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
     return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);

@@ -528,6 +528,11 @@ __global__ __launch_bounds__(256) void k_quant_fp8(const float *__restrict__ src
 
 bool step_large_supported(int64_t ld) { return ld % BM == 0 && ld % BN == 0 && ld >= 1024; }
 
+// The 256 x 256 tiles give (ld / 256)^2 workgroups, one per CU at a time: below
+// one full wave over the 256 CUs (ld < 4096) the 128-wide tiles of the
+// general kernels keep more of the chip busy.
+bool step_large_preferred(int64_t ld) { return step_large_supported(ld) && ld >= 4096; }
+
 hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                                   const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
     if (!step_large_supported(a.ld) || !Wbn) return hipErrorInvalidValue;

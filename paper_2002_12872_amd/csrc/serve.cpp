@@ -166,11 +166,13 @@ struct dpt_server_ctx {
     // ------------------------------------------------------------ worker
     // The launches of one engine step: the pre-pass and the fused step for every
     // (phase, tile) list; lists without work exit at once.
+    // (128x128 launches are left out for a phase that never uses them.)
     hipError_t launch_all(hipStream_t s) const {
         hipError_t e = launch_group_prepass(table_d, grid, s);
         for (int ph : {PH_BF16, PH_FP32})
             for (int tile : {64, 128})
-                if (e == hipSuccess) e = launch_group_step(table_d, ph, tile, grid, s);
+                if (e == hipSuccess && (tile == 64 || min_ld_128[ph == PH_BF16 ? 0 : 1] != INT64_MAX))
+                    e = launch_group_step(table_d, ph, tile, grid, s);
         return e;
     }
 
@@ -542,6 +544,7 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
         std::memset(c->table_h, 0, sizeof(GroupTable));
         e = hipMemcpy(c->table_d, c->table_h, sizeof(GroupTable), hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess && cfg->autotune) e = c->autotune();  // fixes the launches the graph holds
     if (e == hipSuccess && cfg->use_graph) {
         e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
@@ -551,7 +554,6 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
     }
-    if (e == hipSuccess && cfg->autotune) e = c->autotune();
     if (e != hipSuccess) {
         const int code = (e == hipErrorOutOfMemory) ? DPT_ENOMEM : DPT_EDEVICE;
         delete c;

@@ -94,7 +94,7 @@ def _state_after(theta, delta32, lam, precision, k):
     return zk, zk1, ek1
 
 
-@pytest.mark.parametrize("n", [31, 64, 257, 1000, 1100])
+@pytest.mark.parametrize("n", [31, 64, 257, 1000, 1100, 4100])
 @pytest.mark.parametrize("sym", [False, True])
 def test_fp32_step_within_rounding_bound(n, sym):
     theta, delta = small_problem(n, 2, symmetric=sym)
@@ -109,7 +109,7 @@ def test_fp32_step_within_rounding_bound(n, sym):
         assert np.all(err <= bound), (k, float(np.max(err / bound)))
 
 
-@pytest.mark.parametrize("n", [31, 64, 257, 1000, 1100])
+@pytest.mark.parametrize("n", [31, 64, 257, 1000, 1100, 4100])
 @pytest.mark.parametrize("sym", [False, True])
 def test_bf16_step_within_rounding_bound(n, sym):
     theta, delta = small_problem(n, 3, symmetric=sym)
