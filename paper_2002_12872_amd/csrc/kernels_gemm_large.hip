@@ -82,11 +82,13 @@ struct TileLoader {
         lane_off = lr * (int)ldb + (((lane & 7) ^ lr) << 4);
         lds_off = 64 * wave * ROW;
     }
-    __device__ __forceinline__ void issue(unsigned char *smem, int kt, int slot) const {
+    __device__ __forceinline__ void issue(unsigned char *smem, int kt, int slot) const { issue_rows(smem, kt, slot, 0, 8); }
+    // instructions i in [I0, I1) of issue(): rows 8i .. 8i + 7 of both tiles
+    __device__ __forceinline__ void issue_rows(unsigned char *smem, int kt, int slot, int I0, int I1) const {
         unsigned char *sb = smem + slot * STAGE + lds_off;
         const int64_t ko = (int64_t)kt * ROW;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = I0; i < I1; ++i) {
             const int64_t off = ko + 8 * i * ldb + (lane_off ^ (i << 4));
             __builtin_amdgcn_global_load_lds((gbl_void *)(ga + off), (lds_void *)(sb + i * 8 * ROW), 16, 0, 0);
             __builtin_amdgcn_global_load_lds((gbl_void *)(gb + off), (lds_void *)(sb + BM * ROW + i * 8 * ROW), 16,
@@ -317,9 +319,14 @@ __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict
 // loads 4 consecutive values k0 + 4 fg .. k0 + 4 fg + 3 of its row with one
 // 16-byte read, and MFMA j of the group takes element j, so MFMA j sums over
 // k0 + j and k0 + 4 + j and the four MFMAs cover the group once.  A K-tile (32
-// values) is 4 groups of 64 MFMAs per wave; the next group's fragments are read
-// while the current group multiplies.  With 256 MFMAs of 64 cycles per wave and
-// K-tile, the 2-stage ring has a whole K-tile of time to land the next tile.
+// values) is 4 groups of 64 MFMAs per wave; group g + 1's fragments (the other
+// register set) are read while group g multiplies, pinned among its first
+// MFMAs.  The barrier (tile kt+1 landed, tile kt fully read) sits in the middle
+// of group 3; its second half reads tile kt+1's group 0.  The refill of the
+// freed slot with tile kt+2 is spread over that half and groups 0 and 1 of the
+// next K-tile (6, 6 and 4 of the 16 loads per thread): issued together, the
+// loads of the four waves back up behind the CU's vector-memory path and stall
+// the waves' MFMA issue.
 __global__ __launch_bounds__(NT) void k_step_f32_large(const float *__restrict__ A, const float *__restrict__ B,
                                                        const float *__restrict__ deltaT, const float *__restrict__ Wold,
                                                        float *__restrict__ Wnew, StepArgs a, int tiles_m,
@@ -357,31 +364,77 @@ __global__ __launch_bounds__(NT) void k_step_f32_large(const float *__restrict__
         _Pragma("unroll") for (int j_ = 0; j_ < TN; ++j_) fb[BUF][j_] = *reinterpret_cast<const f32x4 *>(           \
             sb_ + ((b_base + j_ * 32 * ROW) ^ ((((j_ & 1) << 2) ^ (2 * (G))) << 4)));                                \
     } while (0)
-#define DPT_MMA32(BUF)                                                                                               \
+#define DPT_MMA32(BUF, E0, E1)                                                                                       \
     do {                                                                                                             \
-        _Pragma("unroll") for (int e_ = 0; e_ < 4; ++e_) _Pragma("unroll") for (int i_ = 0; i_ < TM; ++i_)          \
+        _Pragma("unroll") for (int e_ = (E0); e_ < (E1); ++e_) _Pragma("unroll") for (int i_ = 0; i_ < TM; ++i_)    \
             _Pragma("unroll") for (int j_ = 0; j_ < TN; ++j_) acc[i_][j_] =                                          \
                 __builtin_amdgcn_mfma_f32_32x32x2f32(fa[BUF][i_][e_], fb[BUF][j_][e_], acc[i_][j_], 0, 0, 0);        \
     } while (0)
+    // 8 fragment reads among the first 16 MFMAs, NVMEM tile loads one per 4 MFMAs
+#define DPT_PIN32(NVMEM)                                                                                             \
+    do {                                                                                                             \
+        _Pragma("unroll") for (int g_ = 0; g_ < 8; ++g_) {                                                           \
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                                       \
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                                       \
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                                       \
+        }                                                                                                            \
+        _Pragma("unroll") for (int g_ = 0; g_ < (NVMEM); ++g_) {                                                     \
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                                                       \
+            __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);                                                       \
+        }                                                                                                            \
+    } while (0)
 
+    // prologue: tile 0 and the first rows of tile 1 in flight, wait for tile 0,
+    // read its group 0
     ld.issue(smem, 0, 0);
-    for (int kt = 0; kt < ktiles; ++kt) {
+    ld.issue_rows(smem, 1, 1, 0, 3);
+    wait_vmcnt<6>();
+    barrier_keep_loads();
+    DPT_FRAGS32(0, 0, 0);
+    for (int kt = 0; kt < ktiles - 1; ++kt) {
         const int slot = kt & 1;
-        // tile kt landed everywhere; every wave is done with tile kt-1, whose
-        // slot now takes tile kt+1
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA32(0, 0, 4);
+        DPT_FRAGS32(1, slot, 1);
+        ld.issue_rows(smem, kt + 1, slot ^ 1, 3, 6);
+        DPT_PIN32(6);
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA32(1, 0, 4);
+        DPT_FRAGS32(0, slot, 2);
+        ld.issue_rows(smem, kt + 1, slot ^ 1, 6, 8);
+        DPT_PIN32(4);
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA32(0, 0, 4);
+        DPT_FRAGS32(1, slot, 3);
+        DPT_PIN32(0);
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA32(1, 0, 2);
+        __builtin_amdgcn_sched_barrier(0);
+        // every fragment of tile kt is in registers; tile kt+1 must have landed
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         wait_vmcnt<0>();
         barrier_keep_loads();
-        if (kt + 1 < ktiles) ld.issue(smem, kt + 1, slot ^ 1);
-        DPT_FRAGS32(0, slot, 0);
-        DPT_FRAGS32(1, slot, 1);
-        DPT_MMA32(0);
-        DPT_FRAGS32(0, slot, 2);
-        DPT_MMA32(1);
-        DPT_FRAGS32(1, slot, 3);
-        DPT_MMA32(0);
-        DPT_MMA32(1);
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA32(1, 2, 4);
+        // start the refill of the freed slot (past the end: the last tile
+        // again, never read)
+        DPT_FRAGS32(0, slot ^ 1, 0);
+        ld.issue_rows(smem, min(kt + 2, ktiles - 1), slot, 0, 3);
+        DPT_PIN32(6);
+        __builtin_amdgcn_sched_barrier(0);
     }
+    {
+        const int slot = (ktiles - 1) & 1;
+        DPT_MMA32(0, 0, 4);
+        DPT_FRAGS32(1, slot, 1);
+        DPT_MMA32(1, 0, 4);
+        DPT_FRAGS32(0, slot, 2);
+        DPT_MMA32(0, 0, 4);
+        DPT_FRAGS32(1, slot, 3);
+        DPT_MMA32(1, 0, 4);
+    }
+    wait_vmcnt<0>();
+#undef DPT_PIN32
 #undef DPT_MMA32
 #undef DPT_FRAGS32
     epilogue<EPI_F32>(smem, acc, deltaT, Wold, Wnew, nullptr, nullptr, nullptr, a, row0, col0, tid, lane, wave, wr, wc);
