@@ -214,8 +214,11 @@ __device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[
 // BF16 step.  A K-tile (64 values) is consumed as two halves of K = 32 whose
 // fragments go to two register sets (fa0/fb0, fa1/fb1): half 1 is read while
 // half 0 multiplies.  The barrier (tile kt+1 landed, tile kt fully read) sits
-// before the last substep, whose MFMAs cover the refill of tile kt's slot with
-// tile kt+2 and the reads of tile kt+1's first half.  Fragments: lane (fr, fg)
+// before the last substep, whose MFMAs cover the reads of tile kt+1's first
+// half and the first half of the refill of tile kt's slot with tile kt+2; the
+// other half of the refill runs under the first substep of the next K-tile
+// (the loads of four waves issued in one substep back up behind the CU's
+// vector-memory path and stall the MFMA issue).  Fragments: lane (fr, fg)
 // supplies row fr of a 32-row block and, at half h and substep s, logical chunk
 // 4h + 2fg + s; blocks 32 rows apart differ in key8 by 4 when the block index
 // is odd.
@@ -263,6 +266,13 @@ __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict
         _Pragma("unroll") for (int i_ = 0; i_ < TM; ++i_) _Pragma("unroll") for (int j_ = 0; j_ < TN; ++j_)          \
             acc[i_][j_] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(FA[S][i_], FB[S][j_], acc[i_][j_], 0, 0, 0);       \
     } while (0)
+#define DPT_VPIN(NV)                                                                                                 \
+    do {                                                                                                             \
+        _Pragma("unroll") for (int g_ = 0; g_ < (NV); ++g_) {                                                        \
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);                                                       \
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                                                       \
+        }                                                                                                            \
+    } while (0)
 #define DPT_INTERLEAVE(NVMEM)                                                                                        \
     do {                                                                                                             \
         _Pragma("unroll") for (int g_ = 0; g_ < 8; ++g_) {                                                           \
@@ -273,15 +283,18 @@ __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict
         }                                                                                                            \
     } while (0)
 
-    // prologue: both slots in flight, wait for tile 0, read its first half
+    // prologue: tile 0 and the first rows of tile 1 in flight, wait for tile 0,
+    // read its first half
     ld.issue(smem, 0, 0);
-    ld.issue(smem, 1, 1);
-    wait_vmcnt<LOADS>();
+    ld.issue_rows(smem, 1, 1, 0, 4);
+    wait_vmcnt<8>();
     barrier_keep_loads();
     DPT_FRAGS(fa0, fb0, 0, 0);
     for (int kt = 0; kt < ktiles - 1; ++kt) {
         const int slot = kt & 1;
         DPT_MMA(fa0, fb0, 0);
+        ld.issue_rows(smem, kt + 1, slot ^ 1, 4, 8);
+        DPT_VPIN(8);
         __builtin_amdgcn_sched_barrier(0);
         DPT_MMA(fa0, fb0, 1);
         DPT_FRAGS(fa1, fb1, slot, 1);
@@ -295,10 +308,11 @@ __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict
         barrier_keep_loads();
         __builtin_amdgcn_sched_barrier(0);
         DPT_MMA(fa1, fb1, 1);
-        // refill the freed slot (past the end: the last tile again, never read)
-        ld.issue(smem, min(kt + 2, ktiles - 1), slot);
         DPT_FRAGS(fa0, fb0, slot ^ 1, 0);
-        DPT_INTERLEAVE(16);
+        // start the refill of the freed slot (past the end: the last tile
+        // again, never read)
+        ld.issue_rows(smem, min(kt + 2, ktiles - 1), slot, 0, 4);
+        DPT_INTERLEAVE(8);
         __builtin_amdgcn_sched_barrier(0);
     }
     DPT_MMA(fa0, fb0, 0);
@@ -307,6 +321,7 @@ __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict
     DPT_MMA(fa1, fb1, 0);
     DPT_MMA(fa1, fb1, 1);
     wait_vmcnt<0>();
+#undef DPT_VPIN
 #undef DPT_INTERLEAVE
 #undef DPT_MMA
 #undef DPT_FRAGS
