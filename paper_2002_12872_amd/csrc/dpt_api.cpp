@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -248,7 +249,10 @@ template <typename T>
 hipError_t stage_dense(dpt_ctx *c, const dpt_problem *p, T **dst, bool *own) {
     const int64_t n = c->n, ld = c->ld;
     const bool same_type = (sizeof(T) == 8) == (p->dtype == DPT_DTYPE_F64);
-    if (same_type && p->mem == DPT_MEM_DEVICE && n == ld) {
+    // borrowed when no padding is needed and the kernels' 16-byte vector
+    // accesses are aligned; copied otherwise
+    const bool aligned = ((uintptr_t)p->delta & 15) == 0;
+    if (same_type && p->mem == DPT_MEM_DEVICE && n == ld && aligned) {
         *dst = (T *)p->delta;  // borrowed
         *own = false;
         return hipSuccess;
@@ -444,7 +448,9 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
         unsigned int *flag = nullptr;
         DPT_TRY(dalloc(&flag, 1));
         DPT_TRY(launch_fill_zero(flag, 4, s));
-        DPT_TRY(launch_symmetry_check_f32(c->d32, ld, flag, s));
+        // the BF16 form of Delta comes out of the same pass over it
+        if (prec == DPT_BF16_FP32) DPT_TRY(dalloc(&c->db16, nn));
+        DPT_TRY(launch_symmetry_check_f32(c->d32, ld, flag, c->db16, s));
         unsigned int h = 0;
         DPT_TRY(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s));
         DPT_TRY(hipStreamSynchronize(s));
@@ -480,17 +486,20 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
             DPT_TRY(dalloc(&c->dT32, nn));
             DPT_TRY(launch_transpose_f32(c->dT32, c->d32, ld, s));
         }
+        // W32[0] is the state at the identity (W = 0) and is read by readouts
+        // before any step; W32[1] and the BF16 shadows are written in full by
+        // the first iterate (or a warm start) before anything reads them,
+        // except in the FP8 form, which quantises both states here.
         for (int i = 0; i < 2; ++i) {
             DPT_TRY(dalloc(&c->W32[i], nn));
-            DPT_TRY(launch_fill_zero(c->W32[i], nn * 4, s));
+            if (i == 0 || prec == DPT_FP8_FP32) DPT_TRY(launch_fill_zero(c->W32[i], nn * 4, s));
         }
         if (prec == DPT_BF16_FP32) {
-            DPT_TRY(dalloc(&c->db16, nn));
-            DPT_TRY(launch_cvt_f32_to_bf16(c->db16, c->d32, (int64_t)nn, s));
-            for (int i = 0; i < 2; ++i) {
-                DPT_TRY(dalloc(&c->Wb[i], nn));
-                DPT_TRY(launch_fill_zero(c->Wb[i], nn * 2, s));
+            if (!c->db16) {
+                DPT_TRY(dalloc(&c->db16, nn));
+                DPT_TRY(launch_cvt_f32_to_bf16(c->db16, c->d32, (int64_t)nn, s));
             }
+            for (int i = 0; i < 2; ++i) DPT_TRY(dalloc(&c->Wb[i], nn));
             c->phase = PH_BF16;
         } else if (prec == DPT_FP8_FP32) {
             DPT_TRY(dalloc(&c->dq8, nn));

@@ -56,7 +56,9 @@ hipError_t launch_cvt_f32_to_f64(double *dst, const float *src, int64_t count, h
 hipError_t launch_transpose_f32(float *dst, const float *src, int64_t ld, hipStream_t s);
 hipError_t launch_transpose_f64(double *dst, const double *src, int64_t ld, hipStream_t s);
 // *flag |= 1 when src != src^T anywhere (bitwise).  flag must be zeroed first.
-hipError_t launch_symmetry_check_f32(const float *src, int64_t ld, unsigned int *flag, hipStream_t s);
+// Exact symmetry test of the padded ld x ld matrix (sets *flag on a difference);
+// when bf is not null the same pass writes bf16(src) into bf (ld x ld).
+hipError_t launch_symmetry_check_f32(const float *src, int64_t ld, unsigned int *flag, __bf16 *bf, hipStream_t s);
 hipError_t launch_symmetry_check_f64(const double *src, int64_t ld, unsigned int *flag, hipStream_t s);
 
 // First application of F from A = I: W_1[n][m] = lambda Delta[m][n] / (theta_n - theta_m).

@@ -36,6 +36,12 @@ __global__ void k_fill_zero_u32(unsigned int *p, int64_t count) {
         p[i] = 0u;
 }
 
+__global__ void k_fill_zero_u32x4(uint4 *p, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 template <typename TD, typename TS>
 __global__ void k_pad_copy(TD *__restrict__ dst, const TS *__restrict__ src, int64_t n, int64_t ld) {
     const int64_t total = ld * ld;
@@ -79,18 +85,64 @@ __global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ src, T 
     for (int r = ty; r < 64; r += 4) dst[(bx * 64 + r) * ld + by * 64 + tx] = tile[tx][r];
 }
 
+// Four consecutive values with 16-byte accesses (the address is a multiple of 4
+// elements of a 16-byte aligned array).
+__device__ __forceinline__ void load4v(const float *p, float v[4]) {
+    const float4 x = *reinterpret_cast<const float4 *>(p);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ __forceinline__ void load4v(const double *p, double v[4]) {
+    const double2 x = reinterpret_cast<const double2 *>(p)[0], y = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+}
+__device__ __forceinline__ void store4v(float *p, const float v[4]) {
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store4v(double *p, const double v[4]) {
+    reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+}
+__device__ __forceinline__ void store4_bf16(__bf16 *p, const float v[4]) {
+    const __bf16 b4[4] = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+    uint2 packed;
+    __builtin_memcpy(&packed, b4, sizeof(packed));
+    *reinterpret_cast<uint2 *>(p) = packed;
+}
+
+// Exact symmetry test on 64x64 tiles: block (bx, by) loads tile (by, bx) into
+// LDS and compares it with the mirrored tile (bx, by); any difference sets
+// *flag.  Thread t covers columns 4 (t & 15) .. +3 of rows (t >> 4) + 16 p.
+// When bf is given, the block also writes the BF16 copy of the tile it loaded
+// (every tile is loaded by exactly one block), so the copy costs no extra read.
 template <typename T>
-__global__ __launch_bounds__(256) void k_symmetry_check(const T *__restrict__ src, int64_t ld, unsigned int *flag) {
+__global__ __launch_bounds__(256) void k_symmetry_check(const T *__restrict__ src, int64_t ld, unsigned int *flag,
+                                                        __bf16 *__restrict__ bf) {
     __shared__ T tile[64][65];
     const int64_t bx = blockIdx.x, by = blockIdx.y;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < 64; r += 4) tile[r][tx] = src[(by * 64 + r) * ld + bx * 64 + tx];
+    const int r0 = threadIdx.x >> 4, c4 = (threadIdx.x & 15) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = r0 + 16 * q;
+        const int64_t g = (by * 64 + r) * ld + bx * 64 + c4;
+        T v[4];
+        load4v(src + g, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tile[r][c4 + e] = v[e];
+        if (bf) {
+            const float f[4] = {(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+            store4_bf16(bf + g, f);
+        }
+    }
     __syncthreads();
     bool diff = false;
-    for (int r = ty; r < 64; r += 4) {
-        // src[bx*64 + r][by*64 + tx] against its mirror src[by*64 + tx][bx*64 + r]
-        const T v = src[(bx * 64 + r) * ld + by * 64 + tx];
-        diff |= !(v == tile[tx][r]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        // src[bx*64 + r][by*64 + c] against its mirror src[by*64 + c][bx*64 + r]
+        const int r = r0 + 16 * q;
+        T u[4];
+        load4v(src + (bx * 64 + r) * ld + by * 64 + c4, u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) diff |= !(u[e] == tile[c4 + e][r]);
     }
     if (__any(diff ? 1 : 0) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
 }
@@ -108,21 +160,21 @@ __global__ __launch_bounds__(256) void k_first_iterate(StepArgs a, const T *__re
     bool bad = false;
     for (int64_t m0 = 4 * (int64_t)threadIdx.x; m0 < a.ld; m0 += 4 * 256) {
         const int64_t idx = n * a.ld + m0;
-        T w[4];
+        T d[4], w[4];
+        load4v(dT + idx, d);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t m = m0 + q;
             w[q] = (T)0;
-            if (row_ok && m < a.n && m != n) w[q] = (T)(a.lambda * (double)dT[idx + q] / (th_n - a.theta[m]));
+            if (row_ok && m < a.n && m != n) w[q] = (T)(a.lambda * (double)d[q] / (th_n - a.theta[m]));
             const double v = fabs((double)w[q]);
             dmax = fmax(dmax, v);
             bad |= !(v <= DBL_MAX);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) W[idx + q] = w[q];
+        store4v(W + idx, w);
         if (Wb) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) Wb[idx + q] = (__bf16)(float)w[q];
+            const float f[4] = {(float)w[0], (float)w[1], (float)w[2], (float)w[3]};
+            store4_bf16(Wb + idx, f);
         }
     }
     publish_stats(a.stat, dmax, dmax, bad);
@@ -529,6 +581,11 @@ hipError_t launch_zero_u64(unsigned long long *p, int64_t count, hipStream_t s) 
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
     if (bytes % 4) return hipErrorInvalidValue;
+    if (bytes % 16 == 0 && ((uintptr_t)p & 15) == 0) {
+        const int64_t count = (int64_t)(bytes / 16);
+        hipLaunchKernelGGL(k_fill_zero_u32x4, dim3(grid_1d(count)), dim3(kThreads), 0, s, (uint4 *)p, count);
+        return hipGetLastError();
+    }
     const int64_t count = (int64_t)(bytes / 4);
     hipLaunchKernelGGL(k_fill_zero_u32, dim3(grid_1d(count)), dim3(kThreads), 0, s, (unsigned int *)p, count);
     return hipGetLastError();
@@ -587,15 +644,16 @@ hipError_t launch_transpose_f64(double *dst, const double *src, int64_t ld, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_symmetry_check_f32(const float *src, int64_t ld, unsigned int *flag, hipStream_t s) {
+hipError_t launch_symmetry_check_f32(const float *src, int64_t ld, unsigned int *flag, __bf16 *bf, hipStream_t s) {
     if (ld % 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_symmetry_check<float>), dim3(ld / 64, ld / 64), dim3(256), 0, s, src, ld, flag);
+    hipLaunchKernelGGL((k_symmetry_check<float>), dim3(ld / 64, ld / 64), dim3(256), 0, s, src, ld, flag, bf);
     return hipGetLastError();
 }
 
 hipError_t launch_symmetry_check_f64(const double *src, int64_t ld, unsigned int *flag, hipStream_t s) {
     if (ld % 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_symmetry_check<double>), dim3(ld / 64, ld / 64), dim3(256), 0, s, src, ld, flag);
+    hipLaunchKernelGGL((k_symmetry_check<double>), dim3(ld / 64, ld / 64), dim3(256), 0, s, src, ld, flag,
+                       (__bf16 *)nullptr);
     return hipGetLastError();
 }
 
