@@ -99,11 +99,13 @@ def serving_bench(args):
     trace = workloads.serving_trace(0, count=count, rate=None)
     probs = [workloads.request_matrices(r) for r in trace]
     specs = [dpt.ProblemSpec(th, de, 1.0, stream=0) for th, de in probs]
+    sizes = [th.shape[0] for th, _ in probs]
     o_fp32 = dpt.options(tol=1e-5, max_iter=100, precision=dpt.DPT_FP32)
     o_mixed = dpt.options(tol=1e-5, max_iter=100, precision=dpt.DPT_BF16_FP32)
     # one-at-a-time FP32 solves: service time of every request
     svc = np.empty(count)
     ok = 0
+    base_flop = 0.0
     for i, sp in enumerate(specs):
         t = time.perf_counter()
         h = dpt.dpt_init(sp, o_fp32)
@@ -112,6 +114,7 @@ def serving_bench(args):
         dpt.dpt_destroy(h)
         svc[i] = time.perf_counter() - t
         ok += r["status"] == dpt.DPT_OK
+        base_flop += 2.0 * float(sizes[i]) ** 3 * max(r["iters"] - 1, 0)
     mu1 = count / svc.sum()
     rng = np.random.default_rng(5_100)
     arrivals = np.cumsum(rng.exponential(1.0 / mu1, size=count))
@@ -124,7 +127,8 @@ def serving_bench(args):
     base = {"solves_per_s": round(count / (finish[-1] - arrivals[0]), 2),
             "p50_ms": round(1e3 * percentile(lat_base, 50), 3),
             "p99_ms": round(1e3 * percentile(lat_base, 99), 3),
-            "mean_service_ms": round(1e3 * svc.mean(), 3), "converged": int(ok)}
+            "mean_service_ms": round(1e3 * svc.mean(), 3), "converged": int(ok),
+            "gemm_tflops_while_busy": round(base_flop / svc.sum() / 1e12, 2)}
     def engine_run(arr):
         """Engine in real time on the arrival times arr (None: all at t = 0)."""
         srv = dpt.dpt_serve_open(int(args.serve_budget_gib * (1 << 30)), max_slots=1024, use_graph=True,
@@ -142,7 +146,10 @@ def serving_bench(args):
         dpt.dpt_serve_close(srv)
         lat = np.array([r["times"]["finish"] - r["times"]["submit"] for r in res])
         span = max(r["times"]["finish"] for r in res) - min(r["times"]["submit"] for r in res)
-        return {"solves_per_s": round(count / span, 2), "p50_ms": round(1e3 * percentile(lat, 50), 3),
+        # products run: every iteration after the closed-form first one costs 2 N^3
+        flop = sum(2.0 * float(nr) ** 3 * max(r["iters"] - 1, 0) for nr, r in zip(sizes, res))
+        return {"solves_per_s": round(count / span, 2), "gemm_tflops": round(flop / span / 1e12, 2),
+                "p50_ms": round(1e3 * percentile(lat, 50), 3),
                 "p99_ms": round(1e3 * percentile(lat, 99), 3),
                 "converged": int(sum(r["status"] == dpt.DPT_OK for r in res)),
                 "steps": st["steps"], "peak_active": st["peak_active"],

@@ -36,6 +36,43 @@ __device__ __forceinline__ void publish_stats(unsigned long long *stat, double d
     }
 }
 
+// Block-wide form of publish_stats: the waves' maxima meet in LDS and one lane
+// publishes for the whole block, so a launch issues at most two atomics per
+// block.  Device-scope atomics on one address serialise (tens of ns each), so
+// per-wave publishing from thousands of waves costs tens of microseconds.
+// Every thread of the block must call it (it contains a barrier); blockDim.x is
+// a multiple of 64 and at most 1024.
+__device__ __forceinline__ void publish_stats_block(unsigned long long *stat, double dmax, double wmax, bool bad) {
+    __shared__ double s_d[16], s_w[16];
+    __shared__ int s_b[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        dmax = fmax(dmax, __shfl_xor(dmax, o));
+        wmax = fmax(wmax, __shfl_xor(wmax, o));
+    }
+    const bool any_bad = __any(bad ? 1 : 0);
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_d[wave] = dmax;
+        s_w[wave] = wmax;
+        s_b[wave] = any_bad ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double d = s_d[0], w = s_w[0];
+        int b = s_b[0];
+        for (int i = 1; i < nwaves; ++i) {
+            d = fmax(d, s_d[i]);
+            w = fmax(w, s_w[i]);
+            b |= s_b[i];
+        }
+        const unsigned long long vd = b ? kNanBits : dbits(d), vw = b ? kNanBits : dbits(w);
+        if (vd > __hip_atomic_load(stat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(stat, vd);
+        if (vw > __hip_atomic_load(stat + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(stat + 1, vw);
+    }
+    __syncthreads();  // the arrays may be reused by the block's next publish
+}
+
 // Block -> output tile.  Workgroups are dispatched round-robin over the 8 XCDs
 // (bid % 8), so first make each XCD's blocks a contiguous range of logical tile
 // ids, then walk the tiles in groups of G tile-rows so that the blocks resident

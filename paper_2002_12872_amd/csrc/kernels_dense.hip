@@ -8,6 +8,8 @@
 // and the eigenvalue readout of Sec. II.B is E_n = theta_n + lambda C[n][n].
 #include <float.h>
 
+#include <algorithm>
+
 #include "device_common.h"
 #include "dpt_internal.h"
 
@@ -149,35 +151,38 @@ __global__ __launch_bounds__(256) void k_symmetry_check(const T *__restrict__ sr
 
 // ----------------------------------------------------------- first iterate
 // F(I) = I + lambda gap * Delta'  (the Hadamard with the gap removes any diagonal).
-// One block per row n; 4 consecutive columns per thread (ld is a multiple of 64).
+// Block b covers rows b, b + gridDim.x, ...; 4 consecutive columns per thread
+// (ld is a multiple of 64); one statistics publish per block.
 template <typename T>
 __global__ __launch_bounds__(256) void k_first_iterate(StepArgs a, const T *__restrict__ dT, T *__restrict__ W,
                                                        __bf16 *__restrict__ Wb) {
-    const int64_t n = blockIdx.x;
-    const double th_n = a.theta[n];
-    const bool row_ok = n < a.n;
     double dmax = 0.0;
     bool bad = false;
-    for (int64_t m0 = 4 * (int64_t)threadIdx.x; m0 < a.ld; m0 += 4 * 256) {
-        const int64_t idx = n * a.ld + m0;
-        T d[4], w[4];
-        load4v(dT + idx, d);
+    for (int64_t n = blockIdx.x; n < a.ld; n += gridDim.x) {
+        const double th_n = a.theta[n];
+        const bool row_ok = n < a.n;
+#pragma unroll 4
+        for (int64_t m0 = 4 * (int64_t)threadIdx.x; m0 < a.ld; m0 += 4 * 256) {
+            const int64_t idx = n * a.ld + m0;
+            T d[4], w[4];
+            load4v(dT + idx, d);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t m = m0 + q;
-            w[q] = (T)0;
-            if (row_ok && m < a.n && m != n) w[q] = (T)(a.lambda * (double)d[q] / (th_n - a.theta[m]));
-            const double v = fabs((double)w[q]);
-            dmax = fmax(dmax, v);
-            bad |= !(v <= DBL_MAX);
-        }
-        store4v(W + idx, w);
-        if (Wb) {
-            const float f[4] = {(float)w[0], (float)w[1], (float)w[2], (float)w[3]};
-            store4_bf16(Wb + idx, f);
+            for (int q = 0; q < 4; ++q) {
+                const int64_t m = m0 + q;
+                w[q] = (T)0;
+                if (row_ok && m < a.n && m != n) w[q] = (T)(a.lambda * (double)d[q] / (th_n - a.theta[m]));
+                const double v = fabs((double)w[q]);
+                dmax = fmax(dmax, v);
+                bad |= !(v <= DBL_MAX);
+            }
+            store4v(W + idx, w);
+            if (Wb) {
+                const float f[4] = {(float)w[0], (float)w[1], (float)w[2], (float)w[3]};
+                store4_bf16(Wb + idx, f);
+            }
         }
     }
-    publish_stats(a.stat, dmax, dmax, bad);
+    publish_stats_block(a.stat, dmax, dmax, bad);
 }
 
 // ---------------------------------------------------------------- pre-pass
@@ -657,13 +662,20 @@ hipError_t launch_symmetry_check_f64(const double *src, int64_t ld, unsigned int
     return hipGetLastError();
 }
 
+// One row per block up to 256 rows, then up to 16 rows per block, at most 1024
+// blocks: enough loads in flight to stream at HBM rate with few statistics
+// atomics (one publish per block).
+inline unsigned int first_iterate_grid(int64_t ld) {
+    return (unsigned int)std::min<int64_t>(ld, std::min<int64_t>(1024, std::max<int64_t>(256, ld / 16)));
+}
+
 hipError_t launch_first_iterate_f32(const StepArgs &a, const float *deltaT, float *W, __bf16 *Wb, hipStream_t s) {
-    hipLaunchKernelGGL((k_first_iterate<float>), dim3((unsigned int)a.ld), dim3(256), 0, s, a, deltaT, W, Wb);
+    hipLaunchKernelGGL((k_first_iterate<float>), dim3(first_iterate_grid(a.ld)), dim3(256), 0, s, a, deltaT, W, Wb);
     return hipGetLastError();
 }
 
 hipError_t launch_first_iterate_f64(const StepArgs &a, const double *deltaT, double *W, hipStream_t s) {
-    hipLaunchKernelGGL((k_first_iterate<double>), dim3((unsigned int)a.ld), dim3(256), 0, s, a, deltaT, W,
+    hipLaunchKernelGGL((k_first_iterate<double>), dim3(first_iterate_grid(a.ld)), dim3(256), 0, s, a, deltaT, W,
                        (__bf16 *)nullptr);
     return hipGetLastError();
 }

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_sp_first_iterate(const int64_t *__restr
             bad |= !(v <= DBL_MAX);
         }
     }
-    publish_stats(stat, dmax, dmax, bad);
+    publish_stats_block(stat, dmax, dmax, bad);
 }
 
 // d_n = sum_{l in row n} Delta[n][l] ZT[l][n] = (Delta z_n)[n]  (FP64 accumulation).
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_dom_csr(const int64_t *__restrict__ row
         wmax = fabs((double)w - (m == nstar ? 1.0 : 0.0));
         bad = !(dv <= DBL_MAX);
     }
-    publish_stats(stat, dmax, wmax, bad);
+    publish_stats_block(stat, dmax, wmax, bad);
 }
 
 // Dense dominant mode: s computed first by k_dense_row_dot, then one wave per row.
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256) void k_dom_dense(const T *__restrict__ D, int6
             bad = !(dv <= DBL_MAX);
         }
     }
-    publish_stats(stat, dmax, wmax, bad);
+    publish_stats_block(stat, dmax, wmax, bad);
 }
 
 template <typename TS, typename TD>

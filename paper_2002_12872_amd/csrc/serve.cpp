@@ -603,13 +603,18 @@ int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o,
     } else {
         std::memcpy(r->delta.data(), p->delta, nn * 4);
     }
+    // exact symmetry test over 64 x 64 blocks (the mirrored block stays in cache)
     bool sym = true;
-    for (int64_t i = 0; i < p->n && sym; ++i)
-        for (int64_t j = i + 1; j < p->n; ++j)
-            if (!(r->delta[(size_t)(i * p->n + j)] == r->delta[(size_t)(j * p->n + i)])) {
-                sym = false;
-                break;
-            }
+    const int64_t n = p->n;
+    const float *dl = r->delta.data();
+    for (int64_t bi = 0; bi < n && sym; bi += 64)
+        for (int64_t bj = bi; bj < n && sym; bj += 64)
+            for (int64_t i = bi; i < std::min(bi + 64, n) && sym; ++i)
+                for (int64_t j = std::max(bj, i + 1); j < std::min(bj + 64, n); ++j)
+                    if (!(dl[(size_t)(i * n + j)] == dl[(size_t)(j * n + i)])) {
+                        sym = false;
+                        break;
+                    }
     r->symmetric = sym;
     if (request_bytes(r->ld, r->bf16, r->symmetric) > (size_t)srv->cfg.budget_bytes) {
         delete r;

@@ -257,6 +257,29 @@ def test_device_inputs_are_borrowed_and_match_host_inputs():
     assert torch.equal(de_d.cpu(), torch.from_numpy(delta32))     # input untouched
 
 
+def test_unaligned_device_delta_is_copied_and_matches():
+    """A device Delta whose address is not 16-byte aligned (a view one element
+    into a buffer) cannot be borrowed by the 16-byte vector loads; it is copied
+    instead and gives the same result bit for bit."""
+    import torch
+    n = 1024
+    theta, delta = small_problem(n, 13, symmetric=True)
+    delta32 = delta.astype(np.float32)
+    _, r_host, e_host, z_host = gpu_run(theta, delta32, 1.0, dpt.DPT_BF16_FP32, tol=1e-6)
+    flat = torch.zeros(n * n + 1, dtype=torch.float32, device="cuda")
+    flat[1:] = torch.from_numpy(delta32.reshape(-1)).cuda()
+    de_d = flat[1:].view(n, n)
+    assert de_d.data_ptr() % 16 == 4
+    h = dpt.dpt_init(dpt.ProblemSpec(torch.from_numpy(theta).cuda(), de_d, 1.0),
+                     dpt.options(tol=1e-6, precision=dpt.DPT_BF16_FP32))
+    res = dpt.dpt_solve(h)
+    e = dpt.dpt_eigenvalues(h)
+    z = dpt.dpt_eigenvectors(h, dtype=np.float64)
+    dpt.dpt_destroy(h)
+    assert res["iters"] == r_host["iters"]
+    assert np.array_equal(e, e_host) and np.array_equal(z, z_host)
+
+
 def test_runs_are_deterministic():
     theta, delta = small_problem(1000, 12)
     d32 = delta.astype(np.float32)
