@@ -254,15 +254,19 @@ typedef struct dpt_serve_stats {
                                             * tiles in the BF16 / FP32 phase; -1: none */
 } dpt_serve_stats;
 
-/* Start a server on the current device (creates its own stream).  Returns
- * DPT_OK, DPT_EINVAL, DPT_ENOMEM (arena allocation) or DPT_EDEVICE. */
+/* Start a server on the current device (creates its own stream, the device
+ * arena of cfg->budget_bytes and a 256 MiB pinned host staging ring for
+ * submitted matrices).  Returns DPT_OK, DPT_EINVAL, DPT_ENOMEM (arena or ring
+ * allocation) or DPT_EDEVICE. */
 int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg);
 
 /* Queue a dense problem given in host memory (DPT_MEM_HOST; copied before the
- * call returns).  o->precision must be DPT_FP32 or DPT_BF16_FP32 (o may be
- * NULL: defaults).  want_eigenvectors != 0 keeps Z for dpt_serve_poll.  Returns
- * DPT_OK and a ticket, DPT_EINVAL (bad problem, duplicate theta) or DPT_ENOMEM
- * (the problem alone exceeds the arena). */
+ * call returns, as FP32, into the staging ring when it takes at most half of
+ * it: the call waits while the ring is full of not yet uploaded problems).
+ * o->precision must be DPT_FP32 or DPT_BF16_FP32 (o may be NULL: defaults).
+ * want_eigenvectors != 0 keeps Z for dpt_serve_poll.  Returns DPT_OK and a
+ * ticket, DPT_EINVAL (bad problem, duplicate theta), DPT_ENOMEM (the problem
+ * alone exceeds the arena) or DPT_ESTATE (the server is closing or failed). */
 int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o, int want_eigenvectors,
                      int64_t *ticket);
 

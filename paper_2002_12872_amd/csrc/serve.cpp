@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdint>
 #include <chrono>
@@ -88,7 +89,9 @@ struct Request {
     dpt_options opt{};
     bool bf16 = false, symmetric = false, want_z = false;
     std::vector<double> theta;  // ld entries (zero padded)
-    std::vector<float> delta;   // n*n row-major, freed after admission
+    std::vector<float> delta;   // n*n row-major when it does not fit the pinned ring
+    float *delta_pinned = nullptr;  // n*n row-major in the pinned ring, until uploaded
+    size_t ring_off = 0;
     // device memory inside the arena
     size_t off = 0, bytes = 0;
     int slot = -1;
@@ -102,6 +105,57 @@ struct Request {
     std::vector<double> E;
     std::vector<float> Z;
     int status = DPT_NOT_CONVERGED;
+};
+
+// Ring allocator over one pinned host buffer: submissions stage their FP32
+// Delta here so that the worker's upload is an asynchronous DMA (a copy from
+// pageable memory would block the worker for the whole transfer).  Space is
+// handed out in order and reclaimed from the oldest allocation once it and
+// every allocation before it have been released (releases may come in any
+// order).
+struct PinnedRing {
+    struct Entry {
+        size_t off, bytes;
+        bool released;
+    };
+    unsigned char *base = nullptr;
+    size_t cap = 0, head = 0;
+    std::deque<Entry> live;  // in allocation order
+
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = round_up(bytes);
+        if (bytes == 0 || bytes > cap) return false;
+        size_t at;
+        if (live.empty()) {
+            at = 0;
+        } else {
+            const size_t tail = live.front().off;
+            if (head > tail) {  // free: [head, cap) and [0, tail)
+                if (head + bytes <= cap)
+                    at = head;
+                else if (bytes < tail)
+                    at = 0;
+                else
+                    return false;
+            } else if (head + bytes < tail) {  // wrapped: free [head, tail)
+                at = head;
+            } else {
+                return false;
+            }
+        }
+        live.push_back({at, bytes, false});
+        head = at + bytes;
+        *off = at;
+        return true;
+    }
+    void release(size_t off) {
+        for (Entry &en : live)
+            if (en.off == off && !en.released) {
+                en.released = true;
+                break;
+            }
+        while (!live.empty() && live.front().released) live.pop_front();
+    }
 };
 
 size_t request_bytes(int64_t ld, bool bf16, bool symmetric) {
@@ -136,6 +190,14 @@ struct dpt_server_ctx {
     // set by the autotuner at open, else the defaults below
     int64_t min_ld_128[2] = {1024, 1024};
 
+    // pinned staging ring (guarded by ring_mu; cv_ring wakes waiting submits)
+    static constexpr size_t kRingBytes = (size_t)256 << 20;
+    PinnedRing ring;
+    std::mutex ring_mu;
+    std::condition_variable cv_ring;
+    std::atomic<bool> closing{false};  // set by close and on failure: stop waiting for ring space
+    std::vector<size_t> staged;  // worker only: ring offsets of enqueued uploads not yet known complete
+
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> pending;                  // guarded by mu
@@ -157,6 +219,7 @@ struct dpt_server_ctx {
         if (stats_d) (void)hipFree(stats_d);
         if (table_h) (void)hipHostFree(table_h);
         if (stats_h) (void)hipHostFree(stats_h);
+        if (ring.base) (void)hipHostFree(ring.base);
         if (stream) (void)hipStreamDestroy(stream);
         for (auto *r : pending) delete r;
         for (auto &kv : done) delete kv.second;
@@ -297,13 +360,20 @@ struct dpt_server_ctx {
             r->Db = (__bf16 *)take(l2 * 2);
         }
         hipError_t e = hipMemcpyAsync(r->theta_d, r->theta.data(), l * 8, hipMemcpyHostToDevice, stream);
+        const float *src = r->delta_pinned ? r->delta_pinned : r->delta.data();
         if (e == hipSuccess)
-            e = hipMemcpyAsync(r->W[1], r->delta.data(), (size_t)(r->n * r->n) * 4, hipMemcpyHostToDevice, stream);
+            e = hipMemcpyAsync(r->W[1], src, (size_t)(r->n * r->n) * 4, hipMemcpyHostToDevice, stream);
+        if (r->delta_pinned) {  // its ring space is given back once the stream is idle
+            staged.push_back(r->ring_off);
+            r->delta_pinned = nullptr;
+        }
         if (e == hipSuccess) e = launch_pad_copy_f32_from_f32(r->D, r->W[1], r->n, r->ld, stream);
         if (e == hipSuccess && !r->symmetric) e = launch_transpose_f32(r->DT, r->D, r->ld, stream);
         if (e == hipSuccess && r->bf16) e = launch_cvt_f32_to_bf16(r->Db, r->D, (int64_t)l2, stream);
-        if (e == hipSuccess) e = launch_fill_zero(wpair, 2 * l2 * 4, stream);
-        if (e == hipSuccess && r->bf16) e = launch_fill_zero(r->Wb[0], 2 * l2 * 2, stream);
+        // W[0] is the state at the identity (read if the request retires without
+        // a step); W[1] and the BF16 shadows are written in full by the first
+        // iterate and the first step before anything reads them
+        if (e == hipSuccess) e = launch_fill_zero(r->W[0], l2 * 4, stream);
         if (e == hipSuccess) e = launch_fill_zero(r->d_d, l * 8, stream);
         r->ctl.start(r->opt, r->bf16 ? PH_BF16 : PH_FP32, false);
         r->t_admit = now_s(t0);
@@ -476,7 +546,23 @@ struct dpt_server_ctx {
         return e;
     }
 
+    // The uploads of the requests admitted so far have completed once the stream
+    // is idle; give their ring space back (in allocation order).
+    hipError_t release_staged() {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        {
+            std::lock_guard<std::mutex> lk(ring_mu);
+            for (size_t off : staged) ring.release(off);
+        }
+        staged.clear();
+        cv_ring.notify_all();
+        return hipSuccess;
+    }
+
     void fail_all(int code) {
+        closing.store(true);
+        cv_ring.notify_all();
         std::lock_guard<std::mutex> lk(mu);
         error = code;
         for (Request *r : active) {
@@ -507,6 +593,7 @@ struct dpt_server_ctx {
             hipError_t e = admit();
             if (e == hipSuccess && !active.empty()) e = step();
             if (e == hipSuccess) e = retire();
+            if (e == hipSuccess && !staged.empty()) e = release_staged();
             {
                 std::lock_guard<std::mutex> lk(mu);
                 st.busy_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
@@ -540,6 +627,8 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     if (e == hipSuccess) e = hipMalloc((void **)&c->stats_d, 16 * (size_t)cfg->max_slots);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->table_h, sizeof(GroupTable), 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->stats_h, 16 * (size_t)cfg->max_slots, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->ring.base, dpt_server_ctx::kRingBytes, 0);
+    if (e == hipSuccess) c->ring.cap = dpt_server_ctx::kRingBytes;
     if (e == hipSuccess) {
         std::memset(c->table_h, 0, sizeof(GroupTable));
         e = hipMemcpy(c->table_d, c->table_h, sizeof(GroupTable), hipMemcpyHostToDevice);
@@ -589,24 +678,56 @@ int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o,
     r->bf16 = opt.precision == DPT_BF16_FP32;
     r->want_z = want_eigenvectors != 0;
     const size_t nn = (size_t)(p->n * p->n);
-    try {
-        r->theta.assign((size_t)r->ld, 0.0);
-        r->delta.resize(nn);
-    } catch (...) {
+    if (request_bytes(r->ld, r->bf16, false) > (size_t)srv->cfg.budget_bytes &&
+        request_bytes(r->ld, r->bf16, true) > (size_t)srv->cfg.budget_bytes) {
         delete r;
         return DPT_ENOMEM;
     }
+    // Delta goes to the pinned ring (waiting for space while earlier submissions
+    // are uploaded) unless it takes more than half of it
+    float *dst = nullptr;
+    if (nn * 4 <= srv->ring.cap / 2) {
+        std::unique_lock<std::mutex> lk(srv->ring_mu);
+        size_t off = 0;
+        srv->cv_ring.wait(lk, [&] { return srv->closing.load() || srv->ring.alloc(nn * 4, &off); });
+        if (srv->closing.load()) {
+            delete r;
+            return DPT_ESTATE;
+        }
+        dst = (float *)(srv->ring.base + off);
+        r->delta_pinned = dst;
+        r->ring_off = off;
+    }
+    // an early return from here on gives the ring space back
+    auto drop = [&](int code) {
+        if (r->delta_pinned) {
+            {
+                std::lock_guard<std::mutex> lk(srv->ring_mu);
+                srv->ring.release(r->ring_off);
+            }
+            srv->cv_ring.notify_all();
+        }
+        delete r;
+        return code;
+    };
+    try {
+        r->theta.assign((size_t)r->ld, 0.0);
+        if (!dst) r->delta.resize(nn);
+    } catch (...) {
+        return drop(DPT_ENOMEM);
+    }
+    if (!dst) dst = r->delta.data();
     std::memcpy(r->theta.data(), p->theta, sizeof(double) * (size_t)p->n);
     if (p->dtype == DPT_DTYPE_F64) {
         const double *src = (const double *)p->delta;
-        for (size_t i = 0; i < nn; ++i) r->delta[i] = (float)src[i];
+        for (size_t i = 0; i < nn; ++i) dst[i] = (float)src[i];
     } else {
-        std::memcpy(r->delta.data(), p->delta, nn * 4);
+        std::memcpy(dst, p->delta, nn * 4);
     }
     // exact symmetry test over 64 x 64 blocks (the mirrored block stays in cache)
     bool sym = true;
     const int64_t n = p->n;
-    const float *dl = r->delta.data();
+    const float *dl = dst;
     for (int64_t bi = 0; bi < n && sym; bi += 64)
         for (int64_t bj = bi; bj < n && sym; bj += 64)
             for (int64_t i = bi; i < std::min(bi + 64, n) && sym; ++i)
@@ -616,15 +737,13 @@ int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o,
                         break;
                     }
     r->symmetric = sym;
-    if (request_bytes(r->ld, r->bf16, r->symmetric) > (size_t)srv->cfg.budget_bytes) {
-        delete r;
-        return DPT_ENOMEM;
-    }
+    if (request_bytes(r->ld, r->bf16, r->symmetric) > (size_t)srv->cfg.budget_bytes) return drop(DPT_ENOMEM);
     {
-        std::lock_guard<std::mutex> lk(srv->mu);
+        std::unique_lock<std::mutex> lk(srv->mu);
         if (srv->stop || srv->error != DPT_OK) {
-            delete r;
-            return srv->error != DPT_OK ? srv->error : DPT_ESTATE;
+            const int code = srv->error != DPT_OK ? srv->error : DPT_ESTATE;
+            lk.unlock();
+            return drop(code);
         }
         r->id = srv->next_id++;
         r->t_submit = now_s(srv->t0);
@@ -696,6 +815,8 @@ void dpt_serve_close(dpt_server srv) {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stop = true;
     }
+    srv->closing.store(true);
+    srv->cv_ring.notify_all();
     srv->cv_work.notify_all();
     if (srv->worker.joinable()) srv->worker.join();
     (void)hipStreamSynchronize(srv->stream);
