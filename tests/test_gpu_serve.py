@@ -91,6 +91,28 @@ def test_budget_limits_concurrency_and_everything_completes():
     assert admits == sorted(admits)
 
 
+def test_submissions_beyond_the_staging_ring_wait_and_complete():
+    """More matrices queued than the 256 MiB pinned staging ring holds, with an
+    arena that admits one problem at a time: submit waits for earlier uploads
+    instead of failing, and every result equals the one computed alone."""
+    n, count = 2048, 20                       # 16 MiB of FP32 per matrix, 320 MiB queued
+    th, de = request(n, True, 40)
+    probs = [(th, de)] * count
+    o = dict(tol=1e-5, max_iter=100, precision=1)
+    one = 3 * n * 8 + 3 * n * n * 4           # FP32, symmetric: theta, d, E, W[0..1], D
+    srv = dpt.dpt_serve_open(one + (1 << 20), max_slots=8)
+    res = run_all(srv, probs, want_z=False, opts=o)
+    st = dpt.dpt_serve_stats_read(srv)
+    dpt.dpt_serve_close(srv)
+    srv = dpt.dpt_serve_open(one + (1 << 20), max_slots=8)
+    alone = run_all(srv, probs[:1], want_z=False, opts=o)[0]
+    dpt.dpt_serve_close(srv)
+    assert st["completed"] == count and st["peak_active"] == 1
+    for r in res:
+        assert r["status"] == dpt.DPT_OK
+        assert np.array_equal(r["E"], alone["E"])
+
+
 def test_per_problem_statuses_in_a_mix():
     theta2, delta2 = workloads.two_by_two()
     good = [request(80, True, 30), request(150, False, 31)]
