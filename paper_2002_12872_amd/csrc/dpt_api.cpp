@@ -227,11 +227,12 @@ struct dpt_ctx {
 
     SparseState *sp = nullptr;
     Profiler prof;
+    void *small_hist = nullptr;  // iterates of one fused small-problem batch (ld = 64)
 
     ~dpt_ctx() {
         if (sp) sparse_destroy(sp);
         void *own[] = {theta, dvec, evec, stats, db16, W32[0], W32[1], Wb[0], Wb[1], W64[0], W64[1],
-                       dq8, ds8, Wq8[0], Wq8[1], Ws8[0], Ws8[1]};
+                       dq8, ds8, Wq8[0], Wq8[1], Ws8[0], Ws8[1], small_hist};
         for (void *p : own)
             if (p) (void)hipFree(p);
         if (dT32 && dT32 != d32) (void)hipFree(dT32);
@@ -260,6 +261,17 @@ hipError_t stage_dense(dpt_ctx *c, const dpt_problem *p, T **dst, bool *own) {
     hipError_t e = dalloc(dst, (size_t)(ld * ld));
     if (e != hipSuccess) return e;
     *own = true;
+    // small host inputs: converted and padded on the host, one upload
+    if (p->mem == DPT_MEM_HOST && (size_t)(ld * ld) * sizeof(T) <= ((size_t)16 << 20)) {
+        std::vector<T> hostpad((size_t)(ld * ld), (T)0);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                hostpad[(size_t)(i * ld + j)] = p->dtype == DPT_DTYPE_F64 ? (T)((const double *)p->delta)[i * n + j]
+                                                                         : (T)((const float *)p->delta)[i * n + j];
+        e = hipMemcpyAsync(*dst, hostpad.data(), hostpad.size() * sizeof(T), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // hostpad is freed on return
+        return e;
+    }
     const void *src = p->delta;
     void *tmp = nullptr;
     const size_t in_bytes = (size_t)(n * n) * (p->dtype == DPT_DTYPE_F64 ? 8 : 4);
@@ -425,37 +437,139 @@ void stat_of(dpt_ctx *c, int64_t step, double *delta, double *wmax) {
     *wmax = bits_to_double(c->stats_host[2 * s0 + 1]);
 }
 
+// Small dense problems (ld = 64) in the FP32 or FP64 phase run kSmallBatch
+// steps per launch in one workgroup (k_small_steps): per-step launches and
+// read-backs would cost ~25 us per step against ~1 us of work.  The stopping
+// rule still sees every step's statistics in order; the state is set to the
+// iterate it stops on.
+constexpr int kSmallBatch = 16;
+
+bool small_batch_ok(const dpt_ctx *c) {
+    return !c->sp && c->ld == 64 && (c->phase == PH_FP32 || c->phase == PH_FP64) && c->opt.check_every == 1 &&
+           !c->prof.on;
+}
+
+// Up to kSmallBatch steps; *taken gets the number the controller consumed and
+// *act its last decision.  Every consumed step is counted in ctl and recorded
+// in r's history.
+// Steps to run speculatively: 4 at first, then the number the recent
+// contraction rate predicts until delta < tol (plus one), at most kSmallBatch.
+// The prediction only affects how many steps are computed and discarded.
+int small_batch_size(dpt_ctx *c, const Controller &ctl, int64_t consumed) {
+    const int left = std::max(1, c->opt.max_iter - ctl.iters);
+    if (consumed < 3) return std::min(4, left);
+    double d1, d2, d3, w;
+    stat_of(c, c->k - 1, &d1, &w);
+    stat_of(c, c->k - 2, &d2, &w);
+    stat_of(c, c->k - 3, &d3, &w);
+    const double rho = std::max(d1 / d2, d2 / d3);
+    const double tol = c->phase == PH_FP64 && c->opt.fp64_final_tol > 0 ? c->opt.fp64_final_tol : c->opt.tol;
+    int b = kSmallBatch;
+    if (rho > 0.0 && rho < 1.0 && d1 > tol) b = (int)std::ceil(std::log(tol / d1) / std::log(rho)) + 1;
+    return std::min(left, std::max(2, std::min(kSmallBatch, b)));
+}
+
+int small_batch(dpt_ctx *c, Controller &ctl, dpt_result *r, int64_t consumed, int *taken,
+                Controller::Action *act) {
+    const int m = small_batch_size(c, ctl, consumed);
+    const bool f64 = c->phase == PH_FP64;
+    const size_t l2 = (size_t)(c->ld * c->ld), esz = f64 ? 8 : 4;
+    if (!c->small_hist) DPT_TRY(hipMalloc(&c->small_hist, (size_t)kSmallBatch * l2 * 8));
+    const StepArgs a = step_args(c, nullptr);
+    hipError_t e;
+    if (f64)
+        e = launch_small_steps_f64(c->W64[c->cur], (double *)c->small_hist, c->d64, c->dT64, a, c->stats, c->k, m,
+                                   c->at_identity ? 1 : 0, c->dvec, c->stream);
+    else
+        e = launch_small_steps_f32(c->W32[c->cur], (float *)c->small_hist, c->d32, c->dT32, a, c->stats, c->k, m,
+                                   c->at_identity ? 1 : 0, c->dvec, c->stream);
+    DPT_TRY(e);
+    int rc = fetch_stats(c, c->k, c->k + m);
+    if (rc != DPT_OK) return rc;
+    int j = 0;
+    Controller::Action last = Controller::CONTINUE;
+    while (j < m) {
+        double dl, wm;
+        stat_of(c, c->k + j, &dl, &wm);
+        ctl.count_step();
+        if (r && r->delta_history && ctl.iters - 1 < r->history_cap) r->delta_history[ctl.iters - 1] = dl;
+        ++j;
+        last = ctl.update(dl, wm);
+        if (last != Controller::CONTINUE || ctl.capped()) break;
+    }
+    // the state becomes iterate j of the batch
+    void *dst = f64 ? (void *)c->W64[c->cur] : (void *)c->W32[c->cur];
+    DPT_TRY(hipMemcpyAsync(dst, (const unsigned char *)c->small_hist + (size_t)(j - 1) * l2 * esz, l2 * esz,
+                           hipMemcpyDeviceToDevice, c->stream));
+    c->k += j;
+    c->at_identity = false;
+    *taken = j;
+    *act = last;
+    return DPT_OK;
+}
+
+
+// Exact symmetry of a small host matrix (n x n row-major, dtype of the input).
+bool host_symmetric(const dpt_problem *p) {
+    const int64_t n = p->n;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            const bool eq = p->dtype == DPT_DTYPE_F64
+                                ? ((const double *)p->delta)[i * n + j] == ((const double *)p->delta)[j * n + i]
+                                : ((const float *)p->delta)[i * n + j] == ((const float *)p->delta)[j * n + i];
+            if (!eq) return false;
+        }
+    return true;
+}
+
+// Symmetry test of the staged copy on the device (flag read back).
+template <typename T>
+int device_symmetric(dpt_ctx *c, const T *src, __bf16 *bf, bool *sym) {
+    unsigned int *flag = nullptr;
+    DPT_TRY(dalloc(&flag, 1));
+    hipError_t e = launch_fill_zero(flag, 4, c->stream);
+    if (e == hipSuccess) {
+        if (sizeof(T) == 8)
+            e = launch_symmetry_check_f64((const double *)src, c->ld, flag, c->stream);
+        else
+            e = launch_symmetry_check_f32((const float *)src, c->ld, flag, bf, c->stream);
+    }
+    unsigned int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(flag);
+    DPT_TRY(e);
+    *sym = (h == 0);
+    return DPT_OK;
+}
+
 int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
     const int64_t ld = c->ld;
     const size_t nn = (size_t)(ld * ld);
     const int prec = c->opt.precision;
     hipStream_t s = c->stream;
+    // small host inputs are tested for symmetry on the host (no device round trip)
+    const bool host_sym_test = p->mem == DPT_MEM_HOST && p->n <= 256;
     // Primary copy in the input dtype; the symmetry test runs on it.
     if (p->dtype == DPT_DTYPE_F64) {
         DPT_TRY(stage_dense<double>(c, p, &c->d64, &c->d64_own));
-        unsigned int *flag = nullptr;
-        DPT_TRY(dalloc(&flag, 1));
-        DPT_TRY(launch_fill_zero(flag, 4, s));
-        DPT_TRY(launch_symmetry_check_f64(c->d64, ld, flag, s));
-        unsigned int h = 0;
-        DPT_TRY(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s));
-        DPT_TRY(hipStreamSynchronize(s));
-        (void)hipFree(flag);
-        c->symmetric = (h == 0);
+        if (host_sym_test) {
+            c->symmetric = host_symmetric(p);
+        } else {
+            int rc = device_symmetric<double>(c, c->d64, nullptr, &c->symmetric);
+            if (rc != DPT_OK) return rc;
+        }
         if (prec != DPT_FP64) DPT_TRY(stage_dense<float>(c, p, &c->d32, &c->d32_own));
     } else {
         DPT_TRY(stage_dense<float>(c, p, &c->d32, &c->d32_own));
-        unsigned int *flag = nullptr;
-        DPT_TRY(dalloc(&flag, 1));
-        DPT_TRY(launch_fill_zero(flag, 4, s));
-        // the BF16 form of Delta comes out of the same pass over it
-        if (prec == DPT_BF16_FP32) DPT_TRY(dalloc(&c->db16, nn));
-        DPT_TRY(launch_symmetry_check_f32(c->d32, ld, flag, c->db16, s));
-        unsigned int h = 0;
-        DPT_TRY(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s));
-        DPT_TRY(hipStreamSynchronize(s));
-        (void)hipFree(flag);
-        c->symmetric = (h == 0);
+        if (host_sym_test) {
+            c->symmetric = host_symmetric(p);
+        } else {
+            // the BF16 form of Delta comes out of the same pass over it
+            if (prec == DPT_BF16_FP32) DPT_TRY(dalloc(&c->db16, nn));
+            int rc = device_symmetric<float>(c, c->d32, c->db16, &c->symmetric);
+            if (rc != DPT_OK) return rc;
+        }
         if (prec == DPT_FP64) {
             DPT_TRY(dalloc(&c->d64, nn));
             c->d64_own = true;
@@ -670,8 +784,23 @@ int dpt_solve(dpt_handle h, dpt_result *r) {
     Controller ctl;
     ctl.start(h->opt, h->phase, h->sp == nullptr);
     int64_t checked = h->k;  // stats already consumed
+    const int64_t k_start = h->k;
     bool done = false;
     while (!done && !ctl.capped()) {
+        if (small_batch_ok(h)) {
+            int taken = 0;
+            Controller::Action act = Controller::CONTINUE;
+            int rc = small_batch(h, ctl, r, h->k - k_start, &taken, &act);
+            if (rc != DPT_OK) return rc;
+            checked = h->k;
+            if (act == Controller::TO_FP64) {
+                rc = enter_fp64(h);
+                if (rc != DPT_OK) return rc;
+            } else if (act == Controller::DONE) {
+                done = true;
+            }
+            continue;
+        }
         int rc = do_step(h);
         if (rc != DPT_OK) return rc;
         ctl.count_step();

@@ -154,11 +154,11 @@ __global__ __launch_bounds__(256) void k_symmetry_check(const T *__restrict__ sr
 // Block b covers rows b, b + gridDim.x, ...; 4 consecutive columns per thread
 // (ld is a multiple of 64); one statistics publish per block.
 template <typename T>
-__global__ __launch_bounds__(256) void k_first_iterate(StepArgs a, const T *__restrict__ dT, T *__restrict__ W,
-                                                       __bf16 *__restrict__ Wb) {
+__device__ __forceinline__ void first_iterate_rows(const StepArgs &a, const T *__restrict__ dT, T *__restrict__ W,
+                                                   __bf16 *__restrict__ Wb, int64_t n0, int64_t nstride) {
     double dmax = 0.0;
     bool bad = false;
-    for (int64_t n = blockIdx.x; n < a.ld; n += gridDim.x) {
+    for (int64_t n = n0; n < a.ld; n += nstride) {
         const double th_n = a.theta[n];
         const bool row_ok = n < a.n;
 #pragma unroll 4
@@ -185,6 +185,12 @@ __global__ __launch_bounds__(256) void k_first_iterate(StepArgs a, const T *__re
     publish_stats_block(a.stat, dmax, dmax, bad);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_first_iterate(StepArgs a, const T *__restrict__ dT, T *__restrict__ W,
+                                                       __bf16 *__restrict__ Wb) {
+    first_iterate_rows(a, dT, W, Wb, (int64_t)blockIdx.x, (int64_t)gridDim.x);
+}
+
 // ---------------------------------------------------------------- pre-pass
 __device__ __forceinline__ void load4(const float *p, double out[4]) {
     const float4 v = *reinterpret_cast<const float4 *>(p);
@@ -199,11 +205,13 @@ __device__ __forceinline__ void load4(const double *p, double out[4]) {
 // One block per row n; fixed per-thread strides and a fixed butterfly make the
 // FP64 sum deterministic.  Rows are ld-aligned and zero-padded, so the loop runs
 // over the whole padded row with 4-wide loads.
+// d_n = Delta[n][n] + sum_k W[n][k] Delta[n][k] in FP64 for row n with the whole
+// block (fixed reduction order), E_n = theta_n + lambda d_n when E is given;
+// row 0 clears the step's statistics when stat_clear is given.
 template <typename TW, typename TD>
-__global__ __launch_bounds__(256) void k_prepass(const TW *__restrict__ W, const TD *__restrict__ D, StepArgs a,
-                                                 double *__restrict__ d, double *__restrict__ E,
-                                                 unsigned long long *stat_clear) {
-    const int64_t n = blockIdx.x;
+__device__ __forceinline__ void prepass_row(const TW *__restrict__ W, const TD *__restrict__ D, const StepArgs &a,
+                                            double *__restrict__ d, double *__restrict__ E,
+                                            unsigned long long *stat_clear, int64_t n) {
     const TW *w = W + n * a.ld;
     const TD *dl = D + n * a.ld;
     double s = 0.0;
@@ -227,6 +235,13 @@ __global__ __launch_bounds__(256) void k_prepass(const TW *__restrict__ W, const
             stat_clear[1] = 0ull;
         }
     }
+}
+
+template <typename TW, typename TD>
+__global__ __launch_bounds__(256) void k_prepass(const TW *__restrict__ W, const TD *__restrict__ D, StepArgs a,
+                                                 double *__restrict__ d, double *__restrict__ E,
+                                                 unsigned long long *stat_clear) {
+    prepass_row(W, D, a, d, E, stat_clear, (int64_t)blockIdx.x);
 }
 
 // --------------------------------------------------------- fused MFMA step
@@ -448,6 +463,83 @@ __global__ __launch_bounds__(WM *WN * 64) void k_step_gemm(const typename P::in_
     int tm, tn;
     tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
     step_tile<P, BM, BN, BK, WM, WN, S>(A, B, deltaT, Wold, Wnew, Wbnew, a, tm, tn);
+}
+
+// --------------------------------------------------- small problems (ld 64)
+// Up to nsteps applications of F in one workgroup for ld = 64 (one 64x64 tile),
+// bitwise equal to the separate first-iterate / pre-pass / step launches: the
+// same per-element arithmetic and the same reduction order, with the 64 rows
+// spread over the block (16 lanes per row, 4 columns per lane) instead of one
+// block per row.  Iterate s + 1 goes to hist + s ld^2 and its statistics to
+// ring slot (k0 + s) mod kStatRing; the host picks the iterate its stopping rule
+// ends on (the later ones are discarded).
+template <class P, typename S>
+__global__ __launch_bounds__(256) void k_small_steps(const S *__restrict__ Wcur, S *__restrict__ hist,
+                                                     const S *__restrict__ D, const S *__restrict__ DT, StepArgs a,
+                                                     unsigned long long *__restrict__ stats, int64_t k0, int nsteps,
+                                                     int at_identity, double *__restrict__ d) {
+    constexpr int64_t LD = 64;
+    const int64_t l2 = LD * LD;
+    const int t = threadIdx.x, c4 = 4 * (t & 15), r0 = t >> 4;
+    for (int s = 0; s < nsteps; ++s) {
+        const S *Wold = s == 0 ? Wcur : hist + (int64_t)(s - 1) * l2;
+        S *Wnew = hist + (int64_t)s * l2;
+        StepArgs as = a;
+        as.stat = stats + 2 * ((k0 + s) % kStatRing);
+        as.d = d;
+        if (t == 0) {
+            as.stat[0] = 0ull;
+            as.stat[1] = 0ull;
+        }
+        __syncthreads();
+        if (s == 0 && at_identity) {
+            // k_first_iterate: lane (row n, columns c4 .. c4 + 3)
+            double dmax = 0.0;
+            bool bad = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t n = r0 + 16 * q, idx = n * LD + c4;
+                const double th_n = a.theta[n];
+                const bool row_ok = n < a.n;
+                S dv[4], w[4];
+                load4v(DT + idx, dv);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t m = c4 + e;
+                    w[e] = (S)0;
+                    if (row_ok && m < a.n && m != n) w[e] = (S)(a.lambda * (double)dv[e] / (th_n - a.theta[m]));
+                    const double v = fabs((double)w[e]);
+                    dmax = fmax(dmax, v);
+                    bad |= !(v <= DBL_MAX);
+                }
+                store4v(Wnew + idx, w);
+            }
+            publish_stats_block(as.stat, dmax, dmax, bad);
+        } else {
+            // k_prepass: in a 64-wide block reduction only lanes 0..15 of wave 0
+            // hold values for ld = 64; their xor-32 and xor-16 partners hold
+            // zeros, so those two butterfly levels are additions of +0.0
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t n = r0 + 16 * q;
+                double sum = 0.0;
+                {
+                    double wv[4], dv[4];
+                    load4(Wold + n * LD + c4, wv);
+                    load4(D + n * LD + c4, dv);
+                    sum += wv[0] * dv[0] + wv[1] * dv[1] + wv[2] * dv[2] + wv[3] * dv[3];
+                }
+                sum = sum + 0.0;
+                sum = sum + 0.0;
+#pragma unroll
+                for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+                if ((t & 15) == 0 && n < a.n) d[n] = (double)D[n * LD + n] + ((sum + 0.0) + (0.0 + 0.0));
+            }
+            __syncthreads();  // d complete before the step reads it
+            step_tile<P, 64, 64, 16, 2, 2, S>(Wold, D, DT, Wold, Wnew, (__bf16 *)nullptr, as, 0, 0);
+        }
+        __syncthreads();  // iterate s + 1 complete before the next step reads it
+    }
 }
 
 // ------------------------------------------------------- grouped (serving)
@@ -722,6 +814,24 @@ hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta
 hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT, double *Wn,
                            hipStream_t s) {
     return launch_gemm<PolF64, 64, 64, 16, 2, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
+}
+
+hipError_t launch_small_steps_f32(const float *Wcur, float *hist, const float *D, const float *DT, const StepArgs &a,
+                                  unsigned long long *stats, int64_t k0, int nsteps, int at_identity, double *d,
+                                  hipStream_t s) {
+    if (a.ld != 64 || nsteps < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_small_steps<PolF32, float>), dim3(1), dim3(256), 0, s, Wcur, hist, D, DT, a, stats, k0,
+                       nsteps, at_identity, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_steps_f64(const double *Wcur, double *hist, const double *D, const double *DT,
+                                  const StepArgs &a, unsigned long long *stats, int64_t k0, int nsteps,
+                                  int at_identity, double *d, hipStream_t s) {
+    if (a.ld != 64 || nsteps < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_small_steps<PolF64, double>), dim3(1), dim3(256), 0, s, Wcur, hist, D, DT, a, stats, k0,
+                       nsteps, at_identity, d);
+    return hipGetLastError();
 }
 
 hipError_t launch_export_f32(const float *W, int64_t n, int64_t ld, void *out, int out_f64, hipStream_t s) {

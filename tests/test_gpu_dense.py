@@ -280,6 +280,31 @@ def test_unaligned_device_delta_is_copied_and_matches():
     assert np.array_equal(e, e_host) and np.array_equal(z, z_host)
 
 
+@pytest.mark.parametrize("precision,n,sym,lam,tol,max_iter", [
+    (dpt.DPT_FP64, 64, True, 1.0, 1e-12, 200),   # stops inside the first batch of 16
+    (dpt.DPT_FP64, 33, False, 2.0, 1e-300, 37),  # slow contraction: the cap, over three batches
+    (dpt.DPT_FP32, 50, False, 1.0, 1e-6, 200),
+    (dpt.DPT_FP32, 64, True, 4.0, 1e-300, 20),   # the cap, over two batches
+])
+def test_small_problem_batches_equal_single_steps(precision, n, sym, lam, tol, max_iter):
+    """Problems with padded order 64 run several steps per launch in dpt_solve;
+    the iterate returned and the delta history are those of one launch per step
+    (dpt_step), bit for bit, whichever step the stopping rule ends on."""
+    theta, delta = small_problem(n, 14, symmetric=sym)
+    d = delta if precision == dpt.DPT_FP64 else delta.astype(np.float32)
+    _, res, e1, z1 = gpu_run(theta, d, lam, precision, tol=tol, max_iter=max_iter)
+    steps = res["iters"]
+    assert (steps < 16) if tol > 1e-100 else (steps == max_iter)
+    spec = dpt.ProblemSpec(theta, d, lam, stream=0)
+    h = dpt.dpt_init(spec, dpt.options(tol=tol, max_iter=max_iter, precision=precision))
+    deltas = [dpt.dpt_step(h, 1) for _ in range(steps)]
+    e2 = dpt.dpt_eigenvalues(h)
+    z2 = dpt.dpt_eigenvectors(h, dtype=np.float64)
+    dpt.dpt_destroy(h)
+    assert np.array_equal(e1, e2) and np.array_equal(z1, z2)
+    assert np.array_equal(res["history"][:steps], np.array(deltas))
+
+
 def test_runs_are_deterministic():
     theta, delta = small_problem(1000, 12)
     d32 = delta.astype(np.float32)
