@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cmath>
 #include <cstdio>
@@ -88,15 +89,21 @@ bool csr_ok(const int64_t *indptr, const int32_t *indices, int64_t n, int64_t nn
     return true;
 }
 
+// The current device must be a gfx950; the answer is cached per device (the
+// property query costs far more than a small solve).
 int check_device() {
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return DPT_EDEVICE;
+    static std::atomic<signed char> verdict[64];  // 0 unknown, 1 gfx950, -1 other
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return DPT_EDEVICE;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return DPT_EDEVICE;
+    if (dev < 64) {
+        const signed char v = verdict[dev].load(std::memory_order_relaxed);
+        if (v != 0) return v > 0 ? DPT_OK : DPT_EDEVICE;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DPT_EDEVICE;
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return DPT_EDEVICE;
-    return DPT_OK;
+    const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (dev < 64) verdict[dev].store(ok ? 1 : -1, std::memory_order_relaxed);
+    return ok ? DPT_OK : DPT_EDEVICE;
 }
 
 // True when p is device (or managed) memory that kernels may dereference.
@@ -204,7 +211,7 @@ struct dpt_ctx {
     double *dvec = nullptr;   // ld entries
     double *evec = nullptr;   // ld entries
     unsigned long long *stats = nullptr;
-    unsigned long long *stats_host = nullptr;  // pinned mirror of the ring
+    unsigned long long *stats_host = nullptr;  // host mirror of the ring (read after a stream sync)
 
     // dense Delta copies (padded ld x ld); *_own tells whether we free them
     float *d32 = nullptr, *dT32 = nullptr;
@@ -239,7 +246,7 @@ struct dpt_ctx {
         if (dT64 && dT64 != d64) (void)hipFree(dT64);
         if (d32 && d32_own) (void)hipFree(d32);
         if (d64 && d64_own) (void)hipFree(d64);
-        if (stats_host) (void)hipHostFree(stats_host);
+        delete[] stats_host;
     }
 };
 
@@ -737,8 +744,8 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
     if (dalloc(&c->theta, (size_t)c->ld) != hipSuccess || dalloc(&c->dvec, (size_t)c->ld) != hipSuccess ||
         dalloc(&c->evec, (size_t)c->ld) != hipSuccess || dalloc(&c->stats, (size_t)2 * kStatRing) != hipSuccess)
         return fail(DPT_ENOMEM);
-    if (hipHostMalloc((void **)&c->stats_host, sizeof(unsigned long long) * 2 * kStatRing, 0) != hipSuccess)
-        return fail(DPT_ENOMEM);
+    c->stats_host = new (std::nothrow) unsigned long long[2 * kStatRing];
+    if (!c->stats_host) return fail(DPT_ENOMEM);
     if (hipMemcpyAsync(c->theta, th.data(), sizeof(double) * (size_t)c->ld, hipMemcpyHostToDevice, c->stream) !=
         hipSuccess)
         return fail(DPT_EDEVICE);
