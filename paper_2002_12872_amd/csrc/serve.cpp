@@ -197,6 +197,7 @@ struct dpt_server_ctx {
     std::condition_variable cv_ring;
     std::atomic<bool> closing{false};  // set by close and on failure: stop waiting for ring space
     std::vector<size_t> staged;  // worker only: ring offsets of enqueued uploads not yet known complete
+    bool idle_since_staged = true;  // worker only: the stream was synchronised after the last upload
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -366,6 +367,7 @@ struct dpt_server_ctx {
         if (r->delta_pinned) {  // its ring space is given back once the stream is idle
             staged.push_back(r->ring_off);
             r->delta_pinned = nullptr;
+            idle_since_staged = false;
         }
         if (e == hipSuccess) e = launch_pad_copy_f32_from_f32(r->D, r->W[1], r->n, r->ld, stream);
         if (e == hipSuccess && !r->symmetric) e = launch_transpose_f32(r->DT, r->D, r->ld, stream);
@@ -478,6 +480,7 @@ struct dpt_server_ctx {
         if (e == hipSuccess)
             e = hipMemcpyAsync(stats_h, stats_d, 16 * (size_t)cfg.max_slots, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) idle_since_staged = true;
         if (e != hipSuccess) return e;
         const double t_now = now_s(t0);
         for (Request *r : stepping) {
@@ -525,6 +528,7 @@ struct dpt_server_ctx {
             }
         }
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) idle_since_staged = true;
         const double t_now = now_s(t0);
         for (Request *r : out) {
             arena.release(r->off, r->bytes);
@@ -549,8 +553,10 @@ struct dpt_server_ctx {
     // The uploads of the requests admitted so far have completed once the stream
     // is idle; give their ring space back (in allocation order).
     hipError_t release_staged() {
-        hipError_t e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return e;
+        if (!idle_since_staged) {
+            hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return e;
+        }
         {
             std::lock_guard<std::mutex> lk(ring_mu);
             for (size_t off : staged) ring.release(off);
