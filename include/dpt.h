@@ -29,7 +29,9 @@
  *     when the call returns.
  *   - DPT_MEM_DEVICE inputs (HIP device pointers, e.g. a torch tensor's
  *     data_ptr()) are borrowed: they must stay valid and unchanged for the life of
- *     the handle; the library never frees or writes them.
+ *     the handle; the library never frees or writes them.  (A dense Delta whose
+ *     order needs padding, whose dtype differs from the state's or whose address
+ *     is not 16-byte aligned is copied instead.)
  *   - Output buffers are always caller-owned.  Each handle owns its internal
  *     device state; dpt_destroy releases it.
  *   - All device work is ordered on problem.stream (a hipStream_t; NULL means the
@@ -164,6 +166,10 @@ int dpt_step(dpt_handle h, int nsteps, double *last_delta);
 /* Iterate until the stopping rule ends the solve (options of dpt_init).
  * DPT_BF16_FP32: BF16 steps until delta_k < tol or a stall, then FP32 sweeps
  * until delta_k < tol (at least one), then FP64 sweeps when fp64_final_tol > 0.
+ * The stopping rule sees every step's delta in order (with check_every = 1);
+ * dense problems of padded order 64 run several steps per launch and the state
+ * ends on the step the rule stops at (later speculative steps are discarded),
+ * bitwise as with one launch per step.
  * Returns the status (also in r->status when r != NULL) or an error. */
 int dpt_solve(dpt_handle h, dpt_result *r);
 
@@ -226,8 +232,9 @@ int dpt_profile_read(dpt_handle h, dpt_profile *out);
  * phase (replayed as a HIP graph when use_graph != 0); each problem follows
  * its own stopping rule and is retired individually (freeing its memory for
  * the next admissions).  Results do not depend on which other problems share
- * a step: every problem is computed with the same 64x64 tiles and its own
- * statistics. */
+ * a step: every problem is computed with tiles chosen from its own padded
+ * order and phase (64x64, or 128x128 from a threshold fixed when the server
+ * opens) and with its own statistics. */
 typedef struct dpt_server_ctx *dpt_server;
 
 typedef struct dpt_serve_config {

@@ -422,7 +422,7 @@ int do_step(dpt_ctx *c) {
     return c->sp ? sparse_step(c->sp, c->lambda, c->theta, c->stats, &c->k, c->stream, &c->prof) : dense_step(c);
 }
 
-// Copy the stats of steps [k0, k1) to the pinned mirror and synchronise.
+// Copy the stats of steps [k0, k1) to the host mirror and synchronise.
 int fetch_stats(dpt_ctx *c, int64_t k0, int64_t k1) {
     if (k1 <= k0) return DPT_OK;
     if (k1 - k0 > kStatRing) k0 = k1 - kStatRing;
