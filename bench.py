@@ -523,6 +523,18 @@ def main():
            "gemm_fp8_tflops": round(flop / (g8[0] / max(g8[1], 1) * 1e-3) / 1e12, 2),
            "frac_fp8_peak": round(flop / (g8[0] / max(g8[1], 1) * 1e-3) / 1e12 / PEAK_FP8_TFLOPS, 4)}
 
+    # ---- split-BF16 sweeps (experiment): BF16 steps, then FP32-grade sweeps whose
+    # product is three BF16 products of split operands (same rule)
+    elx, rsx, hsx, profx, e_x3 = timed_solves(dpt, spec, opts(dpt.DPT_BF16_X3, rule), n, 1, 1)
+    gx = profx.get("gemm_x3", (float("nan"), 1))
+    gx_ms = gx[0] / max(gx[1], 1)
+    x3 = {"ms_per_solve": round(1e3 * elx, 2), "iters": [rsx[0]["iters_bf16"], rsx[0]["iters_fp32"]],
+          "gemm_x3_ms": round(gx_ms, 4),
+          "fp32_equivalent_tflops": round(flop / (gx_ms * 1e-3) / 1e12, 2),
+          "bf16_tflops_executed": round(3 * flop / (gx_ms * 1e-3) / 1e12, 2),
+          "frac_bf16_peak": round(3 * flop / (gx_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+          "speedup_vs_bf16_fp32": round(ms_per_solve / (1e3 * elx), 3)}
+
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_solve, 3),
@@ -544,6 +556,7 @@ def main():
         "speedup_vs_fp32": (round(fp32["ms_per_solve"] / ms_per_solve, 3) if fp32 else None),
         "other_stop_rule": {"rule": other, **other_rule},
         "fp8_fp32_experiment": fp8,
+        "bf16_x3_experiment": x3,
     }
 
     # ---- FP64 oracle on 64 sampled rows: converged reference and CPU baseline
@@ -570,8 +583,9 @@ def main():
         if f_handles:
             err["fp32"] = accuracy(dpt, f_handles[-1], e_fp32, theta, ref, rows, z_scale)
         err["fp8_fp32"] = accuracy(dpt, hs8[-1], e_fp8, theta, ref, rows, z_scale)
+        err["bf16_x3"] = accuracy(dpt, hsx[-1], e_x3, theta, ref, rows, z_scale)
         out["error_vs_fp64_oracle"] = err
-    for h in handles + f_handles + hs8:
+    for h in handles + f_handles + hs8 + hsx:
         dpt.dpt_destroy(h)
     if args.serve_requests > 0:
         print("# serving trace of %d requests" % args.serve_requests, file=sys.stderr, flush=True)

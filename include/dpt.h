@@ -71,6 +71,11 @@ extern "C" {
 #define DPT_FP8_FP32 3   /* experiment: block-scaled FP8 (OCP E4M3, E8M0 scale per 32   *
                           * values) products until stall, then FP32; dense problems    *
                           * with N >= 1024 only (DPT_EINVAL otherwise)                 */
+#define DPT_BF16_X3 4    /* experiment: BF16 products until stall, then FP32-grade      *
+                          * sweeps whose product is formed on BF16 matrix cores from   *
+                          * split operands x = h + l (h = bf16(x), l = bf16(x - h)):   *
+                          * W_h D_h^T + W_l D_h^T + W_h D_l^T with FP32 accumulation;  *
+                          * dense problems with N >= 1024 only (DPT_EINVAL otherwise)  */
 
 /* ---- storage ---------------------------------------------------------- */
 #define DPT_DENSE 0
@@ -107,7 +112,7 @@ typedef struct dpt_options {
     double stall_ratio;     /* stall when delta_k >= stall_ratio * min_{j<k} delta_j ...  */
     double blowup;          /* DIVERGED when max |Z - I| exceeds this (> 0)               */
     int32_t max_iter;       /* >= 0; cap on applications of F over all phases              */
-    int32_t precision;      /* DPT_FP64, DPT_FP32, DPT_BF16_FP32 or DPT_FP8_FP32           */
+    int32_t precision;      /* DPT_FP64, DPT_FP32, DPT_BF16_FP32, DPT_FP8_FP32, DPT_BF16_X3 */
     int32_t stall_patience; /* ... for this many consecutive checks (>= 1), or delta_k = 0 */
     int32_t check_every;    /* read delta back every this many steps (>= 1)                */
     int32_t stop_rule;      /* DPT_STOP_DELTA (default) or DPT_STOP_ESTIMATE               */
@@ -131,7 +136,7 @@ typedef struct dpt_result {
     int32_t status;         /* DPT_OK / NOT_CONVERGED / STALLED / DIVERGED                */
     int32_t iters;          /* applications of F made by this call                         */
     int32_t iters_bf16;     /* steps of the reduced-precision phase (BF16, or FP8)        */
-    int32_t iters_fp32;
+    int32_t iters_fp32;     /* FP32-grade sweeps (FP32, or split BF16 for DPT_BF16_X3)  */
     int32_t iters_fp64;
 } dpt_result;
 
@@ -211,6 +216,7 @@ int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, doub
 #define DPT_PROF_GEMM_FP64 4  /* fused FP64 MFMA product + update                */
 #define DPT_PROF_SPMM 5       /* fused CSR product + update                       */
 #define DPT_PROF_GEMM_FP8 6   /* fused block-scaled FP8 MFMA product + update     */
+#define DPT_PROF_GEMM_X3 7    /* fused split-BF16 MFMA product + update (sweeps)  */
 #define DPT_PROF_KINDS 8
 
 typedef struct dpt_profile {

@@ -56,7 +56,7 @@ bool valid_options(const dpt_options *o) {
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return false;
     if (o->max_iter < 0) return false;
     if (o->precision != DPT_FP64 && o->precision != DPT_FP32 && o->precision != DPT_BF16_FP32 &&
-        o->precision != DPT_FP8_FP32)
+        o->precision != DPT_FP8_FP32 && o->precision != DPT_BF16_X3)
         return false;
     if (!(o->fp64_final_tol >= 0.0) || !std::isfinite(o->fp64_final_tol)) return false;
     if (!(o->stall_ratio >= 0.0) || !(o->stall_ratio <= 1.0)) return false;
@@ -219,6 +219,8 @@ struct dpt_ctx {
     __bf16 *db16 = nullptr;
     bool d32_own = false, d64_own = false;
 
+    // split BF16 operands (DPT_BF16_X3): ld x 3ld, Delta as [h | h | l], W as [h | l | h]
+    __bf16 *Dx3 = nullptr, *Wx3[2] = {nullptr, nullptr};
     // block-scaled FP8 copies (DPT_FP8_FP32): values and E8M0 scales per 32 values
     unsigned char *dq8 = nullptr, *ds8 = nullptr;
     unsigned char *Wq8[2] = {nullptr, nullptr}, *Ws8[2] = {nullptr, nullptr};
@@ -239,7 +241,7 @@ struct dpt_ctx {
     ~dpt_ctx() {
         if (sp) sparse_destroy(sp);
         void *own[] = {theta, dvec, evec, stats, db16, W32[0], W32[1], Wb[0], Wb[1], W64[0], W64[1],
-                       dq8, ds8, Wq8[0], Wq8[1], Ws8[0], Ws8[1], small_hist};
+                       dq8, ds8, Wq8[0], Wq8[1], Ws8[0], Ws8[1], small_hist, Dx3, Wx3[0], Wx3[1]};
         for (void *p : own)
             if (p) (void)hipFree(p);
         if (dT32 && dT32 != d32) (void)hipFree(dT32);
@@ -355,6 +357,14 @@ StepArgs step_args(dpt_ctx *c, unsigned long long *slot) {
     return a;
 }
 
+// Leave the reduced-precision phase.  DPT_BF16_X3 sweeps read the split form
+// of the current state, made here from its FP32 copy.
+int enter_fp32(dpt_ctx *c) {
+    c->phase = PH_FP32;
+    if (c->opt.precision == DPT_BF16_X3) DPT_TRY(launch_split_x3(c->W32[c->cur], c->ld, 0, c->Wx3[c->cur], c->stream));
+    return DPT_OK;
+}
+
 // Switch the state to the FP64 phase (upcast the FP32 state).
 int enter_fp64(dpt_ctx *c) {
     int rc = ensure_f64(c);
@@ -398,6 +408,9 @@ int dense_step(dpt_ctx *c) {
         if (c->phase == PH_FP64) {
             pf.begin(DPT_PROF_GEMM_FP64, s);
             e = launch_step_f64(a, c->W64[c->cur], c->d64, c->dT64, c->W64[nx], s);
+        } else if (c->phase == PH_FP32 && c->opt.precision == DPT_BF16_X3) {
+            pf.begin(DPT_PROF_GEMM_X3, s);
+            e = launch_step_x3_large(a, c->Wx3[c->cur], c->Dx3, c->dT32, c->W32[c->cur], c->W32[nx], c->Wx3[nx], s);
         } else if (c->phase == PH_FP32) {
             pf.begin(DPT_PROF_GEMM_FP32, s);
             e = launch_step_f32(a, c->W32[c->cur], c->d32, c->dT32, c->W32[nx], nullptr, s);
@@ -573,7 +586,7 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
             c->symmetric = host_symmetric(p);
         } else {
             // the BF16 form of Delta comes out of the same pass over it
-            if (prec == DPT_BF16_FP32) DPT_TRY(dalloc(&c->db16, nn));
+            if (prec == DPT_BF16_FP32 || prec == DPT_BF16_X3) DPT_TRY(dalloc(&c->db16, nn));
             int rc = device_symmetric<float>(c, c->d32, c->db16, &c->symmetric);
             if (rc != DPT_OK) return rc;
         }
@@ -615,12 +628,17 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
             DPT_TRY(dalloc(&c->W32[i], nn));
             if (i == 0 || prec == DPT_FP8_FP32) DPT_TRY(launch_fill_zero(c->W32[i], nn * 4, s));
         }
-        if (prec == DPT_BF16_FP32) {
+        if (prec == DPT_BF16_FP32 || prec == DPT_BF16_X3) {
             if (!c->db16) {
                 DPT_TRY(dalloc(&c->db16, nn));
                 DPT_TRY(launch_cvt_f32_to_bf16(c->db16, c->d32, (int64_t)nn, s));
             }
             for (int i = 0; i < 2; ++i) DPT_TRY(dalloc(&c->Wb[i], nn));
+            if (prec == DPT_BF16_X3) {  // split operands for the FP32-grade sweeps
+                DPT_TRY(dalloc(&c->Dx3, 3 * nn));
+                DPT_TRY(launch_split_x3(c->d32, ld, 1, c->Dx3, s));
+                for (int i = 0; i < 2; ++i) DPT_TRY(dalloc(&c->Wx3[i], 3 * nn));
+            }
             c->phase = PH_BF16;
         } else if (prec == DPT_FP8_FP32) {
             DPT_TRY(dalloc(&c->dq8, nn));
@@ -637,7 +655,8 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
         }
         if (z0) {
             DPT_TRY(launch_load_state_f32(c->W32[0], z0, p->dtype == DPT_DTYPE_F64, c->n, ld, s));
-            if (prec == DPT_BF16_FP32) DPT_TRY(launch_cvt_f32_to_bf16(c->Wb[0], c->W32[0], (int64_t)nn, s));
+            if (prec == DPT_BF16_FP32 || prec == DPT_BF16_X3)
+                DPT_TRY(launch_cvt_f32_to_bf16(c->Wb[0], c->W32[0], (int64_t)nn, s));
             if (prec == DPT_FP8_FP32) DPT_TRY(launch_quant_fp8(c->W32[0], ld, c->Wq8[0], c->Ws8[0], s));
             c->at_identity = false;
         }
@@ -706,9 +725,9 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
     int rc = dpt_validate(p, o);
     if (rc != DPT_OK) return rc;
     if (p->format == DPT_CSR && z0) return DPT_EINVAL;  // warm start: dense problems only
-    if (o && o->precision == DPT_FP8_FP32 &&
+    if (o && (o->precision == DPT_FP8_FP32 || o->precision == DPT_BF16_X3) &&
         (p->format != DPT_DENSE || !step_large_supported(pad_order(p->n))))
-        return DPT_EINVAL;  // the FP8 product exists for large dense problems only
+        return DPT_EINVAL;  // the FP8 and split-BF16 products exist for large dense problems only
     rc = check_device();
     if (rc != DPT_OK) return rc;
     if (!device_inputs_ok(p, z0)) return DPT_EINVAL;
@@ -825,7 +844,8 @@ int dpt_solve(dpt_handle h, dpt_result *r) {
         stat_of(h, h->k - 1, &dl, &wm);
         switch (ctl.update(dl, wm)) {
             case Controller::TO_FP32:
-                h->phase = PH_FP32;
+                rc = enter_fp32(h);
+                if (rc != DPT_OK) return rc;
                 break;
             case Controller::TO_FP64:
                 rc = enter_fp64(h);

@@ -127,7 +127,9 @@ __device__ __forceinline__ unsigned quant_fp8_x4(const float v[4], unsigned *sca
 }
 
 // Output forms of the shared epilogue.
-enum EpiOut { EPI_F32 = 0, EPI_BF16 = 1, EPI_FP8 = 2 };
+// EPI_X3 writes the split BF16 form of W' (h = bf16(w), l = bf16(w - h)) as
+// row n of the N x 3N operand [h | l | h] (row stride 3 ld).
+enum EpiOut { EPI_F32 = 0, EPI_BF16 = 1, EPI_FP8 = 2, EPI_X3 = 3 };
 
 template <int OUT>
 __device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[TM][TN], const float *__restrict__ deltaT,
@@ -197,7 +199,23 @@ __device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[
                     uint2 packed;
                     __builtin_memcpy(&packed, b4, sizeof(packed));
                     *reinterpret_cast<uint2 *>(&Wbnew[idx]) = packed;
-                } else if (OUT == EPI_FP8) {  // 8 lanes = the 32 columns of one scale block
+                } else if (OUT == EPI_X3) {
+                float hv[4], lv[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    hv[e] = (float)(__bf16)w[e];
+                    lv[e] = w[e] - hv[e];
+                }
+                const __bf16 h4[4] = {(__bf16)hv[0], (__bf16)hv[1], (__bf16)hv[2], (__bf16)hv[3]};
+                const __bf16 l4[4] = {(__bf16)lv[0], (__bf16)lv[1], (__bf16)lv[2], (__bf16)lv[3]};
+                uint2 ph, pl;
+                __builtin_memcpy(&ph, h4, sizeof(ph));
+                __builtin_memcpy(&pl, l4, sizeof(pl));
+                __bf16 *row = Wbnew + n * (3 * ld) + m0;
+                *reinterpret_cast<uint2 *>(row) = ph;
+                *reinterpret_cast<uint2 *>(row + ld) = pl;
+                *reinterpret_cast<uint2 *>(row + 2 * ld) = ph;
+            } else if (OUT == EPI_FP8) {  // 8 lanes = the 32 columns of one scale block
                     const float v4[4] = {w[0], w[1], w[2], w[3]};
                     unsigned sc;
                     *reinterpret_cast<unsigned *>(&Wqnew[idx]) = quant_fp8_x4(v4, &sc);
@@ -222,21 +240,28 @@ __device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[
 // supplies row fr of a 32-row block and, at half h and substep s, logical chunk
 // 4h + 2fg + s; blocks 32 rows apart differ in key8 by 4 when the block index
 // is odd.
+//
+// X3 (the split form): A and B are N x 3N with row stride 3 ld, A = [Wh | Wl | Wh]
+// and B = [Dh | Dh | Dl] (h = bf16(x), l = bf16(x - h)), so the one product over
+// K = 3 ld is Wh Dh^T + Wl Dh^T + Wh Dl^T, everything but the l x l term; the
+// epilogue writes the split form of W' in the same layout.
+template <bool X3>
 __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict__ A, const __bf16 *__restrict__ B,
                                                         const float *__restrict__ deltaT,
                                                         const float *__restrict__ Wold, float *__restrict__ Wnew,
                                                         __bf16 *__restrict__ Wbnew, StepArgs a, int tiles_m,
                                                         int tiles_n) {
+    constexpr int KM = X3 ? 3 : 1;  // operand columns per state column
     __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
     int tm, tn;
     tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
     const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
-    const int ktiles = (int)(a.ld * 2 / ROW);  // a multiple of 4
+    const int ktiles = (int)(KM * a.ld * 2 / ROW);  // a multiple of 4
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave / WN, wc = wave % WN;
     TileLoader ld;
-    ld.init(A, B, row0, col0, a.ld * 2, wave, lane);
+    ld.init(A, B, row0, col0, KM * a.ld * 2, wave, lane);
 
     floatx16_t acc[TM][TN];
 #pragma unroll
@@ -325,7 +350,8 @@ __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict
 #undef DPT_INTERLEAVE
 #undef DPT_MMA
 #undef DPT_FRAGS
-    epilogue<EPI_BF16>(smem, acc, deltaT, Wold, Wnew, Wbnew, nullptr, nullptr, a, row0, col0, tid, lane, wave, wr, wc);
+    epilogue<X3 ? EPI_X3 : EPI_BF16>(smem, acc, deltaT, Wold, Wnew, Wbnew, nullptr, nullptr, a, row0, col0, tid, lane,
+                                     wave, wr, wc);
 }
 
 // ---------------------------------------------------------------------------
@@ -605,8 +631,42 @@ hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __b
                                   const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
     if (!step_large_supported(a.ld) || !Wbn) return hipErrorInvalidValue;
     const int tiles_m = (int)(a.ld / BM), tiles_n = (int)(a.ld / BN);
-    hipLaunchKernelGGL(k_step_bf16_large, dim3((unsigned int)(tiles_m * tiles_n)), dim3(NT), 0, s, Wb, Deltab,
+    hipLaunchKernelGGL(k_step_bf16_large<false>, dim3((unsigned int)(tiles_m * tiles_n)), dim3(NT), 0, s, Wb, Deltab,
                        deltaT, W, Wn, Wbn, a, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_x3_large(const StepArgs &a, const __bf16 *Wx3, const __bf16 *Dx3, const float *deltaT,
+                                const float *W, float *Wn, __bf16 *Wx3n, hipStream_t s) {
+    if (!step_large_supported(a.ld) || !Wx3n) return hipErrorInvalidValue;
+    const int tiles_m = (int)(a.ld / BM), tiles_n = (int)(a.ld / BN);
+    hipLaunchKernelGGL(k_step_bf16_large<true>, dim3((unsigned int)(tiles_m * tiles_n)), dim3(NT), 0, s, Wx3, Dx3,
+                       deltaT, W, Wn, Wx3n, a, tiles_m, tiles_n);
+    return hipGetLastError();
+}
+
+// Split form of an ld x ld FP32 matrix into the ld x 3 ld BF16 layout
+// [h | l | h] (pattern 0, for W) or [h | h | l] (pattern 1, for Delta).
+__global__ __launch_bounds__(256) void k_split_x3(const float *__restrict__ src, int64_t ld, int pattern,
+                                                  __bf16 *__restrict__ dst) {
+    const int64_t total = ld * ld;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / ld, c = i - r * ld;
+        const float x = src[i];
+        const __bf16 h = (__bf16)x;
+        const __bf16 l = (__bf16)(x - (float)h);
+        __bf16 *row = dst + r * (3 * ld) + c;
+        row[0] = h;
+        row[ld] = pattern == 0 ? l : h;
+        row[2 * ld] = pattern == 0 ? h : l;
+    }
+}
+
+hipError_t launch_split_x3(const float *src, int64_t ld, int pattern, __bf16 *dst, hipStream_t s) {
+    const int64_t total = ld * ld;
+    const unsigned int blocks = (unsigned int)std::min<int64_t>((total + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(k_split_x3, dim3(blocks), dim3(256), 0, s, src, ld, pattern, dst);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libdpt.so")
 
 DPT_OK, DPT_NOT_CONVERGED, DPT_STALLED, DPT_DIVERGED, DPT_EAGAIN = 0, 1, 2, 3, 4
 DPT_EINVAL, DPT_ENOMEM, DPT_EDEVICE, DPT_ESTATE = -1, -2, -3, -4
-DPT_FP64, DPT_FP32, DPT_BF16_FP32, DPT_FP8_FP32 = 0, 1, 2, 3
+DPT_FP64, DPT_FP32, DPT_BF16_FP32, DPT_FP8_FP32, DPT_BF16_X3 = 0, 1, 2, 3, 4
 DPT_DENSE, DPT_CSR = 0, 1
 DPT_MEM_HOST, DPT_MEM_DEVICE = 0, 1
 DPT_DTYPE_F64, DPT_DTYPE_F32 = 0, 1
@@ -79,7 +79,7 @@ class Result(ctypes.Structure):
 
 
 DPT_PROF_KINDS = 8
-PROF_NAMES = ["first_iterate", "prepass", "gemm_bf16", "gemm_fp32", "gemm_fp64", "spmm", "gemm_fp8", "k7"]
+PROF_NAMES = ["first_iterate", "prepass", "gemm_bf16", "gemm_fp32", "gemm_fp64", "spmm", "gemm_fp8", "gemm_x3"]
 
 
 class Profile(ctypes.Structure):
