@@ -219,7 +219,7 @@ struct dpt_ctx {
     __bf16 *db16 = nullptr;
     bool d32_own = false, d64_own = false;
 
-    // split BF16 operands (DPT_BF16_X3): ld x 3ld, Delta as [h | h | l], W as [h | l | h]
+    // split BF16 operands (DPT_BF16_X3): ld x 2ld, [h | l] of Delta and of W
     __bf16 *Dx3 = nullptr, *Wx3[2] = {nullptr, nullptr};
     // block-scaled FP8 copies (DPT_FP8_FP32): values and E8M0 scales per 32 values
     unsigned char *dq8 = nullptr, *ds8 = nullptr;
@@ -361,7 +361,7 @@ StepArgs step_args(dpt_ctx *c, unsigned long long *slot) {
 // of the current state, made here from its FP32 copy.
 int enter_fp32(dpt_ctx *c) {
     c->phase = PH_FP32;
-    if (c->opt.precision == DPT_BF16_X3) DPT_TRY(launch_split_x3(c->W32[c->cur], c->ld, 0, c->Wx3[c->cur], c->stream));
+    if (c->opt.precision == DPT_BF16_X3) DPT_TRY(launch_split_x3(c->W32[c->cur], c->ld, c->Wx3[c->cur], c->stream));
     return DPT_OK;
 }
 
@@ -635,9 +635,9 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
             }
             for (int i = 0; i < 2; ++i) DPT_TRY(dalloc(&c->Wb[i], nn));
             if (prec == DPT_BF16_X3) {  // split operands for the FP32-grade sweeps
-                DPT_TRY(dalloc(&c->Dx3, 3 * nn));
-                DPT_TRY(launch_split_x3(c->d32, ld, 1, c->Dx3, s));
-                for (int i = 0; i < 2; ++i) DPT_TRY(dalloc(&c->Wx3[i], 3 * nn));
+                DPT_TRY(dalloc(&c->Dx3, 2 * nn));
+                DPT_TRY(launch_split_x3(c->d32, ld, c->Dx3, s));
+                for (int i = 0; i < 2; ++i) DPT_TRY(dalloc(&c->Wx3[i], 2 * nn));
             }
             c->phase = PH_BF16;
         } else if (prec == DPT_FP8_FP32) {

@@ -98,12 +98,13 @@ bool step_large_supported(int64_t ld);
 bool step_large_preferred(int64_t ld);
 hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                                   const float *W, float *Wn, __bf16 *Wbn, hipStream_t s);
-// Split BF16 form (DPT_BF16_X3): operands ld x 3ld, A = [Wh | Wl | Wh],
-// B = [Dh | Dh | Dl]; writes W' (FP32) and its split form in the layout of A.
+// Split BF16 form (DPT_BF16_X3): operands ld x 2ld, A = [Wh | Wl], B = [Dh | Dl],
+// product Wh Dh^T + Wl Dh^T + Wh Dl^T; writes W' (FP32) and its split form in
+// the layout of A.
 hipError_t launch_step_x3_large(const StepArgs &a, const __bf16 *Wx3, const __bf16 *Dx3, const float *deltaT,
                                 const float *W, float *Wn, __bf16 *Wx3n, hipStream_t s);
-// ld x ld FP32 -> ld x 3ld BF16: [h | l | h] (pattern 0) or [h | h | l] (pattern 1).
-hipError_t launch_split_x3(const float *src, int64_t ld, int pattern, __bf16 *dst, hipStream_t s);
+// ld x ld FP32 -> ld x 2ld BF16 [h | l], h = bf16(x), l = bf16(x - h).
+hipError_t launch_split_x3(const float *src, int64_t ld, __bf16 *dst, hipStream_t s);
 hipError_t launch_step_f32_large(const StepArgs &a, const float *W, const float *Delta, const float *deltaT,
                                  float *Wn, hipStream_t s);
 // FP8 step (large problems only): A = block-scaled FP8 copy of W (Wq values,

@@ -67,9 +67,15 @@ __device__ __forceinline__ void barrier_keep_loads() { asm volatile("s_barrier" 
 // 64w + 8i + lr is lr ^ i, so the lane's byte offset inside instruction i is
 // lr * ldb + (((L & 7) ^ lr ^ i) << 4); ldb (a multiple of 512) leaves the
 // chunk bits free for the XOR with i << 4.
+//
+// Split form (blk != 0): the operands hold two K blocks of blk bytes per row,
+// A = [Wh | Wl] and B = [Dh | Dl], and logical K-tile 3p + b reads physical
+// K-tile p of the block pair (h, h), (l, h), (h, l) for b = 0, 1, 2; the tiles
+// read twice come back within three K-tiles, from L2.
 struct TileLoader {
     const unsigned char *ga, *gb;  // row 64w of the A and B tiles (bytes)
     int64_t ldb;                   // bytes per matrix row
+    int64_t blk = 0;               // split form: bytes per K block (0: plain operands)
     int lane_off;                  // lr * ldb + (((L & 7) ^ lr) << 4)
     int lds_off;                   // 64 w * ROW
 
@@ -86,13 +92,18 @@ struct TileLoader {
     // instructions i in [I0, I1) of issue(): rows 8i .. 8i + 7 of both tiles
     __device__ __forceinline__ void issue_rows(unsigned char *smem, int kt, int slot, int I0, int I1) const {
         unsigned char *sb = smem + slot * STAGE + lds_off;
-        const int64_t ko = (int64_t)kt * ROW;
+        int64_t koa = (int64_t)kt * ROW, kob = koa;
+        if (blk) {
+            const int p = kt / 3, b = kt - 3 * p;
+            koa = (int64_t)p * ROW + (b == 1 ? blk : 0);
+            kob = (int64_t)p * ROW + (b == 2 ? blk : 0);
+        }
 #pragma unroll
         for (int i = I0; i < I1; ++i) {
-            const int64_t off = ko + 8 * i * ldb + (lane_off ^ (i << 4));
-            __builtin_amdgcn_global_load_lds((gbl_void *)(ga + off), (lds_void *)(sb + i * 8 * ROW), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((gbl_void *)(gb + off), (lds_void *)(sb + BM * ROW + i * 8 * ROW), 16,
-                                             0, 0);
+            const int64_t off = 8 * i * ldb + (lane_off ^ (i << 4));
+            __builtin_amdgcn_global_load_lds((gbl_void *)(ga + koa + off), (lds_void *)(sb + i * 8 * ROW), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((gbl_void *)(gb + kob + off), (lds_void *)(sb + BM * ROW + i * 8 * ROW),
+                                             16, 0, 0);
         }
     }
 };
@@ -128,7 +139,7 @@ __device__ __forceinline__ unsigned quant_fp8_x4(const float v[4], unsigned *sca
 
 // Output forms of the shared epilogue.
 // EPI_X3 writes the split BF16 form of W' (h = bf16(w), l = bf16(w - h)) as
-// row n of the N x 3N operand [h | l | h] (row stride 3 ld).
+// row n of the N x 2N operand [h | l] (row stride 2 ld).
 enum EpiOut { EPI_F32 = 0, EPI_BF16 = 1, EPI_FP8 = 2, EPI_X3 = 3 };
 
 template <int OUT>
@@ -211,10 +222,9 @@ __device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[
                 uint2 ph, pl;
                 __builtin_memcpy(&ph, h4, sizeof(ph));
                 __builtin_memcpy(&pl, l4, sizeof(pl));
-                __bf16 *row = Wbnew + n * (3 * ld) + m0;
+                __bf16 *row = Wbnew + n * (2 * ld) + m0;
                 *reinterpret_cast<uint2 *>(row) = ph;
                 *reinterpret_cast<uint2 *>(row + ld) = pl;
-                *reinterpret_cast<uint2 *>(row + 2 * ld) = ph;
             } else if (OUT == EPI_FP8) {  // 8 lanes = the 32 columns of one scale block
                     const float v4[4] = {w[0], w[1], w[2], w[3]};
                     unsigned sc;
@@ -241,10 +251,11 @@ __device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[
 // 4h + 2fg + s; blocks 32 rows apart differ in key8 by 4 when the block index
 // is odd.
 //
-// X3 (the split form): A and B are N x 3N with row stride 3 ld, A = [Wh | Wl | Wh]
-// and B = [Dh | Dh | Dl] (h = bf16(x), l = bf16(x - h)), so the one product over
-// K = 3 ld is Wh Dh^T + Wl Dh^T + Wh Dl^T, everything but the l x l term; the
-// epilogue writes the split form of W' in the same layout.
+// X3 (the split form): A = [Wh | Wl] and B = [Dh | Dl] are N x 2N (row stride
+// 2 ld; h = bf16(x), l = bf16(x - h)) and the K loop runs over 3 ld, pairing the
+// blocks (h, h), (l, h), (h, l) K-tile by K-tile (TileLoader), so the product is
+// Wh Dh^T + Wl Dh^T + Wh Dl^T, everything but the l x l term; the epilogue
+// writes the split form of W' in the layout of A.
 template <bool X3>
 __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict__ A, const __bf16 *__restrict__ B,
                                                         const float *__restrict__ deltaT,
@@ -261,7 +272,8 @@ __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave / WN, wc = wave % WN;
     TileLoader ld;
-    ld.init(A, B, row0, col0, KM * a.ld * 2, wave, lane);
+    ld.init(A, B, row0, col0, (X3 ? 2 : 1) * a.ld * 2, wave, lane);
+    if (X3) ld.blk = a.ld * 2;
 
     floatx16_t acc[TM][TN];
 #pragma unroll
@@ -645,9 +657,8 @@ hipError_t launch_step_x3_large(const StepArgs &a, const __bf16 *Wx3, const __bf
     return hipGetLastError();
 }
 
-// Split form of an ld x ld FP32 matrix into the ld x 3 ld BF16 layout
-// [h | l | h] (pattern 0, for W) or [h | h | l] (pattern 1, for Delta).
-__global__ __launch_bounds__(256) void k_split_x3(const float *__restrict__ src, int64_t ld, int pattern,
+// Split form of an ld x ld FP32 matrix into the ld x 2 ld BF16 layout [h | l].
+__global__ __launch_bounds__(256) void k_split_x3(const float *__restrict__ src, int64_t ld,
                                                   __bf16 *__restrict__ dst) {
     const int64_t total = ld * ld;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
@@ -655,18 +666,16 @@ __global__ __launch_bounds__(256) void k_split_x3(const float *__restrict__ src,
         const int64_t r = i / ld, c = i - r * ld;
         const float x = src[i];
         const __bf16 h = (__bf16)x;
-        const __bf16 l = (__bf16)(x - (float)h);
-        __bf16 *row = dst + r * (3 * ld) + c;
+        __bf16 *row = dst + r * (2 * ld) + c;
         row[0] = h;
-        row[ld] = pattern == 0 ? l : h;
-        row[2 * ld] = pattern == 0 ? h : l;
+        row[ld] = (__bf16)(x - (float)h);
     }
 }
 
-hipError_t launch_split_x3(const float *src, int64_t ld, int pattern, __bf16 *dst, hipStream_t s) {
+hipError_t launch_split_x3(const float *src, int64_t ld, __bf16 *dst, hipStream_t s) {
     const int64_t total = ld * ld;
     const unsigned int blocks = (unsigned int)std::min<int64_t>((total + 255) / 256, 1 << 16);
-    hipLaunchKernelGGL(k_split_x3, dim3(blocks), dim3(256), 0, s, src, ld, pattern, dst);
+    hipLaunchKernelGGL(k_split_x3, dim3(blocks), dim3(256), 0, s, src, ld, dst);
     return hipGetLastError();
 }
 
