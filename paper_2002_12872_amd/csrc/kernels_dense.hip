@@ -151,29 +151,62 @@ __global__ __launch_bounds__(256) void k_symmetry_check(const T *__restrict__ sr
 
 // ----------------------------------------------------------- first iterate
 // F(I) = I + lambda gap * Delta'  (the Hadamard with the gap removes any diagonal).
-// Block b covers rows b, b + gridDim.x, ...; 4 consecutive columns per thread
-// (ld is a multiple of 64); one statistics publish per block.
+//
+// lambda d / (th_n - th_m) rounded to the state type, with the gap taken in
+// FP64.  FP64 state: the correctly rounded quotient.  FP32 state: the FP64
+// reciprocal of the gap from the hardware estimate and two Newton steps (each
+// squares the relative error, so the product carries a few FP64 ulps), then
+// one rounding to FP32; this differs from the rounded exact quotient only where
+// the quotient lies within a few FP64 ulps of an FP32 rounding boundary, and
+// costs a fraction of the FP64 division sequence, which bound the first
+// iterate by arithmetic rather than by memory.
 template <typename T>
-__device__ __forceinline__ void first_iterate_rows(const StepArgs &a, const T *__restrict__ dT, T *__restrict__ W,
-                                                   __bf16 *__restrict__ Wb, int64_t n0, int64_t nstride) {
-    double dmax = 0.0;
+__device__ __forceinline__ T gap_quotient(double lam_d, double th_n, double th_m) {
+    const double g = th_n - th_m;
+    if constexpr (sizeof(T) == 8) {
+        return lam_d / g;
+    } else {
+        double r = __builtin_amdgcn_rcp(g);
+        r = fma(r, fma(-g, r, 1.0), r);
+        r = fma(r, fma(-g, r, 1.0), r);
+        return (T)(lam_d * r);
+    }
+}
+
+// Block (bx, by) covers columns [bx CW, bx CW + CW) of rows by R + q, (by + gy)
+// R + q, ... (R = 1024 / CW rows per pass, q = thread / (CW / 4)); each thread
+// holds theta of its 4 consecutive columns in registers for all its rows.  CW
+// is 1024, or the padded order when that is smaller (ld is a multiple of 64);
+// one statistics publish per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_first_iterate(StepArgs a, const T *__restrict__ dT, T *__restrict__ W,
+                                                       __bf16 *__restrict__ Wb, int cw) {
+    const int tpr = cw >> 2, rpb = 256 / tpr;
+    const int64_t m0 = (int64_t)blockIdx.x * cw + 4 * (threadIdx.x % tpr);
+    const int64_t nstride = (int64_t)gridDim.y * rpb;
+    double th_m[4];
+    bool col_ok[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        col_ok[q] = m0 + q < a.n;
+        th_m[q] = m0 + q < a.ld ? a.theta[m0 + q] : 0.0;
+    }
+    T amax = (T)0;
     bool bad = false;
-    for (int64_t n = n0; n < a.ld; n += nstride) {
-        const double th_n = a.theta[n];
-        const bool row_ok = n < a.n;
-#pragma unroll 4
-        for (int64_t m0 = 4 * (int64_t)threadIdx.x; m0 < a.ld; m0 += 4 * 256) {
+    if (m0 < a.ld) {
+        for (int64_t n = (int64_t)blockIdx.y * rpb + threadIdx.x / tpr; n < a.ld; n += nstride) {
+            const double th_n = a.theta[n];
+            const bool row_ok = n < a.n;
             const int64_t idx = n * a.ld + m0;
             T d[4], w[4];
             load4v(dT + idx, d);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t m = m0 + q;
                 w[q] = (T)0;
-                if (row_ok && m < a.n && m != n) w[q] = (T)(a.lambda * (double)d[q] / (th_n - a.theta[m]));
-                const double v = fabs((double)w[q]);
-                dmax = fmax(dmax, v);
-                bad |= !(v <= DBL_MAX);
+                if (row_ok && col_ok[q] && m0 + q != n) w[q] = gap_quotient<T>(a.lambda * (double)d[q], th_n, th_m[q]);
+                const T v = w[q] < (T)0 ? -w[q] : w[q];
+                amax = v > amax ? v : amax;
+                bad |= !(v <= (sizeof(T) == 8 ? (T)DBL_MAX : (T)FLT_MAX));
             }
             store4v(W + idx, w);
             if (Wb) {
@@ -182,13 +215,7 @@ __device__ __forceinline__ void first_iterate_rows(const StepArgs &a, const T *_
             }
         }
     }
-    publish_stats_block(a.stat, dmax, dmax, bad);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_first_iterate(StepArgs a, const T *__restrict__ dT, T *__restrict__ W,
-                                                       __bf16 *__restrict__ Wb) {
-    first_iterate_rows(a, dT, W, Wb, (int64_t)blockIdx.x, (int64_t)gridDim.x);
+    publish_stats_block(a.stat, (double)amax, (double)amax, bad);
 }
 
 // ---------------------------------------------------------------- pre-pass
@@ -507,7 +534,7 @@ __global__ __launch_bounds__(256) void k_small_steps(const S *__restrict__ Wcur,
                 for (int e = 0; e < 4; ++e) {
                     const int64_t m = c4 + e;
                     w[e] = (S)0;
-                    if (row_ok && m < a.n && m != n) w[e] = (S)(a.lambda * (double)dv[e] / (th_n - a.theta[m]));
+                    if (row_ok && m < a.n && m != n) w[e] = gap_quotient<S>(a.lambda * (double)dv[e], th_n, a.theta[m]);
                     const double v = fabs((double)w[e]);
                     dmax = fmax(dmax, v);
                     bad |= !(v <= DBL_MAX);
@@ -757,18 +784,25 @@ hipError_t launch_symmetry_check_f64(const double *src, int64_t ld, unsigned int
 // One row per block up to 256 rows, then up to 16 rows per block, at most 1024
 // blocks: enough loads in flight to stream at HBM rate with few statistics
 // atomics (one publish per block).
-inline unsigned int first_iterate_grid(int64_t ld) {
-    return (unsigned int)std::min<int64_t>(ld, std::min<int64_t>(1024, std::max<int64_t>(256, ld / 16)));
+// column chunk and grid of k_first_iterate: about 2048 blocks at large orders
+// (ld is a multiple of 64, so its lowest set bit is a chunk width of at least 64)
+inline int first_iterate_cw(int64_t ld) { return ld >= 1024 ? 1024 : (int)(ld & -ld); }
+inline dim3 first_iterate_grid(int64_t ld, int cw) {
+    const int64_t gx = (ld + cw - 1) / cw, rpb = 256 / (cw / 4);
+    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>((ld + rpb - 1) / rpb, 2048 / gx));
+    return dim3((unsigned int)gx, (unsigned int)gy);
 }
 
 hipError_t launch_first_iterate_f32(const StepArgs &a, const float *deltaT, float *W, __bf16 *Wb, hipStream_t s) {
-    hipLaunchKernelGGL((k_first_iterate<float>), dim3(first_iterate_grid(a.ld)), dim3(256), 0, s, a, deltaT, W, Wb);
+    const int cw = first_iterate_cw(a.ld);
+    hipLaunchKernelGGL((k_first_iterate<float>), first_iterate_grid(a.ld, cw), dim3(256), 0, s, a, deltaT, W, Wb, cw);
     return hipGetLastError();
 }
 
 hipError_t launch_first_iterate_f64(const StepArgs &a, const double *deltaT, double *W, hipStream_t s) {
-    hipLaunchKernelGGL((k_first_iterate<double>), dim3(first_iterate_grid(a.ld)), dim3(256), 0, s, a, deltaT, W,
-                       (__bf16 *)nullptr);
+    const int cw = first_iterate_cw(a.ld);
+    hipLaunchKernelGGL((k_first_iterate<double>), first_iterate_grid(a.ld, cw), dim3(256), 0, s, a, deltaT, W,
+                       (__bf16 *)nullptr, cw);
     return hipGetLastError();
 }
 
