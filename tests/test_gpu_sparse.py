@@ -201,6 +201,26 @@ def test_dominant_needs_only_theta_index_simple(mem):
     assert ei.value.code == dpt.DPT_EINVAL
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dominant_order_beyond_l2(precision):
+    """N = 2^20 (3.4e7 non-zeros): z (4 MiB in FP32, 8 MiB in FP64) no longer
+    fits one XCD's L2, so most gathers are served from the Infinity Cache; the
+    FP64 and FP32 solves must still reach the oracle's row n - 1."""
+    n = 1 << 20
+    theta, ip, ix, v = workloads.sparse_sym(1, n=n)
+    dtype = np.float64 if precision == 0 else np.float32
+    spec = dpt.ProblemSpec(theta, (ip, ix, v.astype(dtype)), 1.0, stream=0)
+    tol = 1e-14 if precision == 0 else 1e-6
+    ev, vec, res = dpt.dpt_dominant(spec, dpt.options(tol=tol, max_iter=50, precision=precision))
+    assert res["status"] == dpt.DPT_OK
+    ref = oracle.iterate(theta, (ip, ix, v.astype(np.float64)), 1.0, rows=[n - 1], max_iter=50, tol=tol)
+    assert abs(res["iters"] - ref["iters"]) <= 1
+    etol = 1e-12 if precision == 0 else 1e-6
+    assert abs(ev - ref["e"][0]) <= etol * abs(ref["e"][0])
+    assert vec[n - 1] == 1.0
+    assert np.max(np.abs(vec - ref["z"][0])) <= (1e-12 if precision == 0 else 1e-6)
+
+
 @pytest.mark.slow
 def test_paper_scale_dominant_pair():
     """Dominant pair of the 1.34e8-nonzero matrix (N = 2^22, the size of the
