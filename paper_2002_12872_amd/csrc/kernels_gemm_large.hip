@@ -241,12 +241,15 @@ __device__ __forceinline__ void epilogue(unsigned char *smem, floatx16_t (&acc)[
 // ---------------------------------------------------------------------------
 // BF16 step.  A K-tile (64 values) is consumed as two halves of K = 32 whose
 // fragments go to two register sets (fa0/fb0, fa1/fb1): half 1 is read while
-// half 0 multiplies.  The barrier (tile kt+1 landed, tile kt fully read) sits
-// before the last substep, whose MFMAs cover the reads of tile kt+1's first
-// half and the first half of the refill of tile kt's slot with tile kt+2; the
-// other half of the refill runs under the first substep of the next K-tile
-// (the loads of four waves issued in one substep back up behind the CU's
-// vector-memory path and stall the MFMA issue).  Fragments: lane (fr, fg)
+// half 0 multiplies, so after the first of the four substeps every fragment of
+// tile kt is in registers.  A first barrier there frees tile kt's slot, and its
+// refill with tile kt+2 runs under substeps 2 and 3 (8 loads each: issued in
+// one substep, the loads of four waves back up behind the CU's vector-memory
+// path and stall the MFMA issue); a second barrier before the last substep
+// waits for tile kt+1, whose first half is read under that substep.  A refill
+// thus has about 1.5 K-tiles of MFMA work to arrive, and up to two tiles per CU
+// are in flight: the operand stream into LDS is latency-bound, and one tile in
+// flight sustains about 12 TB/s against 15 TB/s for two.  Fragments: lane (fr, fg)
 // supplies row fr of a 32-row block and, at half h and substep s, logical chunk
 // 4h + 2fg + s; blocks 32 rows apart differ in key8 by 4 when the block index
 // is odd.
@@ -320,36 +323,39 @@ __global__ __launch_bounds__(NT) void k_step_bf16_large(const __bf16 *__restrict
         }                                                                                                            \
     } while (0)
 
-    // prologue: tile 0 and the first rows of tile 1 in flight, wait for tile 0,
-    // read its first half
+    // prologue: tiles 0 and 1 in flight, wait for tile 0, read its first half
     ld.issue(smem, 0, 0);
-    ld.issue_rows(smem, 1, 1, 0, 4);
-    wait_vmcnt<8>();
+    ld.issue(smem, 1, 1);
+    wait_vmcnt<16>();
     barrier_keep_loads();
     DPT_FRAGS(fa0, fb0, 0, 0);
     for (int kt = 0; kt < ktiles - 1; ++kt) {
         const int slot = kt & 1;
         DPT_MMA(fa0, fb0, 0);
-        ld.issue_rows(smem, kt + 1, slot ^ 1, 4, 8);
-        DPT_VPIN(8);
-        __builtin_amdgcn_sched_barrier(0);
-        DPT_MMA(fa0, fb0, 1);
         DPT_FRAGS(fa1, fb1, slot, 1);
         DPT_INTERLEAVE(0);
         __builtin_amdgcn_sched_barrier(0);
-        DPT_MMA(fa1, fb1, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        // every fragment of tile kt is in registers; tile kt+1 must have landed
+        // every fragment of tile kt is in registers: its slot takes tile kt+2
+        // (past the end: the last tile again, never read)
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        wait_vmcnt<0>();
+        barrier_keep_loads();
+        __builtin_amdgcn_sched_barrier(0);
+        const int refill = min(kt + 2, ktiles - 1);
+        DPT_MMA(fa0, fb0, 1);
+        ld.issue_rows(smem, refill, slot, 0, 4);
+        DPT_VPIN(8);
+        __builtin_amdgcn_sched_barrier(0);
+        DPT_MMA(fa1, fb1, 0);
+        ld.issue_rows(smem, refill, slot, 4, 8);
+        DPT_VPIN(8);
+        __builtin_amdgcn_sched_barrier(0);
+        // tile kt+1 must have landed (only tile kt+2's 16 loads may be pending)
+        wait_vmcnt<16>();
         barrier_keep_loads();
         __builtin_amdgcn_sched_barrier(0);
         DPT_MMA(fa1, fb1, 1);
         DPT_FRAGS(fa0, fb0, slot ^ 1, 0);
-        // start the refill of the freed slot (past the end: the last tile
-        // again, never read)
-        ld.issue_rows(smem, min(kt + 2, ktiles - 1), slot, 0, 4);
-        DPT_INTERLEAVE(8);
+        DPT_INTERLEAVE(0);
         __builtin_amdgcn_sched_barrier(0);
     }
     DPT_MMA(fa0, fb0, 0);
