@@ -38,6 +38,62 @@ def test_sparse_steps_match_oracle(n, precision):
         assert rel_eig_error(e[rows], ref["e"], theta) <= tol
 
 
+def _thin_rows(theta, ip, ix, v, keep):
+    """The CSR with only the entries of rows m where keep(m, count) allows them:
+    rows emptied or cut to their first entry (columns stay sorted)."""
+    rows_out, cols, vals = [0], [], []
+    for m in range(len(ip) - 1):
+        a, b = ip[m], ip[m + 1]
+        k = keep(m, b - a)
+        cols.extend(ix[a:a + k])
+        vals.extend(v[a:a + k])
+        rows_out.append(len(cols))
+    return (np.asarray(rows_out, np.int64), np.asarray(cols, np.int32), np.asarray(vals, v.dtype))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sparse_empty_and_single_entry_rows(precision):
+    """Rows 0..63 empty, rows 64..127 with one entry, the rest as generated (not
+    symmetric any more): the product of an empty row is zero, so those rows keep
+    only the -d_n z_n term; every row must still follow the oracle step by step,
+    and so must the dominant mode."""
+    n = 700
+    dtype = np.float64 if precision == 0 else np.float32
+    theta, (ip, ix, v) = csr_problem(n, 6, dtype)
+    ip, ix, v = _thin_rows(theta, ip, ix, v, lambda m, c: 0 if m < 64 else (min(1, c) if m < 128 else c))
+    v64 = v.astype(np.float64)
+    rows = np.concatenate([np.arange(0, 8), np.arange(60, 70), np.arange(124, 132), workloads.sample_rows(n, 24)])
+    tol = 1e-12 if precision == 0 else 2e-6
+    for k in (1, 3):
+        _, _, e, z = gpu_sparse(theta, (ip, ix, v), 0.8, precision, steps=k)
+        ref = oracle.iterate(theta, (ip, ix, v64), 0.8, rows=rows, max_iter=k, fixed_steps=True)
+        scale = max(1.0, np.abs(ref["z"]).max())
+        assert np.max(np.abs(z[rows] - ref["z"])) <= tol * scale, k
+        assert rel_eig_error(e[rows], ref["e"], theta) <= tol
+    dtol = 1e-14 if precision == 0 else 1e-6
+    ev, vec, res = dpt.dpt_dominant(dpt.ProblemSpec(theta, (ip, ix, v), 0.8, stream=0),
+                                    dpt.options(tol=dtol, max_iter=50, precision=precision), index=30)
+    ref = oracle.iterate(theta, (ip, ix, v64), 0.8, rows=[30], max_iter=50, tol=dtol)
+    assert res["status"] == dpt.DPT_OK
+    assert abs(ev - ref["e"][0]) <= (1e-12 if precision == 0 else 1e-6) * abs(ref["e"][0])
+    assert np.max(np.abs(vec - ref["z"][0])) <= (1e-12 if precision == 0 else 1e-6)
+
+
+def test_sparse_zero_matrix():
+    """No entries at all: F(I) = I, so the first step already has delta = 0 and
+    E = theta; the dominant mode returns e_index and theta_index."""
+    n = 200
+    theta = np.arange(n, dtype=np.float64) * 0.5
+    csr = (np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    h, res, e, z = gpu_sparse(theta, csr, 1.0, dpt.DPT_FP32, tol=1e-6)
+    assert res["status"] == dpt.DPT_OK and res["iters"] == 1
+    assert np.array_equal(e, theta) and np.array_equal(z, np.eye(n))
+    ev, vec, res = dpt.dpt_dominant(dpt.ProblemSpec(theta, csr, 1.0, stream=0),
+                                    dpt.options(tol=1e-6, precision=dpt.DPT_FP32))
+    assert res["status"] == dpt.DPT_OK and ev == theta[-1]
+    assert np.array_equal(vec, np.eye(n, dtype=np.float32)[-1])
+
+
 def test_sparse_solve_matches_oracle_and_dense_path():
     n = 1500
     theta, (ip, ix, v) = csr_problem(n, 2)
