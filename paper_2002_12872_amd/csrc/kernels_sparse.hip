@@ -68,26 +68,28 @@ __global__ void k_zero(T *__restrict__ p, int64_t count) {
 // dpt_validate): rowptr[0] = 0, rowptr[n] = nnz, non-decreasing row pointers,
 // column indices in [0, n) and strictly increasing within a row.  Any violation
 // sets *bad.  Column indices of a row are read only once its pointers are known
-// to lie inside [0, nnz].
-__global__ void k_csr_validate(const int64_t *__restrict__ rowptr, const int *__restrict__ col, int64_t n,
-                               int64_t nnz, unsigned int *bad) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// to lie inside [0, nnz].  8 lanes per row (32 rows per block, grid-stride over
+// row groups), so the column indices are read in coalesced runs; each lane
+// compares its entries with their predecessors in the row.
+__global__ __launch_bounds__(256) void k_csr_validate(const int64_t *__restrict__ rowptr,
+                                                      const int *__restrict__ col, int64_t n, int64_t nnz,
+                                                      unsigned int *bad) {
+    const int sub = threadIdx.x & 7;
     bool err = false;
-    if (i == 0) err = rowptr[0] != 0 || rowptr[n] != nnz;
-    if (i < n) {
-        const int64_t a = rowptr[i], b = rowptr[i + 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) err = rowptr[0] != 0 || rowptr[n] != nnz;
+    for (int64_t m = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3); m < n; m += (int64_t)gridDim.x * 32) {
+        const int64_t a = rowptr[m], b = rowptr[m + 1];
         if (a < 0 || b > nnz || b < a) {
             err = true;
         } else {
-            int prev = -1;
-            for (int64_t e = a; e < b; ++e) {
+            for (int64_t e = a + sub; e < b; e += 8) {
                 const int c = col[e];
-                err |= c <= prev || c >= n;
-                prev = c;
+                err |= c < 0 || c >= n;
+                if (e > a) err |= c <= col[e - 1];
             }
         }
     }
-    if (err) atomicOr(bad, 1u);
+    if (__any(err ? 1 : 0) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
 }
 
 // ZT[m][m] = 1 for m < n (the buffers start as the identity; the steps keep it).
@@ -328,8 +330,27 @@ __global__ __launch_bounds__(256) void k_dom_csr(const int64_t *__restrict__ row
     const int sub = threadIdx.x & 7;
     const int64_t m = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
     T c = (T)0;
-    if (m < n)
-        for (int64_t e = rowptr[m] + sub; e < rowptr[m + 1]; e += 8) c += val[e] * z[col[e]];
+    if (m < n) {
+        // four entries per lane at a time: their four gathers are in flight together
+        const int64_t e1 = rowptr[m + 1];
+        for (int64_t e = rowptr[m] + sub; e < e1; e += 32) {
+            int cc[4];
+            T vv[4];
+            bool in[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                in[u] = e + 8 * u < e1;
+                cc[u] = in[u] ? col[e + 8 * u] : 0;
+                vv[u] = in[u] ? val[e + 8 * u] : (T)0;
+            }
+            T zz[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) zz[u] = z[cc[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (in[u]) c += vv[u] * zz[u];
+        }
+    }
     c += __shfl_xor(c, 4);
     c += __shfl_xor(c, 2);
     c += __shfl_xor(c, 1);
@@ -531,7 +552,7 @@ int stage_csr(const dpt_problem *p, DevCsr<T> *c, hipStream_t s) {
         e = hipMalloc((void **)&flag, sizeof(unsigned int));
         if (e == hipSuccess) {
             hipLaunchKernelGGL((k_zero<unsigned int>), dim3(1), dim3(64), 0, s, flag, (int64_t)1);
-            hipLaunchKernelGGL(k_csr_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s, p->indptr, p->indices, n,
+            hipLaunchKernelGGL(k_csr_validate, dim3(blocks_for(n, 32)), dim3(256), 0, s, p->indptr, p->indices, n,
                                nnz, flag);
             e = hipGetLastError();
             if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, s);
