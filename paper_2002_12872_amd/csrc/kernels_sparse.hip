@@ -314,7 +314,8 @@ __global__ void k_csr_row_dot(const int64_t *rowptr, const int *col, const T *va
     if (threadIdx.x == 0) *s_out = s;
 }
 
-// One iteration of F_{nstar}: 8 lanes per row, 32 rows per block.
+// One iteration of F_{nstar}: 8 lanes per row, 32 rows per block pass
+// (grid-stride over groups of 32 rows).
 template <typename T>
 __global__ __launch_bounds__(256) void k_dom_csr(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
                                                  const T *__restrict__ val, int64_t n, int64_t nstar, double lambda,
@@ -328,42 +329,90 @@ __global__ __launch_bounds__(256) void k_dom_csr(const int64_t *__restrict__ row
     __syncthreads();
     const T s = (T)s_sh;
     const int sub = threadIdx.x & 7;
-    const int64_t m = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
-    T c = (T)0;
-    if (m < n) {
-        // four entries per lane at a time: their four gathers are in flight together
-        const int64_t e1 = rowptr[m + 1];
-        for (int64_t e = rowptr[m] + sub; e < e1; e += 32) {
-            int cc[4];
-            T vv[4];
-            bool in[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                in[u] = e + 8 * u < e1;
-                cc[u] = in[u] ? col[e + 8 * u] : 0;
-                vv[u] = in[u] ? val[e + 8 * u] : (T)0;
-            }
-            T zz[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) zz[u] = z[cc[u]];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (in[u]) c += vv[u] * zz[u];
-        }
-    }
-    c += __shfl_xor(c, 4);
-    c += __shfl_xor(c, 2);
-    c += __shfl_xor(c, 1);
     double dmax = 0.0, wmax = 0.0;
     bool bad = false;
-    if (m < n && sub == 0) {
+    for (int64_t g = (int64_t)blockIdx.x * 32; g < n; g += (int64_t)gridDim.x * 32) {
+        const int64_t m = g + (threadIdx.x >> 3);
+        T c = (T)0;
+        if (m < n) {
+            // four entries per lane at a time: their four gathers are in flight together
+            const int64_t e1 = rowptr[m + 1];
+            for (int64_t e = rowptr[m] + sub; e < e1; e += 32) {
+                int cc[4];
+                T vv[4];
+                bool in[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    in[u] = e + 8 * u < e1;
+                    cc[u] = in[u] ? col[e + 8 * u] : 0;
+                    vv[u] = in[u] ? val[e + 8 * u] : (T)0;
+                }
+                T zz[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) zz[u] = z[cc[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (in[u]) c += vv[u] * zz[u];
+            }
+        }
+        c += __shfl_xor(c, 4);
+        c += __shfl_xor(c, 2);
+        c += __shfl_xor(c, 1);
+        if (m < n && sub == 0) {
+            T w = (T)1;
+            if (m != nstar) w = (T)lambda * (c - s * z[m]) / (T)(theta[nstar] - theta[m]);
+            zn[m] = w;
+            const double dv = fabs((double)w - (double)z[m]);
+            dmax = fmax(dmax, dv);
+            wmax = fmax(wmax, fabs((double)w - (m == nstar ? 1.0 : 0.0)));
+            bad |= !(dv <= DBL_MAX);
+        }
+    }
+    publish_stats_block(stat, dmax, wmax, bad);
+}
+
+// The first iteration, from z = e_nstar, in closed form (the single-line
+// analogue of F(I)): (Delta z)[m] = Delta[m][nstar] and s = Delta[nstar][nstar],
+// so z1[m] = lambda (Delta[m][nstar] - s 0) / (theta_nstar - theta_m) for m !=
+// nstar, with the arithmetic of k_dom_csr / k_dom_dense on e_nstar but without
+// reading the whole matrix.  CSR entries are found by binary search in the
+// row's sorted column indices (absent: 0).  One thread per row, grid-stride.
+template <typename T>
+__device__ __forceinline__ T csr_entry(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
+                                       const T *__restrict__ val, int64_t m, int64_t c) {
+    const int64_t end = rowptr[m + 1];
+    int64_t lo = rowptr[m], hi = end;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (col[mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < end && col[lo] == c ? val[lo] : (T)0;
+}
+
+template <typename T, bool CSR>
+__global__ __launch_bounds__(256) void k_dom_first(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
+                                                   const T *__restrict__ val, int64_t n, int64_t nstar,
+                                                   double lambda, const double *__restrict__ theta,
+                                                   T *__restrict__ zn, unsigned long long *stat) {
+    // dense: val is the n x n row-major matrix
+    const T s = CSR ? csr_entry(rowptr, col, val, nstar, nstar) : val[nstar * n + nstar];
+    double dmax = 0.0, wmax = 0.0;
+    bool bad = false;
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x) {
+        const T z = m == nstar ? (T)1 : (T)0;
         T w = (T)1;
-        if (m != nstar) w = (T)lambda * (c - s * z[m]) / (T)(theta[nstar] - theta[m]);
+        if (m != nstar) {
+            const T c = CSR ? csr_entry(rowptr, col, val, m, nstar) : val[m * n + nstar];
+            w = (T)lambda * (c - s * z) / (T)(theta[nstar] - theta[m]);
+        }
         zn[m] = w;
-        const double dv = fabs((double)w - (double)z[m]);
-        dmax = dv;
-        wmax = fabs((double)w - (m == nstar ? 1.0 : 0.0));
-        bad = !(dv <= DBL_MAX);
+        const double dv = fabs((double)w - (double)z);
+        dmax = fmax(dmax, dv);
+        wmax = fmax(wmax, fabs((double)w - (m == nstar ? 1.0 : 0.0)));
+        bad |= !(dv <= DBL_MAX);
     }
     publish_stats_block(stat, dmax, wmax, bad);
 }
@@ -858,7 +907,16 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
         int cur = 0;
         while (iters < o->max_iter) {
             unsigned long long *st = stats + 2 * iters;
-            if (p->format == DPT_CSR) {
+            if (iters == 0) {  // z = e_nstar: closed form
+                if (p->format == DPT_CSR)
+                    hipLaunchKernelGGL((k_dom_first<T, true>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
+                                       csr.rowptr, csr.col, csr.val, n, nstar, p->lambda, (const double *)theta,
+                                       z[cur ^ 1], st);
+                else
+                    hipLaunchKernelGGL((k_dom_first<T, false>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
+                                       (const int64_t *)nullptr, (const int *)nullptr, (const T *)dense, n, nstar,
+                                       p->lambda, (const double *)theta, z[cur ^ 1], st);
+            } else if (p->format == DPT_CSR) {
                 hipLaunchKernelGGL((k_dom_csr<T>), dim3(blocks_for(n, 32)), dim3(256), 0, s, csr.rowptr, csr.col,
                                    csr.val, n, nstar, p->lambda, (const double *)theta, (const T *)z[cur],
                                    z[cur ^ 1], st);

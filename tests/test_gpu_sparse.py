@@ -135,6 +135,28 @@ def test_dominant_matches_oracle_row(fmt, precision):
     assert np.max(np.abs(vec - ref["z"][0])) <= (1e-12 if precision == 0 else 1e-6)
 
 
+@pytest.mark.parametrize("fmt", ["csr", "dense"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dominant_first_iterate_is_the_closed_form(fmt, precision):
+    """One iteration from e_index is (Sec. II.H's map at z = e) z1[m] =
+    lambda Delta[m][index] / (theta_index - theta_m) for m != index, z1[index] = 1,
+    evaluated in the state's precision; the GPU reads only column `index` of
+    Delta for it and must give exactly these values."""
+    n, idx, lam = 900, 417, 0.8
+    dtype = np.float64 if precision == 0 else np.float32
+    theta, (ip, ix, v) = csr_problem(n, 8, dtype)
+    dense = workloads.csr_to_dense(n, ip, ix, v, dtype=dtype)
+    delta = (ip, ix, v) if fmt == "csr" else dense
+    _, vec, res = dpt.dpt_dominant(dpt.ProblemSpec(theta, delta, lam, stream=0),
+                                   dpt.options(tol=1e-30, max_iter=1, precision=precision), index=idx)
+    assert res["iters"] == 1
+    s = dense[idx, idx]
+    z1 = np.empty(n, dtype)
+    for m in range(n):
+        z1[m] = 1 if m == idx else dtype(lam) * (dense[m, idx] - s * dtype(0)) / dtype(theta[idx] - theta[m])
+    assert np.array_equal(vec, z1)
+
+
 def test_dominant_explicit_index_equals_row_of_full_solve():
     n = 800
     theta, (ip, ix, v) = csr_problem(n, 4, np.float64)
