@@ -9,6 +9,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -150,3 +151,14 @@ def test_init_rejects_invalid_before_touching_device():
     with pytest.raises(dpt.DptError) as ei:
         dpt.dpt_init(p)
     assert ei.value.code == dpt.DPT_EINVAL
+
+
+def test_missing_library_fails_loudly():
+    """No fallback: without the built library the binding raises at load time."""
+    code = ("from paper_2002_12872_amd import dpt\n"
+            "try:\n"
+            "    dpt.load_library('/nonexistent/libdpt.so')\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n")
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert p.returncode == 0 and p.stdout.startswith("raised"), p.stdout + p.stderr
