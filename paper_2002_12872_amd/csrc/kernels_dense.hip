@@ -845,8 +845,14 @@ hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta
     return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
 }
 
+// FP64: from order 4096 on, 128 x 128 tiles of 8 waves (32 x 64 each, two
+// waves per SIMD) and K-tiles of 32 take 139 ms per step at N = 16384 against
+// 154 ms for the 64 x 64 tiles (4 waves, three workgroups per CU); below,
+// 128-wide tiles leave CUs idle.
 hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT, double *Wn,
                            hipStream_t s) {
+    if (a.ld >= 4096 && a.ld % 128 == 0)
+        return launch_gemm<PolF64, 128, 128, 32, 4, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
     return launch_gemm<PolF64, 64, 64, 16, 2, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
 }
 
