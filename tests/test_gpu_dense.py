@@ -314,6 +314,30 @@ def test_runs_are_deterministic():
     assert r1["iters"] == r2["iters"] and np.array_equal(e1, e2) and np.array_equal(z1, z2)
 
 
+def test_recycled_buffers_leave_no_trace():
+    """Small device buffers are recycled across handles (they come back holding
+    the previous handle's data): solves of different orders and precisions,
+    interleaved, with handles destroyed and created again, must repeat their
+    first results exactly, including at the identity (max_iter = 0)."""
+    cases = [(64, dpt.DPT_FP64, 200), (300, dpt.DPT_FP32, 200), (64, dpt.DPT_FP32, 0), (257, dpt.DPT_BF16_FP32, 200),
+             (33, dpt.DPT_FP64, 0)]
+    probs = {n: small_problem(n, 20 + n) for n, _, _ in cases}
+    first = {}
+    for rep in range(3):
+        for n, prec, mi in cases:
+            theta, delta = probs[n]
+            d = delta if prec == dpt.DPT_FP64 else delta.astype(np.float32)
+            h, r, e, z = gpu_run(theta, d, 0.7, prec, max_iter=mi)
+            dpt.dpt_destroy(h)
+            if rep == 0:
+                first[(n, prec, mi)] = (r["iters"], e, z)
+                if mi == 0:
+                    assert np.array_equal(z, np.eye(n))
+            else:
+                it0, e0, z0 = first[(n, prec, mi)]
+                assert r["iters"] == it0 and np.array_equal(e, e0) and np.array_equal(z, z0), (rep, n, prec)
+
+
 def test_device_rejects_duplicate_theta():
     import torch
     theta = torch.tensor([0.0, 1.0, 1.0], dtype=torch.float64, device="cuda")
