@@ -198,7 +198,9 @@ int dpt_residuals(dpt_handle h, int64_t nrows, const int64_t *rows, double *res)
  * (DPT_FP64 -> FP64, otherwise FP32).  eigvec: n values of p->dtype in p->mem
  * (eigvec[index] = 1).  *eigval receives theta_index + lambda (Delta z)[index].
  * Only theta_index has to be simple here (the map divides by theta_index -
- * theta_m alone); other theta values may coincide.  A CSR Delta in device
+ * theta_m alone); other theta values may coincide.  The first iteration, from
+ * e_index, is evaluated in closed form (it reads column index of Delta only,
+ * with the same arithmetic as the general iteration).  A CSR Delta in device
  * memory is checked on the device and borrowed for the call.  Returns the
  * numerical status, or DPT_EINVAL (bad arguments, non-finite theta, theta_index
  * repeated, malformed CSR), DPT_ENOMEM, DPT_EDEVICE. */
