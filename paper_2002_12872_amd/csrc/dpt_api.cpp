@@ -295,6 +295,7 @@ struct dpt_ctx {
     int cur = 0;
     int phase = PH_FP32;
     bool at_identity = true;
+    bool w0_dirty = false;  // W32[0] not yet cleared to the identity state (see clean_identity)
     int64_t k = 0;
 
     SparseState *sp = nullptr;
@@ -419,9 +420,21 @@ StepArgs step_args(dpt_ctx *c, unsigned long long *slot) {
     return a;
 }
 
+// Clear W32[0] to the identity state if it has not been written yet; every
+// reader of the FP32 state that can run before the first step calls it.
+int clean_identity(dpt_ctx *c) {
+    if (c->w0_dirty) {
+        DPT_TRY(launch_fill_zero(c->W32[0], (size_t)(c->ld * c->ld) * 4, c->stream));
+        c->w0_dirty = false;
+    }
+    return DPT_OK;
+}
+
 // Leave the reduced-precision phase.  DPT_BF16_X3 sweeps read the split form
 // of the current state, made here from its FP32 copy.
 int enter_fp32(dpt_ctx *c) {
+    int rc = clean_identity(c);
+    if (rc != DPT_OK) return rc;
     c->phase = PH_FP32;
     if (c->opt.precision == DPT_BF16_X3) DPT_TRY(launch_split_x3(c->W32[c->cur], c->ld, c->Wx3[c->cur], c->stream));
     return DPT_OK;
@@ -429,7 +442,9 @@ int enter_fp32(dpt_ctx *c) {
 
 // Switch the state to the FP64 phase (upcast the FP32 state).
 int enter_fp64(dpt_ctx *c) {
-    int rc = ensure_f64(c);
+    int rc = clean_identity(c);
+    if (rc != DPT_OK) return rc;
+    rc = ensure_f64(c);
     if (rc != DPT_OK) return rc;
     if (c->phase != PH_FP64) {
         DPT_TRY(launch_cvt_f32_to_f64(c->W64[c->cur], c->W32[c->cur], c->ld * c->ld, c->stream));
@@ -487,6 +502,7 @@ int dense_step(dpt_ctx *c) {
         pf.end(s);
         DPT_TRY(e);
     }
+    if (nx == 0 && c->phase != PH_FP64) c->w0_dirty = false;  // the step wrote all of W32[0]
     c->cur = nx;
     c->at_identity = false;
     c->k += 1;
@@ -553,6 +569,8 @@ int small_batch_size(dpt_ctx *c, const Controller &ctl, int64_t consumed) {
 
 int small_batch(dpt_ctx *c, Controller &ctl, dpt_result *r, int64_t consumed, int *taken,
                 Controller::Action *act) {
+    int rc0 = clean_identity(c);
+    if (rc0 != DPT_OK) return rc0;
     const int m = small_batch_size(c, ctl, consumed);
     const bool f64 = c->phase == PH_FP64;
     const size_t l2 = (size_t)(c->ld * c->ld), esz = f64 ? 8 : 4;
@@ -682,14 +700,17 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
             DPT_TRY(dalloc(&c->dT32, nn));
             DPT_TRY(launch_transpose_f32(c->dT32, c->d32, ld, s));
         }
-        // W32[0] is the state at the identity (W = 0) and is read by readouts
-        // before any step; W32[1] and the BF16 shadows are written in full by
-        // the first iterate (or a warm start) before anything reads them,
-        // except in the FP8 form, which quantises both states here.
+        // W32[0] is the state at the identity (W = 0); nothing but a readout
+        // at the identity reads it before a step overwrites it, so it is
+        // cleared on first such use (clean_identity; a solve never needs it).
+        // W32[1] and the BF16 shadows are written in full by the first iterate
+        // (or a warm start) before anything reads them, except in the FP8
+        // form, which quantises both states here.
         for (int i = 0; i < 2; ++i) {
             DPT_TRY(dalloc(&c->W32[i], nn));
-            if (i == 0 || prec == DPT_FP8_FP32) DPT_TRY(launch_fill_zero(c->W32[i], nn * 4, s));
+            if (prec == DPT_FP8_FP32) DPT_TRY(launch_fill_zero(c->W32[i], nn * 4, s));
         }
+        c->w0_dirty = prec != DPT_FP8_FP32;
         if (prec == DPT_BF16_FP32 || prec == DPT_BF16_X3) {
             if (!c->db16) {
                 DPT_TRY(dalloc(&c->db16, nn));
@@ -721,6 +742,7 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
                 DPT_TRY(launch_cvt_f32_to_bf16(c->Wb[0], c->W32[0], (int64_t)nn, s));
             if (prec == DPT_FP8_FP32) DPT_TRY(launch_quant_fp8(c->W32[0], ld, c->Wq8[0], c->Ws8[0], s));
             c->at_identity = false;
+            c->w0_dirty = false;
         }
     }
     if (z0_dev.p) DPT_TRY(hipStreamSynchronize(s));  // the temporary is freed on return
@@ -729,6 +751,8 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
 
 // E = theta + lambda d from the current state, into c->evec.
 int compute_eigenvalues(dpt_ctx *c) {
+    int rc = clean_identity(c);
+    if (rc != DPT_OK) return rc;
     if (c->sp) return map_err(sparse_eigenvalues(c->sp, c->lambda, c->theta, c->evec, c->stream));
     const StepArgs a = step_args(c, nullptr);
     if (c->phase == PH_FP64) {
@@ -940,6 +964,10 @@ int dpt_eigenvectors(dpt_handle h, void *Z, int dtype, int mem) {
     if (!h || !Z || (mem != DPT_MEM_HOST && mem != DPT_MEM_DEVICE)) return DPT_EINVAL;
     if (dtype != DPT_DTYPE_F32 && dtype != DPT_DTYPE_F64) return DPT_EINVAL;
     if (mem == DPT_MEM_DEVICE && !is_device_ptr(Z)) return DPT_EINVAL;
+    if (!h->sp) {
+        int rc = clean_identity(h);
+        if (rc != DPT_OK) return rc;
+    }
     const size_t bytes = (size_t)(h->n * h->n) * (dtype == DPT_DTYPE_F64 ? 8 : 4);
     void *dst = Z;
     void *tmp = nullptr;
