@@ -122,11 +122,13 @@ bool is_device_ptr(const void *p) {
 
 // Inputs declared DPT_MEM_DEVICE must really be device memory (a host pointer
 // would be dereferenced by a kernel).
+// A warm start must live in the problem's memory kind: a device z0 declared
+// with a host problem would otherwise be read by a host-to-device copy.
 bool device_inputs_ok(const dpt_problem *p, const void *z0) {
+    if (z0 && is_device_ptr(z0) != (p->mem == DPT_MEM_DEVICE)) return false;
     if (p->mem != DPT_MEM_DEVICE) return true;
     if (!is_device_ptr(p->theta) || !is_device_ptr(p->delta)) return false;
     if (p->format == DPT_CSR && (!is_device_ptr(p->indptr) || !is_device_ptr(p->indices))) return false;
-    if (z0 && !is_device_ptr(z0)) return false;
     return true;
 }
 
@@ -433,8 +435,12 @@ int clean_identity(dpt_ctx *c) {
 // Leave the reduced-precision phase.  DPT_BF16_X3 sweeps read the split form
 // of the current state, made here from its FP32 copy.
 int enter_fp32(dpt_ctx *c) {
-    int rc = clean_identity(c);
-    if (rc != DPT_OK) return rc;
+    // only the identity state (cur == 0) can still be uncleared; after the first
+    // iterate W32[0] is overwritten by the next step before anything reads it
+    if (c->cur == 0) {
+        int rc = clean_identity(c);
+        if (rc != DPT_OK) return rc;
+    }
     c->phase = PH_FP32;
     if (c->opt.precision == DPT_BF16_X3) DPT_TRY(launch_split_x3(c->W32[c->cur], c->ld, c->Wx3[c->cur], c->stream));
     return DPT_OK;
@@ -442,7 +448,7 @@ int enter_fp32(dpt_ctx *c) {
 
 // Switch the state to the FP64 phase (upcast the FP32 state).
 int enter_fp64(dpt_ctx *c) {
-    int rc = clean_identity(c);
+    int rc = c->cur == 0 ? clean_identity(c) : DPT_OK;
     if (rc != DPT_OK) return rc;
     rc = ensure_f64(c);
     if (rc != DPT_OK) return rc;

@@ -15,8 +15,8 @@
 //    through the whole ld x ld array.
 //  * Dominant mode (Sec. II.H): the single-line map F_{n*} of eq.
 //    (single_line_dyn) on one vector, z' = e + lambda g * (Delta z - (Delta z)[n*] z),
-//    one SpMV (or GEMV) per iteration; every block recomputes the scalar
-//    (Delta z)[n*] from row n* so that one launch performs one iteration.
+//    one SpMV (or GEMV) per iteration, preceded by a one-wave kernel that
+//    forms the scalar (Delta z)[n*] from row n* once.
 #include <float.h>
 
 #include <algorithm>
@@ -52,6 +52,9 @@ struct Panel {
     // offset of element (l, n) of the ld x ld state
     __host__ __device__ static int64_t at(int64_t l, int64_t n, int64_t ld) { return (n / P) * (ld * P) + l * P + n % P; }
 };
+// Persistent grid of the dominant-mode SpMV: 8 blocks of 256 threads per CU.
+constexpr int64_t kDomGrid = 256 * 8;
+
 inline unsigned int blocks_for(int64_t items, int per_block, int64_t cap = 1 << 20) {
     int64_t b = (items + per_block - 1) / per_block;
     return (unsigned int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
@@ -314,20 +317,17 @@ __global__ void k_csr_row_dot(const int64_t *rowptr, const int *col, const T *va
     if (threadIdx.x == 0) *s_out = s;
 }
 
-// One iteration of F_{nstar}: 8 lanes per row, 32 rows per block pass
-// (grid-stride over groups of 32 rows).
+// One iteration of F_{nstar}: 8 lanes per row, 32 rows per block pass; a
+// persistent grid (a few blocks per CU) strides over groups of 32 rows.
+// s = (Delta z)[nstar] comes from k_csr_row_dot, launched before it on the
+// same stream, so each iteration computes s once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_dom_csr(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
                                                  const T *__restrict__ val, int64_t n, int64_t nstar, double lambda,
-                                                 const double *__restrict__ theta, const T *__restrict__ z,
-                                                 T *__restrict__ zn, unsigned long long *stat) {
-    __shared__ double s_sh;
-    if (threadIdx.x < 64) {
-        const double s = csr_row_dot_wave(rowptr, col, val, nstar, z);
-        if (threadIdx.x == 0) s_sh = s;
-    }
-    __syncthreads();
-    const T s = (T)s_sh;
+                                                 const double *__restrict__ theta, const double *__restrict__ s_in,
+                                                 const T *__restrict__ z, T *__restrict__ zn,
+                                                 unsigned long long *stat) {
+    const T s = (T)(*s_in);
     const int sub = threadIdx.x & 7;
     double dmax = 0.0, wmax = 0.0;
     bool bad = false;
@@ -573,6 +573,21 @@ bool host_csr_ok(const int64_t *ip, const int *col, int64_t n, int64_t nnz) {
     return true;
 }
 
+// Structural check of a device CSR (same rules as the host check) with the
+// caller's one-word device flag; synchronises the stream.  Returns DPT_OK,
+// DPT_EINVAL or a device error code.
+int validate_device_csr(const dpt_problem *p, unsigned int *flag, hipStream_t s) {
+    unsigned int hflag = 0;
+    hipLaunchKernelGGL((k_zero<unsigned int>), dim3(1), dim3(64), 0, s, flag, (int64_t)1);
+    hipLaunchKernelGGL(k_csr_validate, dim3(blocks_for(p->n, 32)), dim3(256), 0, s, p->indptr, p->indices, p->n,
+                       p->nnz, flag);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return err_code(e);
+    return hflag ? DPT_EINVAL : DPT_OK;
+}
+
 // Returns DPT_OK, DPT_EINVAL (bad structure) or a device error code; on
 // failure nothing stays allocated.
 template <typename T>
@@ -597,18 +612,13 @@ int stage_csr(const dpt_problem *p, DevCsr<T> *c, hipStream_t s) {
     } else {
         c->rowptr = p->indptr;
         c->col = p->indices;
-        unsigned int *flag = nullptr, hflag = 0;
+        unsigned int *flag = nullptr;
         e = hipMalloc((void **)&flag, sizeof(unsigned int));
         if (e == hipSuccess) {
-            hipLaunchKernelGGL((k_zero<unsigned int>), dim3(1), dim3(64), 0, s, flag, (int64_t)1);
-            hipLaunchKernelGGL(k_csr_validate, dim3(blocks_for(n, 32)), dim3(256), 0, s, p->indptr, p->indices, n,
-                               nnz, flag);
-            e = hipGetLastError();
-            if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            const int rc = validate_device_csr(p, flag, s);
             (void)hipFree(flag);
+            if (rc != DPT_OK) return rc;
         }
-        if (e == hipSuccess && hflag) return DPT_EINVAL;
         if (e == hipSuccess && vals64 == (sizeof(T) == 8)) {
             c->val = (const T *)p->delta;  // borrowed
             return DPT_OK;
@@ -834,6 +844,112 @@ hipError_t sparse_residuals(SparseState *sp, double lambda, const double *theta,
 // ========================================================== dominant mode
 namespace {
 
+// Device buffers of one dominant-mode solve: the iterate and its successor,
+// the scalar (Delta z)[n*], and the per-iteration statistics (2 u64 per
+// iteration, iterations 0 .. cap-1).
+template <typename T>
+struct DomBuffers {
+    T *z[2] = {nullptr, nullptr};
+    double *s = nullptr;
+    unsigned long long *stats = nullptr;
+};
+
+struct DomOutcome {
+    int status = DPT_NOT_CONVERGED, iters = 0;
+    double last = std::numeric_limits<double>::quiet_NaN();
+};
+
+// The iteration of F_nstar from e_nstar and the readout, on device buffers the
+// caller provides (allocates nothing).  `val` holds the CSR values, or the
+// n x n row-major matrix when rowptr is NULL.  The eigenvector goes to the
+// device array dst (dtype out64 ? double : float); *eigval gets
+// theta_star + lambda (Delta z)[nstar] of the returned iterate.
+template <typename T>
+hipError_t dominant_iterate(const dpt_problem *p, const dpt_options *o, const int64_t *rowptr, const int *col,
+                            const T *val, const double *theta, double theta_star, int64_t nstar,
+                            const DomBuffers<T> &b, int cap, void *dst, bool out64, double *eigval,
+                            DomOutcome *out, dpt_result *r, hipStream_t s) {
+    const int64_t n = p->n;
+    const bool csr = rowptr != nullptr;
+    unsigned long long hs[2] = {0ull, 0ull};
+    hipLaunchKernelGGL((k_zero<unsigned long long>), dim3(blocks_for(2 * (int64_t)cap, 256)), dim3(256), 0, s,
+                       b.stats, (int64_t)2 * cap);
+    hipLaunchKernelGGL((k_zero<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, b.z[0], n);
+    hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, s, sizeof(T) == 4 ? (float *)b.z[0] : nullptr,
+                       sizeof(T) == 8 ? (double *)b.z[0] : nullptr, nstar);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int cur = 0;
+    while (out->iters < o->max_iter) {
+        unsigned long long *st = b.stats + 2 * out->iters;
+        if (out->iters == 0) {  // z = e_nstar: closed form
+            if (csr)
+                hipLaunchKernelGGL((k_dom_first<T, true>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, rowptr,
+                                   col, val, n, nstar, p->lambda, theta, b.z[cur ^ 1], st);
+            else
+                hipLaunchKernelGGL((k_dom_first<T, false>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
+                                   (const int64_t *)nullptr, (const int *)nullptr, val, n, nstar, p->lambda, theta,
+                                   b.z[cur ^ 1], st);
+        } else if (csr) {
+            hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, rowptr, col, val, nstar,
+                               (const T *)b.z[cur], b.s);
+            hipLaunchKernelGGL((k_dom_csr<T>), dim3(blocks_for(n, 32, kDomGrid)), dim3(256), 0, s, rowptr, col, val,
+                               n, nstar, p->lambda, theta, (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
+        } else {
+            hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, val, n, nstar, (const T *)b.z[cur],
+                               b.s);
+            hipLaunchKernelGGL((k_dom_dense<T>), dim3(blocks_for(n, 4)), dim3(256), 0, s, val, n, nstar, p->lambda,
+                               theta, (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
+        }
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(hs, st, 16, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+        out->iters += 1;
+        const double dl = bits_to_double(hs[0]), wm = bits_to_double(hs[1]);
+        out->last = dl;
+        if (r && r->delta_history && out->iters - 1 < r->history_cap) r->delta_history[out->iters - 1] = dl;
+        if (!std::isfinite(dl) || !(wm <= o->blowup)) {
+            out->status = DPT_DIVERGED;
+            break;
+        }
+        if (dl < o->tol) {
+            out->status = DPT_OK;
+            break;
+        }
+    }
+    // eigenvalue readout from the returned iterate
+    if (csr)
+        hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, rowptr, col, val, nstar, (const T *)b.z[cur],
+                           b.s);
+    else
+        hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, val, n, nstar, (const T *)b.z[cur], b.s);
+    double sv = 0.0;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&sv, b.s, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    *eigval = theta_star + p->lambda * sv;
+    if (out64)
+        hipLaunchKernelGGL((k_convert<T, double>), dim3(blocks_for(n, 256)), dim3(256), 0, s, (const T *)b.z[cur],
+                           (double *)dst, n);
+    else
+        hipLaunchKernelGGL((k_convert<T, float>), dim3(blocks_for(n, 256)), dim3(256), 0, s, (const T *)b.z[cur],
+                           (float *)dst, n);
+    return hipGetLastError();
+}
+
+void fill_dom_result(dpt_result *r, const DomOutcome &out, bool fp64) {
+    if (!r) return;
+    r->status = out.status;
+    r->iters = out.iters;
+    r->iters_bf16 = 0;
+    r->iters_fp32 = fp64 ? 0 : out.iters;
+    r->iters_fp64 = fp64 ? out.iters : 0;
+    r->last_delta = out.last;
+}
+
 template <typename T>
 int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_host, double theta_star,
                int64_t nstar, double *eigval, void *eigvec, dpt_result *r) {
@@ -842,15 +958,12 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
     int rc = DPT_OK;
     DevCsr<T> csr;
     T *val = nullptr, *dense = nullptr;
-    T *z[2] = {nullptr, nullptr};
+    DomBuffers<T> b;
     const double *theta = nullptr;
-    double *theta_own = nullptr, *s_dev = nullptr;
-    unsigned long long *stats = nullptr;
+    double *theta_own = nullptr;
     void *out_tmp = nullptr;
     const int cap = std::max(1, o->max_iter);
-    std::vector<unsigned long long> hs(2);
-    int status = DPT_NOT_CONVERGED, iters = 0;
-    double last = std::numeric_limits<double>::quiet_NaN();
+    DomOutcome out;
     auto run = [&]() -> hipError_t {
         hipError_t e;
         if (p->format == DPT_CSR) {
@@ -884,9 +997,9 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
                 if (e != hipSuccess) return e;
             }
         }
-        e = hipMalloc((void **)&s_dev, sizeof(double));
-        if (e == hipSuccess) e = hipMalloc((void **)&stats, sizeof(unsigned long long) * 2 * (cap + 1));
-        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc((void **)&z[i], sizeof(T) * n);
+        e = hipMalloc((void **)&b.s, sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void **)&b.stats, sizeof(unsigned long long) * 2 * cap);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc((void **)&b.z[i], sizeof(T) * n);
         if (e != hipSuccess) return e;
         if (theta_host) {  // host inputs: upload theta; device inputs: borrow it
             e = hipMalloc((void **)&theta_own, sizeof(double) * n);
@@ -897,67 +1010,6 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
         } else {
             theta = p->theta;
         }
-        hipLaunchKernelGGL((k_zero<unsigned long long>), dim3(blocks_for(2 * (cap + 1), 256)), dim3(256), 0, s, stats,
-                           (int64_t)2 * (cap + 1));
-        hipLaunchKernelGGL((k_zero<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, z[0], n);
-        hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, s, sizeof(T) == 4 ? (float *)z[0] : nullptr,
-                           sizeof(T) == 8 ? (double *)z[0] : nullptr, nstar);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        int cur = 0;
-        while (iters < o->max_iter) {
-            unsigned long long *st = stats + 2 * iters;
-            if (iters == 0) {  // z = e_nstar: closed form
-                if (p->format == DPT_CSR)
-                    hipLaunchKernelGGL((k_dom_first<T, true>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
-                                       csr.rowptr, csr.col, csr.val, n, nstar, p->lambda, (const double *)theta,
-                                       z[cur ^ 1], st);
-                else
-                    hipLaunchKernelGGL((k_dom_first<T, false>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
-                                       (const int64_t *)nullptr, (const int *)nullptr, (const T *)dense, n, nstar,
-                                       p->lambda, (const double *)theta, z[cur ^ 1], st);
-            } else if (p->format == DPT_CSR) {
-                hipLaunchKernelGGL((k_dom_csr<T>), dim3(blocks_for(n, 32)), dim3(256), 0, s, csr.rowptr, csr.col,
-                                   csr.val, n, nstar, p->lambda, (const double *)theta, (const T *)z[cur],
-                                   z[cur ^ 1], st);
-            } else {
-                hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, (const T *)dense, n, nstar,
-                                   (const T *)z[cur], s_dev);
-                hipLaunchKernelGGL((k_dom_dense<T>), dim3(blocks_for(n, 4)), dim3(256), 0, s, (const T *)dense, n,
-                                   nstar, p->lambda, (const double *)theta, (const double *)s_dev, (const T *)z[cur],
-                                   z[cur ^ 1], st);
-            }
-            e = hipGetLastError();
-            if (e == hipSuccess) e = hipMemcpyAsync(hs.data(), st, 16, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return e;
-            cur ^= 1;
-            ++iters;
-            const double dl = bits_to_double(hs[0]), wm = bits_to_double(hs[1]);
-            last = dl;
-            if (r && r->delta_history && iters - 1 < r->history_cap) r->delta_history[iters - 1] = dl;
-            if (!std::isfinite(dl) || !(wm <= o->blowup)) {
-                status = DPT_DIVERGED;
-                break;
-            }
-            if (dl < o->tol) {
-                status = DPT_OK;
-                break;
-            }
-        }
-        // eigenvalue readout from the returned iterate
-        if (p->format == DPT_CSR)
-            hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, csr.rowptr, csr.col, csr.val, nstar,
-                               (const T *)z[cur], s_dev);
-        else
-            hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, (const T *)dense, n, nstar,
-                               (const T *)z[cur], s_dev);
-        double sv = 0.0;
-        e = hipGetLastError();
-        if (e == hipSuccess) e = hipMemcpyAsync(&sv, s_dev, sizeof(double), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return e;
-        *eigval = theta_star + p->lambda * sv;
         // eigenvector in the problem's dtype and memory kind
         const bool out64 = p->dtype == DPT_DTYPE_F64;
         const size_t ob = (size_t)n * (out64 ? 8 : 4);
@@ -967,13 +1019,10 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
             if (e != hipSuccess) return e;
             dst = out_tmp;
         }
-        if (out64)
-            hipLaunchKernelGGL((k_convert<T, double>), dim3(blocks_for(n, 256)), dim3(256), 0, s, (const T *)z[cur],
-                               (double *)dst, n);
-        else
-            hipLaunchKernelGGL((k_convert<T, float>), dim3(blocks_for(n, 256)), dim3(256), 0, s, (const T *)z[cur],
-                               (float *)dst, n);
-        e = hipGetLastError();
+        const bool is_csr = p->format == DPT_CSR;
+        e = dominant_iterate<T>(p, o, is_csr ? csr.rowptr : nullptr, is_csr ? csr.col : nullptr,
+                                is_csr ? csr.val : (const T *)dense, theta, theta_star, nstar, b, cap, dst, out64,
+                                eigval, &out, r, s);
         if (e == hipSuccess && out_tmp) e = hipMemcpyAsync(eigvec, out_tmp, ob, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         return e;
@@ -983,22 +1032,34 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
     csr.release();
     if (val) (void)hipFree(val);
     for (int i = 0; i < 2; ++i)
-        if (z[i]) (void)hipFree(z[i]);
+        if (b.z[i]) (void)hipFree(b.z[i]);
     if (theta_own) (void)hipFree(theta_own);
-    if (s_dev) (void)hipFree(s_dev);
-    if (stats) (void)hipFree(stats);
+    if (b.s) (void)hipFree(b.s);
+    if (b.stats) (void)hipFree(b.stats);
     if (out_tmp) (void)hipFree(out_tmp);
     if (rc != DPT_OK) return rc;
     if (e != hipSuccess) return err_code(e);
-    if (r) {
-        r->status = status;
-        r->iters = iters;
-        r->iters_bf16 = 0;
-        r->iters_fp32 = sizeof(T) == 4 ? iters : 0;
-        r->iters_fp64 = sizeof(T) == 8 ? iters : 0;
-        r->last_delta = last;
-    }
-    return status;
+    fill_dom_result(r, out, sizeof(T) == 8);
+    return out.status;
+}
+
+// Device-side theta checks into the caller's ThetaScan (allocates nothing).
+int theta_check_into(const double *theta, int64_t n, int64_t *index, double *theta_index, ThetaScan *sc,
+                     hipStream_t s) {
+    ThetaScan h{};
+    const unsigned int g = blocks_for(n, 256, 1024);
+    hipLaunchKernelGGL(k_theta_scan_init, dim3(1), dim3(64), 0, s, sc, n, *index);
+    hipLaunchKernelGGL(k_theta_max, dim3(g), dim3(256), 0, s, theta, n, sc);
+    hipLaunchKernelGGL(k_theta_argmax, dim3(g), dim3(256), 0, s, theta, n, sc, *index);
+    hipLaunchKernelGGL(k_theta_count, dim3(g), dim3(256), 0, s, theta, n, sc);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, sc, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return err_code(e);
+    if (h.bad || h.index >= (unsigned long long)n || h.count != 1) return DPT_EINVAL;
+    *index = (int64_t)h.index;
+    *theta_index = bits_to_double(h.value_bits);
+    return DPT_OK;
 }
 
 }  // namespace
@@ -1011,23 +1072,11 @@ int dominant_solve(const dpt_problem *p, const dpt_options *o, const double *the
 
 int dominant_theta_check_device(const double *theta, int64_t n, int64_t *index, double *theta_index, hipStream_t s) {
     ThetaScan *sc = nullptr;
-    ThetaScan h{};
     hipError_t e = hipMalloc((void **)&sc, sizeof(ThetaScan));
     if (e != hipSuccess) return err_code(e);
-    const unsigned int g = blocks_for(n, 256, 1024);
-    hipLaunchKernelGGL(k_theta_scan_init, dim3(1), dim3(64), 0, s, sc, n, *index);
-    hipLaunchKernelGGL(k_theta_max, dim3(g), dim3(256), 0, s, theta, n, sc);
-    hipLaunchKernelGGL(k_theta_argmax, dim3(g), dim3(256), 0, s, theta, n, sc, *index);
-    hipLaunchKernelGGL(k_theta_count, dim3(g), dim3(256), 0, s, theta, n, sc);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, sc, sizeof(h), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const int rc = theta_check_into(theta, n, index, theta_index, sc, s);
     (void)hipFree(sc);
-    if (e != hipSuccess) return err_code(e);
-    if (h.bad || h.index >= (unsigned long long)n || h.count != 1) return DPT_EINVAL;
-    *index = (int64_t)h.index;
-    *theta_index = bits_to_double(h.value_bits);
-    return DPT_OK;
+    return rc;
 }
 
 }  // namespace dpt

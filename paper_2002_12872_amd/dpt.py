@@ -284,7 +284,9 @@ def dpt_init(problem: ProblemSpec, opts: Options = None, z0=None) -> Handle:
     zp = None
     keep = None
     if z0 is not None:
-        zp, _, _, keep = _info(z0)
+        zp, _, zdev, keep = _info(z0)
+        if zdev != problem.device:
+            raise ValueError("z0 must live in the same memory kind as the problem's arrays")
     rc = load_library().dpt_init(ctypes.byref(h), ctypes.byref(problem.struct),
                                  ctypes.byref(opts) if opts is not None else None, zp)
     del keep

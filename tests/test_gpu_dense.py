@@ -236,6 +236,27 @@ def test_warm_start_refines_approximate_eigenvectors():
     assert rel_eig_error(e, ref["e"], theta) <= 1e-11
 
 
+def test_warm_start_must_match_the_problem_memory_kind():
+    """A device z0 given with a host problem (and a host z0 with a device
+    problem) is rejected by the library itself, not dereferenced."""
+    import ctypes
+    import torch
+    n = 64
+    theta, delta = small_problem(n, 12)
+    z_host = np.eye(n)
+    z_dev = torch.eye(n, dtype=torch.float64, device="cuda")
+    lib = dpt.load_library()
+    o = dpt.options(precision=dpt.DPT_FP64)
+    for spec, z0 in ((dpt.ProblemSpec(theta, delta, 1.0, stream=0), z_dev.data_ptr()),
+                     (dpt.ProblemSpec(torch.from_numpy(theta).cuda(), torch.from_numpy(delta).cuda(), 1.0),
+                      z_host.ctypes.data)):
+        h = ctypes.c_void_p()
+        rc = lib.dpt_init(ctypes.byref(h), ctypes.byref(spec.struct), ctypes.byref(o), z0)
+        assert rc == dpt.DPT_EINVAL and not h.value
+    with pytest.raises(ValueError):
+        dpt.dpt_init(dpt.ProblemSpec(theta, delta, 1.0, stream=0), o, z_dev)
+
+
 def test_device_inputs_are_borrowed_and_match_host_inputs():
     import torch
     n = 1024

@@ -52,6 +52,37 @@ def test_c4_dense_symmetric_16384_bf16_then_fp32():
     assert abs(e_all.sum() - theta.sum()) <= 1e-5 * np.abs(theta).sum() / n
 
 
+@pytest.mark.parametrize("precision", ["bf16_fp32", "bf16_x3"])
+def test_c4_estimate_rule_as_benchmarked(precision):
+    """The benchmark's timed solve: N = 16384 BF16 -> FP32 (and the split-BF16
+    sweep form beside it) to tol 1e-6 under the a-posteriori contraction rule,
+    device-resident inputs, large-tile kernels.  Errors against the converged
+    FP64 oracle on 64 rows: eigenvalues, eigenvectors and residual <= 1e-5, the
+    residual also element by element against the oracle's own residual of the
+    same exported rows."""
+    n = 16384
+    theta, delta = workloads.dense_sym_large(0, n=n)
+    spec = dpt.ProblemSpec(device(theta), device(delta), 1.0)
+    prec = dpt.DPT_BF16_FP32 if precision == "bf16_fp32" else dpt.DPT_BF16_X3
+    h = dpt.dpt_init(spec, dpt.options(tol=1e-6, max_iter=100, precision=prec,
+                                       stop_rule=dpt.DPT_STOP_ESTIMATE))
+    res = dpt.dpt_solve(h)
+    assert res["status"] == dpt.DPT_OK and res["iters_bf16"] >= 2 and res["iters_fp32"] >= 1, res
+    e = dpt.dpt_eigenvalues(h)
+    rows = workloads.sample_rows(n, 64)
+    d64 = delta.astype(np.float64)
+    ref = oracle.iterate(theta, d64, 1.0, rows=rows, max_iter=40, tol=1e-14)
+    assert ref["status"] == oracle.OR_OK
+    assert rel_eig_error(e[rows], ref["e"], theta) <= 1e-5
+    z = rows_of_state(h, n, rows)
+    assert np.max(np.abs(z - ref["z"])) / np.max(np.abs(ref["z"] - np.eye(n)[rows])) <= 1e-5
+    r = dpt.dpt_residuals(h, rows)
+    norm_ub = np.abs(theta).max() + float(np.linalg.norm(d64))
+    assert np.max(r / (norm_ub * np.linalg.norm(z, axis=1))) <= 1e-5
+    r_or, mz, zn = oracle.residual(theta, d64, 1.0, z, e[rows])
+    assert np.all(np.abs(r - r_or) <= 1e-10 * r_or + 1e-12 * np.sqrt(n) * (mz + np.abs(e[rows]) * zn))
+
+
 def test_c2_dense_unsymmetric_4096_thirty_fp32_steps():
     n = 4096
     theta, delta = workloads.dense_unsym(0, n=n)

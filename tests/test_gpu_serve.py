@@ -18,6 +18,11 @@ pytestmark = pytest.mark.gpu
 dpt = pytest.importorskip("paper_2002_12872_amd.dpt")
 
 OPTS = dict(tol=1e-5, max_iter=100, precision=2)
+# Parity against the oracle uses a tighter per-request tolerance: with tol 1e-5 on
+# delta the iteration itself stops up to ~1.5e-5 of max|Z* - I| away from the fixed
+# point (FP64 oracle, same stopping rule), so the relative eigenvector bar of 1e-5
+# is checked on requests iterated to delta < 1e-6.
+OPTS_ACC = dict(tol=1e-6, max_iter=100, precision=2)
 
 
 def request(n, symmetric, seed):
@@ -38,8 +43,8 @@ def test_results_are_batch_invariant_and_match_oracle():
     probs = [request(*m) for m in MIX]
     srv = dpt.dpt_serve_open(4 << 30, max_slots=64)
     target = 5
-    alone = run_all(srv, [probs[target]])[0]
-    mixed = run_all(srv, probs)
+    alone = run_all(srv, [probs[target]], opts=OPTS_ACC)[0]
+    mixed = run_all(srv, probs, opts=OPTS_ACC)
     dpt.dpt_serve_close(srv)
     assert alone["status"] == dpt.DPT_OK
     assert np.array_equal(alone["E"], mixed[target]["E"])
@@ -50,7 +55,7 @@ def test_results_are_batch_invariant_and_match_oracle():
         assert res["iters_bf16"] >= 1 and res["iters_fp32"] >= 1
         ref = oracle.iterate(th, de.astype(np.float64), 1.0, max_iter=200, tol=1e-14)
         assert rel_eig_error(res["E"], ref["e"], th) <= 1e-5
-        assert np.max(np.abs(res["Z"] - ref["z"])) <= 1e-5 * max(1.0, np.abs(ref["z"]).max())
+        assert np.max(np.abs(res["Z"] - ref["z"])) <= 1e-5 * np.max(np.abs(ref["z"] - np.eye(len(th))))
 
 
 def test_graph_and_direct_launches_agree():
@@ -176,8 +181,8 @@ def test_large_problems_and_tile_autotuner(autotune):
         assert m in (-1, 256, 512, 1024, 2048)
     if not autotune:
         assert st["tile128_min_ld"] == [1024, 1024]
-    alone = run_all(srv, [probs[0]])[0]
-    mixed = run_all(srv, probs)
+    alone = run_all(srv, [probs[0]], opts=OPTS_ACC)[0]
+    mixed = run_all(srv, probs, opts=OPTS_ACC)
     dpt.dpt_serve_close(srv)
     assert np.array_equal(alone["E"], mixed[0]["E"]) and np.array_equal(alone["Z"], mixed[0]["Z"])
     for (th, de), res in zip(probs, mixed):
@@ -186,4 +191,4 @@ def test_large_problems_and_tile_autotuner(autotune):
         rows = workloads.sample_rows(n, 32)
         ref = oracle.iterate(th, de.astype(np.float64), 1.0, rows=rows, max_iter=200, tol=1e-14)
         assert rel_eig_error(res["E"][rows], ref["e"], th) <= 1e-5
-        assert np.max(np.abs(res["Z"][rows] - ref["z"])) <= 1e-5 * max(1.0, np.abs(ref["z"]).max())
+        assert np.max(np.abs(res["Z"][rows] - ref["z"])) <= 1e-5 * np.max(np.abs(ref["z"] - np.eye(n)[rows]))
