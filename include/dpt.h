@@ -207,6 +207,24 @@ int dpt_residuals(dpt_handle h, int64_t nrows, const int64_t *rows, double *res)
 int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval,
                  void *eigvec, dpt_result *r);
 
+/* Dominant-eigenvector mode that allocates no device memory, for callers that
+ * cannot call hipMalloc (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same iteration, kernels and results as
+ * dpt_dominant (bitwise), with every work buffer (the two iterates, the scalar
+ * (Delta z)[index], per-iteration statistics, the theta and CSR checks) in one
+ * fixed array per GPU of 64 MiB + 68 KiB, held by each GPU the library runs on
+ * until the process ends.  Requirements beyond dpt_dominant's: p->mem ==
+ * DPT_MEM_DEVICE; p->dtype is DPT_DTYPE_F64 for o->precision == DPT_FP64 and
+ * DPT_DTYPE_F32 otherwise (no conversion copy); eigvec is device memory of n
+ * values of that dtype.  Limits: o->max_iter <= 4096 and n <= 8388608 (FP32) or
+ * 4194304 (FP64); beyond them DPT_EINVAL.  Host-side results (eigval, r) as in
+ * dpt_dominant; the call synchronises p->stream.  All calls on one GPU share
+ * that GPU's array and leave their contents in it: calls that overlap on one
+ * GPU (from several host threads or streams) race and must be serialised by
+ * the caller.  Returns the numerical status, DPT_EINVAL or DPT_EDEVICE. */
+int dpt_dominant_noalloc(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval,
+                         void *eigvec, dpt_result *r);
+
 /* ---- kernel timing --------------------------------------------------------
  * Device time of the library's kernels, measured with HIP events recorded on
  * the handle's stream around each launch (accumulated per kernel class).

@@ -1064,6 +1064,23 @@ int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, doub
     return dominant_solve(p, &opt, th, th[index], index, eigval, eigvec, r);
 }
 
+int dpt_dominant_noalloc(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval, void *eigvec,
+                         dpt_result *r) {
+    int rc = validate_args(p, o, false);  // theta and the CSR structure are checked on the device
+    if (rc != DPT_OK) return rc;
+    if (!eigval || !eigvec || index >= p->n || p->mem != DPT_MEM_DEVICE) return DPT_EINVAL;
+    rc = check_device();
+    if (rc != DPT_OK) return rc;
+    if (!device_inputs_ok(p, nullptr) || !is_device_ptr(eigvec)) return DPT_EINVAL;
+    dpt_options opt;
+    if (o) {
+        opt = *o;
+    } else {
+        dpt_options_default(&opt);
+    }
+    return dominant_solve_noalloc(p, &opt, index, eigval, eigvec, r);
+}
+
 int dpt_profile_enable(dpt_handle h, int on) {
     if (!h) return DPT_EINVAL;
     h->prof.reset();

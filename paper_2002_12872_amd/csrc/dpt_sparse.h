@@ -45,6 +45,21 @@ hipError_t sparse_residuals(SparseState *sp, double lambda, const double *theta,
 int dominant_solve(const dpt_problem *p, const dpt_options *o, const double *theta_host, double theta_index,
                    int64_t index, double *eigval, void *eigvec, dpt_result *r);
 
+// Limits of the dominant mode without allocation (dpt_dominant_noalloc): at most
+// kNoallocMaxIter iterations, and two iterates of n values (each rounded up to
+// 256 bytes) within kNoallocVectorBytes, i.e. n <= 8 Mi in FP32, 4 Mi in FP64.
+constexpr int kNoallocMaxIter = 4096;
+constexpr size_t kNoallocVectorBytes = (size_t)64 << 20;
+
+// Dominant mode on device-resident inputs with every work buffer in the
+// library's fixed per-device array (no device allocation).  p->mem must be
+// DPT_MEM_DEVICE, p->dtype the state's dtype, eigvec device memory of that
+// dtype.  Returns the numerical status, DPT_EINVAL (also for sizes beyond the
+// limits above) or DPT_EDEVICE.  Calls on one device share the array: they must
+// not overlap.
+int dominant_solve_noalloc(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval, void *eigvec,
+                           dpt_result *r);
+
 // Checks of a device-resident theta for the dominant mode without copying it to
 // the host: all values finite and theta[*index] occurring once; *index < 0 is
 // replaced by the first index of the largest value.  *theta_index receives the

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <vector>
 
 #include "device_common.h"
@@ -1077,6 +1078,87 @@ int dominant_theta_check_device(const double *theta, int64_t n, int64_t *index, 
     const int rc = theta_check_into(theta, n, index, theta_index, sc, s);
     (void)hipFree(sc);
     return rc;
+}
+
+// ------------------------------------------------- dominant mode, no allocation
+// Work memory of dpt_dominant_noalloc: one fixed array per GPU, for callers that
+// cannot allocate (HIP graph capture, serving loops).  Layout: a 4 KiB header
+// (the scalar s, the theta scan, the CSR check flag), the statistics of up to
+// kNoallocMaxIter iterations, then the two iterates.  Host code must use the
+// device address from hipGetSymbolAddress (per device), never `scratch` itself.
+constexpr size_t kScratchHeader = 4096;
+constexpr size_t kScratchStats = (size_t)2 * kNoallocMaxIter * sizeof(unsigned long long);
+constexpr size_t kScratchBytes = kScratchHeader + kScratchStats + kNoallocVectorBytes;
+static_assert(kScratchStats % 256 == 0, "iterates stay 256-byte aligned");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(unsigned char **out) {
+    static std::mutex mu;
+    static unsigned char *addr[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DPT_EDEVICE;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return DPT_EDEVICE;
+        }
+        addr[dev] = (unsigned char *)ptr;
+    }
+    *out = addr[dev];
+    return DPT_OK;
+}
+
+template <typename T>
+int dominant_noalloc_t(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval, void *eigvec,
+                       dpt_result *r, unsigned char *base) {
+    const int64_t n = p->n;
+    hipStream_t s = (hipStream_t)p->stream;
+    double *s_dev = (double *)base;
+    ThetaScan *scan = (ThetaScan *)(base + 256);
+    unsigned int *flag = (unsigned int *)(base + 512);
+    DomBuffers<T> b;
+    b.s = s_dev;
+    b.stats = (unsigned long long *)(base + kScratchHeader);
+    const size_t zb = ((size_t)n * sizeof(T) + 255) / 256 * 256;
+    b.z[0] = (T *)(base + kScratchHeader + kScratchStats);
+    b.z[1] = (T *)(base + kScratchHeader + kScratchStats + zb);
+    double theta_index = 0.0;
+    int rc = theta_check_into(p->theta, n, &index, &theta_index, scan, s);
+    if (rc != DPT_OK) return rc;
+    const bool csr = p->format == DPT_CSR;
+    if (csr) {
+        rc = validate_device_csr(p, flag, s);
+        if (rc != DPT_OK) return rc;
+    }
+    DomOutcome out;
+    hipError_t e = dominant_iterate<T>(p, o, csr ? p->indptr : nullptr, csr ? p->indices : nullptr,
+                                       (const T *)p->delta, p->theta, theta_index, index, b,
+                                       std::max(1, o->max_iter), eigvec, sizeof(T) == 8, eigval, &out, r, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return err_code(e);
+    fill_dom_result(r, out, sizeof(T) == 8);
+    return out.status;
+}
+
+}  // namespace
+
+int dominant_solve_noalloc(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval, void *eigvec,
+                           dpt_result *r) {
+    const bool fp64 = o->precision == DPT_FP64;
+    const size_t esz = fp64 ? 8 : 4;
+    if (p->dtype != (fp64 ? DPT_DTYPE_F64 : DPT_DTYPE_F32)) return DPT_EINVAL;
+    if (o->max_iter > kNoallocMaxIter) return DPT_EINVAL;
+    if (2 * (((size_t)p->n * esz + 255) / 256 * 256) > kNoallocVectorBytes) return DPT_EINVAL;
+    unsigned char *base = nullptr;
+    const int rc = scratch_address(&base);
+    if (rc != DPT_OK) return rc;
+    return fp64 ? dominant_noalloc_t<double>(p, o, index, eigval, eigvec, r, base)
+                : dominant_noalloc_t<float>(p, o, index, eigval, eigvec, r, base);
 }
 
 }  // namespace dpt

@@ -117,6 +117,9 @@ _FUNCS = {
     "dpt_dominant": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
                                     ctypes.POINTER(Result)]),
+    "dpt_dominant_noalloc": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                            ctypes.POINTER(Result)]),
     "dpt_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "dpt_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Profile)]),
     "dpt_serve_open": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ServeConfig)]),
@@ -371,6 +374,26 @@ def dpt_dominant(problem: ProblemSpec, opts: Options = None, index: int = -1, ou
                                      int(index), ctypes.byref(ev), p, ctypes.byref(r))
     if rc < 0:
         raise DptError(rc, "dpt_dominant")
+    return ev.value, out, {"status": r.status, "iters": r.iters, "last_delta": r.last_delta,
+                           "history": hist[:min(r.iters, history_cap)].copy()}
+
+
+def dpt_dominant_noalloc(problem: ProblemSpec, opts: Options, out, index: int = -1, history_cap: int = 64):
+    """Dominant mode without device allocation: device-resident problem, ``out`` a
+    device tensor of n values of the problem's dtype.  Returns (eigval, out, result dict)."""
+    st = problem.struct
+    p, _, dev, keep = _info(out)
+    if not dev or not problem.device:
+        raise ValueError("dpt_dominant_noalloc takes device-resident inputs and output")
+    ev = ctypes.c_double()
+    hist = np.full(max(history_cap, 1), np.nan)
+    r = Result()
+    r.delta_history = hist.ctypes.data
+    r.history_cap = history_cap
+    rc = load_library().dpt_dominant_noalloc(ctypes.byref(st), ctypes.byref(opts) if opts is not None else None,
+                                             int(index), ctypes.byref(ev), p, ctypes.byref(r))
+    if rc < 0:
+        raise DptError(rc, "dpt_dominant_noalloc")
     return ev.value, out, {"status": r.status, "iters": r.iters, "last_delta": r.last_delta,
                            "history": hist[:min(r.iters, history_cap)].copy()}
 
