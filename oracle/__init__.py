@@ -12,6 +12,9 @@ Contents
 ``jacobi_eigh``    hand-written cyclic Jacobi eigensolver (textbook method), a pin for
                    symmetric N <= 64.
 ``rs_coefficients`` Rayleigh-Schroedinger recursion eq. (ARS-alpha) / Supplement B.
+``homotopy``       Sec. III: Q stages of lambda/Q, each diagonalised by D-PT in the
+                   eigenbasis of the previous stage.
+``ramp``           Supplement E: the non-autonomous coupling lambda (1 - alpha^k).
 """
 from .core import (  # noqa: F401
     OR_OK,
@@ -25,5 +28,6 @@ from .core import (  # noqa: F401
     max_threads,
     residual,
 )
+from .homotopy import homotopy, ramp  # noqa: F401
 from .jacobi import jacobi_eigh  # noqa: F401
 from .rs import rs_coefficients, rs_partial_sum, rs_eigenvalue_coefficients  # noqa: F401

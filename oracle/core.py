@@ -56,8 +56,9 @@ class OracleLib:
         lib.or_iterate.restype = ctypes.c_int
         lib.or_iterate.argtypes = [
             ctypes.POINTER(_Problem), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
-            ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+            ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+            ctypes.c_void_p,
         ]
         lib.or_max_threads.restype = ctypes.c_int
         self.lib = lib
@@ -67,8 +68,13 @@ class OracleLib:
         return int(self.lib.or_max_threads())
 
     def iterate(self, theta, delta, lam, rows=None, z0=None, max_iter=200, tol=1e-12,
-                fixed_steps=False, blowup=1e6, nthreads=0):
+                fixed_steps=False, blowup=1e6, nthreads=0, ramp_alpha=0.0, per_row=False):
         """Run the D-PT iteration on the eigenvector rows ``rows`` (default: all).
+
+        ``ramp_alpha`` in (0, 1) selects the non-autonomous coupling of
+        Supplement E, lambda_k = lambda (1 - ramp_alpha^k) (see dpt_oracle.c).
+        ``per_row`` stops each row on its own delta (frozen rows keep their
+        iterate); the result then has ``row_iters``, the step each row froze on.
 
         ``delta`` is a dense (n, n) array, Delta[m, l], or a CSR triple
         ``(indptr, indices, values)``.  Returns a dict with
@@ -107,15 +113,17 @@ class OracleLib:
         e = np.zeros(nrows, dtype=np.float64)
         hist = np.full(max(max_iter, 1), np.nan, dtype=np.float64)
         iters = ctypes.c_int(0)
+        row_iters = np.zeros(nrows, dtype=np.int32)
         rc = self.lib.or_iterate(ctypes.byref(prob), nrows, _ptr(rows), _ptr(z0), int(max_iter),
                                  float(tol), int(bool(fixed_steps)), float(blowup), int(nthreads),
-                                 _ptr(z), _ptr(e), _ptr(hist), ctypes.byref(iters))
+                                 float(ramp_alpha), int(bool(per_row)), _ptr(z), _ptr(e), _ptr(hist),
+                                 ctypes.byref(iters), _ptr(row_iters))
         del keep
         if rc < 0:
             raise ValueError("oracle rejected the problem (code %d)" % rc)
         k = iters.value
         return {"z": z, "e": e, "hist": hist[:k].copy(), "iters": k, "status": rc,
-                "rows": rows}
+                "rows": rows, "row_iters": row_iters}
 
 
 def _default():

@@ -74,9 +74,9 @@ static double delta_row_dot(const or_problem *p, int64_t m, const double *z)
     return s;
 }
 
-/* One application of F_n (eq. single_line_dyn) to z, result in znew.
- * c is scratch of length n holding Delta z. */
-static void apply_single_line_map(const or_problem *p, int64_t nidx, const double *z,
+/* One application of F_n (eq. single_line_dyn) with coupling lam to z, result
+ * in znew.  c is scratch of length n holding Delta z. */
+static void apply_single_line_map(const or_problem *p, int64_t nidx, double lam, const double *z,
                                   double *znew, double *c)
 {
     const int64_t n = p->n;
@@ -86,7 +86,7 @@ static void apply_single_line_map(const or_problem *p, int64_t nidx, const doubl
         if (m == nidx) {
             znew[m] = 1.0;
         } else {
-            znew[m] = p->lambda * (c[m] - cn * z[m]) / (p->theta[nidx] - p->theta[m]);
+            znew[m] = lam * (c[m] - cn * z[m]) / (p->theta[nidx] - p->theta[m]);
         }
     }
 }
@@ -156,6 +156,20 @@ static int validate(const or_problem *p, int64_t nrows, const int64_t *rows)
  *   tol       : stop when delta_k < tol (ignored in fixed mode).
  *   blowup    : DIVERGED threshold on max |z - e_n|.
  *   nthreads  : OpenMP threads (<= 0: library default).
+ *   ramp_alpha: 0 for the autonomous map; in (0, 1) the non-autonomous scheme
+ *               of Supplement E: the k-th application (k = 1, 2, ...) uses
+ *               lambda_k = lambda (1 - a_k) with a_k = ramp_alpha^k formed by
+ *               repeated multiplication, as long as a_k >= 2^-53, and lambda
+ *               itself afterwards; the tol test is skipped while the ramp runs
+ *               (the eigenvalue readout always uses lambda).
+ *   per_row   : 0: the rows stop together (delta_k over all rows < tol).
+ *               1: each row stops on its own (Sec. II.B: row n evolves under F_n
+ *               alone): row r is frozen after the first step whose
+ *               delta_k(r) = max_m |z^(k)[m] - z^(k-1)[m]| is below tol; the
+ *               iteration ends when every row is frozen (OK) or at the cap.
+ *               delta_hist records the maximum over the rows still running.
+ *   row_iters : nrows entries (may be NULL): the step on which each row was
+ *               frozen (per_row), 0 for a row still running at the end.
  * Outputs (all caller-owned):
  *   z         : nrows*n, final iterate rows
  *   e         : nrows, E_n = theta_n + lambda (Delta z_n)[n] of the final iterate
@@ -165,9 +179,12 @@ static int validate(const or_problem *p, int64_t nrows, const int64_t *rows)
  */
 int or_iterate(const or_problem *p, int64_t nrows, const int64_t *rows, const double *z0,
                int max_iter, double tol, int fixed_steps, double blowup, int nthreads,
-               double *z, double *e, double *delta_hist, int *iters)
+               double ramp_alpha, int per_row, double *z, double *e, double *delta_hist, int *iters,
+               int *row_iters)
 {
     if (nrows < 1 || !rows || !z || !e || !iters || max_iter < 0) return OR_EINVAL;
+    if (per_row && fixed_steps) return OR_EINVAL;
+    if (!(ramp_alpha >= 0.0 && ramp_alpha < 1.0)) return OR_EINVAL;
     int rc = validate(p, nrows, rows);
     if (rc != OR_OK) return rc;
     if (!fixed_steps && !(tol > 0.0)) return OR_EINVAL;
@@ -187,9 +204,11 @@ int or_iterate(const or_problem *p, int64_t nrows, const int64_t *rows, const do
 #endif
     double *znew = (double *)malloc(sizeof(double) * (size_t)(nrows * n));
     double *scratch = (double *)malloc(sizeof(double) * (size_t)n * (size_t)nth);
-    if (!znew || !scratch) {
+    int *frozen_at = (int *)calloc((size_t)nrows, sizeof(int)); /* 0: running */
+    if (!znew || !scratch || !frozen_at) {
         free(znew);
         free(scratch);
+        free(frozen_at);
         return OR_ENOMEM;
     }
 
@@ -205,39 +224,61 @@ int or_iterate(const or_problem *p, int64_t nrows, const int64_t *rows, const do
 
     int status = fixed_steps ? OR_OK : OR_NOT_CONVERGED;
     int k = 0;
+    double ak = 1.0; /* ramp_alpha^k */
     while (k < max_iter) {
+        double lam = p->lambda;
+        int ramping = 0;
+        if (ramp_alpha > 0.0) {
+            ak *= ramp_alpha;
+            if (ak >= 0x1p-53) {
+                lam = p->lambda * (1.0 - ak);
+                ramping = 1;
+            }
+        }
         double dk = 0.0, wmax = 0.0;
-        int nonfinite = 0;
-#pragma omp parallel for schedule(static) num_threads(nth) reduction(max : dk, wmax) reduction(| : nonfinite)
+        int nonfinite = 0, running = 0;
+#pragma omp parallel for schedule(static) num_threads(nth) reduction(max : dk, wmax) reduction(| : nonfinite) \
+    reduction(+ : running)
         for (int64_t r = 0; r < nrows; ++r) {
+            if (frozen_at[r]) continue;
             int t = 0;
 #ifdef _OPENMP
             t = omp_get_thread_num();
 #endif
             double *c = scratch + (size_t)t * (size_t)n;
-            const double *zr = z + r * n;
+            double *zr = z + r * n;
             double *zn = znew + r * n;
-            apply_single_line_map(p, rows[r], zr, zn, c);
+            apply_single_line_map(p, rows[r], lam, zr, zn, c);
+            double dr = 0.0;
             for (int64_t m = 0; m < n; ++m) {
                 if (!isfinite(zn[m])) nonfinite = 1;
                 double ch = fabs(zn[m] - zr[m]);
-                if (ch > dk) dk = ch;
+                if (ch > dr) dr = ch;
                 double off = fabs(zn[m] - (m == rows[r] ? 1.0 : 0.0));
                 if (off > wmax) wmax = off;
             }
+            if (dr > dk) dk = dr;
+            memcpy(zr, zn, sizeof(double) * (size_t)n);
+            if (per_row && !ramping && dr < tol) {
+                frozen_at[r] = k + 1;
+            } else {
+                running += 1;
+            }
         }
-        memcpy(z, znew, sizeof(double) * (size_t)(nrows * n));
         if (delta_hist) delta_hist[k] = nonfinite ? NAN : dk;
         ++k;
         if (nonfinite || !(wmax <= blowup)) {
             status = OR_DIVERGED;
             break;
         }
-        if (!fixed_steps && dk < tol) {
+        if (!fixed_steps && !ramping && (per_row ? running == 0 : dk < tol)) {
             status = OR_OK;
             break;
         }
     }
+    if (row_iters)
+        for (int64_t r = 0; r < nrows; ++r) row_iters[r] = frozen_at[r];
+    free(frozen_at);
     free(scratch);
     free(znew);
     *iters = k;
