@@ -55,8 +55,12 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--stop-rule", choices=["estimate", "delta"], default="estimate",
                     help="stopping rule of the timed solves (both precision forms)")
-    ap.add_argument("--kernel-precision", choices=["bf16", "fp32"], default="bf16",
+    ap.add_argument("--kernel-precision", choices=["bf16", "fp32", "fp64"], default="bf16",
                     help="precision of the --kernel-only steps")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="profiling mode: CSR product steps of the N = 32768 sparse workload only")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="profiling mode: the serving engine on the first --serve-requests trace requests, burst")
     ap.add_argument("--fp32-solves", type=int, default=2)
     ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle work")
@@ -245,6 +249,12 @@ def secondary_bench(args):
         "frac_hbm_peak": round(step_bytes / (sms * 1e-3) / 1e9 / PEAK_HBM_GBS, 3),
         "l2_gather_gbs": round(gather / (sms * 1e-3) / 1e9, 1),
         "algorithmic_bytes_per_step": step_bytes}
+    # gather roof: random 512-byte runs from one panel of the same size (16 MiB),
+    # as many as the product gathers per step
+    p_ms, p_gbs = dpt.dpt_probe_gather(n, nnz * (n // 128), 5)
+    out["sparse_sym_n32768_spmm_fp32"].update({
+        "gather_roof_gbs": round(p_gbs, 1), "gather_roof_ms": round(p_ms, 3),
+        "frac_gather_roof": round((gather / (sms * 1e-3) / 1e9) / p_gbs, 3)})
     dpt.dpt_destroy(h)
     o = dpt.options(tol=1e-6, max_iter=50, precision=dpt.DPT_FP32)
     for _ in range(3):
@@ -320,6 +330,185 @@ def paper_scale_dominant():
             "paper": "4 iterations, 3 s (Mathematica on a desktop CPU, 1e8 nnz; Sec. II.H)"}
 
 
+def next_rows_bench():
+    """Per-row retirement, homotopy continuation, Rayleigh-Schroedinger comparator
+    and the coupling ramp, one line each (device-resident inputs)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2002_12872_amd import dpt
+    out = {}
+
+    def dev(x):
+        return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+    # per-row retirement on the delta-potential (Sec. II.F): the lowest level
+    # converges last, most rows freeze after 6-7 steps
+    n = 8192
+    th, de = workloads.delta_potential(n)
+    spec = dpt.ProblemSpec(dev(th), dev(de), 1.0)
+    line = {"workload": "delta-potential N=%d (theta_n = 2n + 1/2, Delta = phi phi^T), lambda = 1, FP64, "
+                        "tol 1e-12" % n}
+    for name, rule in (("delta_rule", dpt.DPT_STOP_DELTA), ("per_row", dpt.DPT_STOP_ROW)):
+        o = dpt.options(tol=1e-12, max_iter=200, precision=dpt.DPT_FP64, stop_rule=rule)
+        dpt.dpt_destroy(dpt.dpt_init(spec, o))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        h = dpt.dpt_init(spec, o)
+        r = dpt.dpt_solve(h, history_cap=0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        at, rows_mult = dpt.dpt_row_status(h)
+        line[name] = {"ms_per_solve": round(1e3 * el, 2), "iters": r["iters"], "status": r["status"]}
+        if rule == dpt.DPT_STOP_ROW:
+            full = n * (r["iters"] - 1)
+            line[name]["rows_multiplied"] = int(rows_mult)
+            line[name]["products_saved"] = round(1.0 - rows_mult / full, 3)
+            line[name]["rows_frozen_by_step"] = {int(k): int(v) for k, v in
+                                                 zip(*np.unique(at, return_counts=True))}
+        dpt.dpt_destroy(h)
+    line["speedup"] = round(line["delta_rule"]["ms_per_solve"] / line["per_row"]["ms_per_solve"], 3)
+    out["per_row_retirement"] = line
+    del spec
+    # homotopy: the delta-potential beyond the plain iteration's radius (about 2.9)
+    n = 2048
+    th, de = workloads.delta_potential(n)
+    spec = dpt.ProblemSpec(dev(th), dev(de), 4.0)
+    o = dpt.options(tol=1e-12, max_iter=500, precision=dpt.DPT_FP64)
+    plain = dpt.dpt_solve(dpt.dpt_init(spec, o), history_cap=0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    e, z, r = dpt.dpt_homotopy(spec, o, 2)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    w = np.linalg.eigvalsh(np.diag(th) + 4.0 * de)
+    out["homotopy"] = {"workload": "delta-potential N=%d, lambda = 4, 2 stages, FP64 tol 1e-12" % n,
+                       "plain_status": plain["status"], "status": r["status"], "iters": r["iters"],
+                       "ms": round(1e3 * el, 2),
+                       "max_rel_eigenvalue_error_vs_eigvalsh": float(np.max(np.abs(e.cpu().numpy() - w) /
+                                                                            np.abs(w)))}
+    del spec, z
+    # Rayleigh-Schroedinger comparator (Sec. II.F): orders vs D-PT iterations
+    th, de = workloads.delta_potential(100)
+    rs = {}
+    for lam in (1.5, 2.5):
+        exact = np.linalg.eigvalsh(np.diag(th) + lam * de)
+        eps, _, _ = dpt.dpt_rs_series(dpt.ProblemSpec(th, de, lam, stream=0), 120, want_z=False)
+        partial = th[None, :] + np.cumsum((lam ** np.arange(1, 121))[:, None] * eps, axis=0)
+        err_rs = np.max(np.abs(partial - exact) / np.abs(exact), axis=1)
+        h = dpt.dpt_init(dpt.ProblemSpec(th, de, lam, stream=0), dpt.options(precision=dpt.DPT_FP64))
+        err_d = []
+        for _ in range(400):
+            dpt.dpt_step(h, 1)
+            err_d.append(float(np.max(np.abs(dpt.dpt_eigenvalues(h) - exact) / np.abs(exact))))
+            if err_d[-1] < 1e-12:
+                break
+        hit = lambda errs: int(np.argmax(np.asarray(errs) < 1e-8)) + 1 if min(errs) < 1e-8 else None
+        rs["lambda_%g" % lam] = {"rs_orders_to_1e-8": hit(err_rs), "dpt_iterations_to_1e-8": hit(err_d),
+                                 "rs_error_at_order_120": float(err_rs[-1]), "dpt_error_final": err_d[-1]}
+    n = 4096
+    th, de = small_problem_sym(n)
+    spec = dpt.ProblemSpec(dev(th), dev(de), 0.5)
+    dpt.dpt_rs_series(spec, 2, want_z=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    dpt.dpt_rs_series(spec, 10, want_z=False)
+    torch.cuda.synchronize()
+    rs["n4096_fp64_ms_per_order"] = round(1e3 * (time.perf_counter() - t) / 10, 3)
+    rs["workload"] = "delta-potential N=100 (Sec. II.F); timing: dense symmetric N=4096, 10 orders"
+    out["rs_comparator"] = rs
+    # coupling ramp (Supplement E) on the 4x4 example whose plain iteration diverges
+    th4 = np.arange(4.0)
+    de4 = np.array([[0.0, 0.4, -0.25, 1.15], [0.4, 0.0, 0.9, -1.05], [-0.25, 0.9, 0.0, 0.4],
+                    [1.15, -1.05, 0.4, 0.0]])
+    sp4 = dpt.ProblemSpec(th4, de4, 0.75, stream=0)
+    r_plain = dpt.dpt_solve(dpt.dpt_init(sp4, dpt.options(tol=1e-13, max_iter=3000, precision=dpt.DPT_FP64)))
+    t = time.perf_counter()
+    h = dpt.dpt_init(sp4, dpt.options(tol=1e-13, max_iter=3000, precision=dpt.DPT_FP64, ramp_alpha=0.9))
+    r_ramp = dpt.dpt_solve(h, history_cap=0)
+    el = time.perf_counter() - t
+    w = np.linalg.eigvalsh(np.diag(th4) + 0.75 * de4)
+    out["ramp"] = {"workload": "4x4, theta = (0,1,2,3), lambda = 0.75, alpha = 0.9, FP64 tol 1e-13",
+                   "plain_status": r_plain["status"], "status": r_ramp["status"], "iters": r_ramp["iters"],
+                   "ms": round(1e3 * el, 2),
+                   "max_abs_eigenvalue_error": float(np.max(np.abs(dpt.dpt_eigenvalues(h) - w)))}
+    return out
+
+
+def small_problem_sym(n, seed=0):
+    """Dense symmetric test matrix: theta_i = i + U(0, 0.5) sorted, Delta = (R + R^T)/2,
+    R off-diagonal iid N(0, (0.5/sqrt n)^2)."""
+    import numpy as np
+    rng = np.random.default_rng(77_000 + seed)
+    theta = np.sort(np.arange(n, dtype=np.float64) + rng.uniform(0, 0.5, n))
+    r = rng.normal(0, 0.5 / np.sqrt(n), (n, n))
+    np.fill_diagonal(r, 0.0)
+    return theta, 0.5 * (r + r.T)
+
+
+def host_info():
+    """CPU of the machine the baseline runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def cpu_baselines(threads):
+    """The FP64 oracle on the other configurations (host cores, and one core):
+    full solves where they fit a few seconds (N = 64), per-row samples scaled by
+    N / rows otherwise (rows evolve independently, so a sample's time per row is
+    the full solve's), and the serving mix on its first requests."""
+    import numpy as np
+
+    import oracle
+    import workloads
+    out = {"host": host_info(), "threads": threads}
+    th, de = workloads.dense_sym_small(0)
+    t = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        r = oracle.iterate(th, de, 1.0, max_iter=200, tol=1e-12)
+    out["dense_sym_n64_fp64_full_solve"] = {"us_per_solve": round(1e6 * (time.perf_counter() - t) / reps, 1),
+                                            "iters": r["iters"]}
+    n = 4096
+    th, de = workloads.dense_unsym(0, n=n)
+    rows = workloads.sample_rows(n, 32)
+    t = time.perf_counter()
+    oracle.iterate(th, de.astype(np.float64), 1.0, rows=rows, max_iter=30, fixed_steps=True)
+    el = time.perf_counter() - t
+    out["dense_unsym_n4096_30_steps"] = {"iter_s": round(30 * len(rows) / n / el, 4),
+                                         "sample": "%d of %d rows, 30 FP64 steps in %.2f s, scaled by rows/N"
+                                                   % (len(rows), n, el)}
+    trace = workloads.serving_trace(0, count=4096, rate=None)
+    count = 32
+    t = time.perf_counter()
+    for req in trace[:count]:
+        th, de = workloads.request_matrices(req)
+        oracle.iterate(th, de.astype(np.float64), 1.0, max_iter=100, tol=1e-5)
+    el = time.perf_counter() - t
+    out["serving_mix_full_solves"] = {"solves_per_s": round(count / el, 3),
+                                      "sample": "first %d of 4096 trace requests, full FP64 solves to tol 1e-5 "
+                                                "in %.2f s" % (count, el)}
+    n = 16384
+    th, de = workloads.dense_sym_large(0, n=n)
+    rows = workloads.sample_rows(n, 64)[:4]
+    t = time.perf_counter()
+    r = oracle.iterate(th, de.astype(np.float64), 1.0, rows=rows, max_iter=40, tol=1e-14, nthreads=1)
+    el = time.perf_counter() - t
+    out["one_core_dense_sym_n16384"] = {"iter_s": round(r["iters"] * len(rows) / n / el, 7), "cores": 1,
+                                        "sample": "%d rows, %d FP64 iterations in %.2f s on one thread, scaled "
+                                                  "by rows/N" % (len(rows), r["iters"], el)}
+    return out
+
+
 def kernel_only(args):
     """Fused product steps of one precision at size n only (for counter
     collection with rocprofv3): BF16 steps of the BF16 -> FP32 form, or FP32 steps."""
@@ -329,7 +518,7 @@ def kernel_only(args):
     from paper_2002_12872_amd import dpt
     theta, delta = workloads.dense_sym_large(0, n=args.n)
     spec = dpt.ProblemSpec(torch.from_numpy(theta).cuda(), torch.from_numpy(delta).cuda(), 1.0)
-    prec = dpt.DPT_BF16_FP32 if args.kernel_precision == "bf16" else dpt.DPT_FP32
+    prec = {"bf16": dpt.DPT_BF16_FP32, "fp32": dpt.DPT_FP32, "fp64": dpt.DPT_FP64}[args.kernel_precision]
     h = dpt.dpt_init(spec, dpt.options(precision=prec))
     dpt.dpt_step(h, 1 + args.warmup)            # first iterate (no product) + warm-up steps
     dpt.dpt_profile_enable(h, True)
@@ -338,6 +527,47 @@ def kernel_only(args):
     print(json.dumps({"mode": "kernel-only", "precision": args.kernel_precision, "n": args.n,
                       "steps": args.steps, "last_delta": last,
                       "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items()}}), flush=True)
+
+
+def spmm_only(args):
+    """CSR product steps of the sparse workload (N = 32768, ~1.05e6 non-zeros,
+    FP32) after 4 warm-up steps (the state is dense by then)."""
+    import torch
+
+    import workloads
+    from paper_2002_12872_amd import dpt
+    n = 32768
+    th, ip, ix, v = workloads.sparse_sym(0, n=n)
+    spec = dpt.ProblemSpec(torch.from_numpy(th).cuda(), (torch.from_numpy(ip).cuda(), torch.from_numpy(ix).cuda(),
+                                                          torch.from_numpy(v).cuda()), 1.0)
+    h = dpt.dpt_init(spec, dpt.options(precision=dpt.DPT_FP32))
+    dpt.dpt_step(h, 4)
+    dpt.dpt_profile_enable(h, True)
+    last = dpt.dpt_step(h, args.steps)
+    prof = dpt.dpt_profile_read(h)
+    print(json.dumps({"mode": "spmm-only", "n": n, "nnz": int(v.shape[0]), "steps": args.steps,
+                      "last_delta": last, "kernel_ms": {k: x[0] / max(x[1], 1) for k, x in prof.items()}}),
+          flush=True)
+
+
+def serve_only(args):
+    """The serving engine on the first --serve-requests requests of the trace,
+    all submitted at once (BF16 -> FP32, tol 1e-5)."""
+    import workloads
+    from paper_2002_12872_amd import dpt
+    trace = workloads.serving_trace(0, count=4096, rate=None)[:args.serve_requests]
+    specs = [dpt.ProblemSpec(th, de, 1.0, stream=0) for th, de in (workloads.request_matrices(r) for r in trace)]
+    o = dpt.options(tol=1e-5, max_iter=100, precision=dpt.DPT_BF16_FP32)
+    srv = dpt.dpt_serve_open(int(args.serve_budget_gib * (1 << 30)), max_slots=1024, use_graph=True, autotune=True)
+    t = time.perf_counter()
+    tickets = [dpt.dpt_serve_submit(srv, sp, o) for sp in specs]
+    res = [dpt.dpt_serve_poll(srv, x, wait_ms=-1) for x in tickets]
+    el = time.perf_counter() - t
+    st = dpt.dpt_serve_stats_read(srv)
+    dpt.dpt_serve_close(srv)
+    print(json.dumps({"mode": "serve-only", "requests": len(specs), "solves_per_s": round(len(specs) / el, 2),
+                      "converged": sum(r["status"] == dpt.DPT_OK for r in res), "steps": st["steps"]}),
+          flush=True)
 
 
 def copy_probe(args):
@@ -454,6 +684,10 @@ def main():
         return kernel_only(args)
     if args.copy_probe:
         return copy_probe(args)
+    if args.spmm_only:
+        return spmm_only(args)
+    if args.serve_only:
+        return serve_only(args)
     if args.secondary_only:
         print(json.dumps({"mode": "secondary-only", "secondary": secondary_bench(args)}), flush=True)
         return
@@ -493,6 +727,12 @@ def main():
     dominant = max((k for k in KERNELS if by_kernel[k]), key=lambda k: prof[k][0])
     roofline = dict(by_kernel[dominant])
     roofline["share_of_solve_gpu_time"] = round(prof[dominant][0] / sum(v[0] for v in prof.values()), 3)
+    # the BF16 step, which runs most of the iterations, beside it: fraction of the
+    # BF16 matrix-core peak against the 0.6 target
+    if by_kernel.get("gemm_bf16"):
+        roofline["bf16_step_frac"] = by_kernel["gemm_bf16"]["frac"]
+        roofline["bf16_step_target_frac"] = 0.6
+        roofline["bf16_step_ms"] = by_kernel["gemm_bf16"]["avg_launch_ms"]
 
     # ---- plain FP32 solves, same tolerance and stopping rule
     fp32 = None
@@ -589,12 +829,22 @@ def main():
                                "sample": "%d of %d eigenvector rows (rows evolve independently), %d FP64 "
                                          "iterations to max|dz| < 1e-14 in %.1f s, scaled by rows/N"
                                          % (len(rows), n, k, cpu_t)}
+        print("# CPU oracle on the other configurations", file=sys.stderr, flush=True)
+        out["cpu_baseline"]["other_configs"] = cpu_baselines(threads)
         z_scale = float(np.max(np.abs(ref["z"] - np.eye(n)[rows])))
         err = {"reference": "FP64 oracle, %d rows, %d iterations" % (len(rows), k),
                "bf16_fp32": accuracy(dpt, handles[-1], e_mixed, theta, ref, rows, z_scale)}
         res = dpt.dpt_residuals(handles[-1], rows)
         norm_ub = np.abs(theta).max() + np.sqrt(np.sum(d64 ** 2))
-        err["bf16_fp32"]["residual_rel"] = float(np.max(res / norm_ub))
+        zr = dpt.dpt_eigenvectors(handles[-1])[rows] if n <= 4096 else None
+        if zr is None:
+            zt = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            dpt.dpt_eigenvectors(handles[-1], zt)
+            zr = zt[torch.as_tensor(rows, device="cuda")].double().cpu().numpy()
+            del zt
+        # ||M z - E z||_2 / (||M||_ub ||z||_2), ||M||_ub = max|theta| + |lambda| ||Delta||_F
+        err["bf16_fp32"]["residual_rel"] = float(np.max(res / (norm_ub * np.linalg.norm(zr, axis=1))))
+        err["bf16_fp32"]["residual_norm"] = "||Mz - Ez||_2 / ((max|theta| + |lambda| ||Delta||_F) ||z||_2)"
         if f_handles:
             err["fp32"] = accuracy(dpt, f_handles[-1], e_fp32, theta, ref, rows, z_scale)
         err["fp8_fp32"] = accuracy(dpt, hs8[-1], e_fp8, theta, ref, rows, z_scale)
@@ -609,6 +859,8 @@ def main():
     if not args.skip_secondary:
         print("# secondary configurations", file=sys.stderr, flush=True)
         out["secondary"] = secondary_bench(args)
+        print("# per-row retirement, homotopy, RS comparator, ramp", file=sys.stderr, flush=True)
+        out["next_rows"] = next_rows_bench()
     print(json.dumps(out), flush=True)
 
 

@@ -111,6 +111,10 @@ typedef struct dpt_options {
     double fp64_final_tol;  /* > 0: after FP32 convergence run FP64 sweeps to this; 0 off */
     double stall_ratio;     /* stall when delta_k >= stall_ratio * min_{j<k} delta_j ...  */
     double blowup;          /* DIVERGED when max |Z - I| exceeds this (> 0)               */
+    double ramp_alpha;      /* 0: autonomous map.  In (0, 1): coupling ramp of Supplement *
+                             * E, lambda_k = lambda (1 - alpha^k) for the k-th application *
+                             * while alpha^k >= 2^-53 (alpha^k by repeated multiplication), *
+                             * lambda afterwards; stopping tests wait for the ramp's end   */
     int32_t max_iter;       /* >= 0; cap on applications of F over all phases              */
     int32_t precision;      /* DPT_FP64, DPT_FP32, DPT_BF16_FP32, DPT_FP8_FP32, DPT_BF16_X3 */
     int32_t stall_patience; /* ... for this many consecutive checks (>= 1), or delta_k = 0 */
@@ -128,6 +132,15 @@ typedef struct dpt_options {
  * falls back to delta_k < tol. */
 #define DPT_STOP_DELTA 0
 #define DPT_STOP_ESTIMATE 1
+/* DPT_STOP_ROW: per-row retirement (Sec. II.B: row n evolves under its own map
+ * F_n).  In the final phase (FP32 sweeps of DPT_FP32 / DPT_BF16_FP32, the FP64
+ * steps of DPT_FP64) each row is frozen after the first step on which its own
+ * delta_k(n) = max_m |Z_k[n][m] - Z_{k-1}[n][m]| is below tol, and later products
+ * run on the remaining rows only (row list padded to the product tile); the
+ * solve ends with DPT_OK when no row is left.  The phases before the final one
+ * follow the delta rule.  Dense problems with those precisions and
+ * fp64_final_tol = 0 only (DPT_EINVAL otherwise); see dpt_row_status. */
+#define DPT_STOP_ROW 2
 
 typedef struct dpt_result {
     double last_delta;      /* delta_k of the last application of F (NaN if none)          */
@@ -141,7 +154,8 @@ typedef struct dpt_result {
 } dpt_result;
 
 /* Fill *o with defaults: tol 1e-6, max_iter 200, DPT_FP32, fp64_final_tol 0,
- * stall_ratio 0.5, stall_patience 2, check_every 1, blowup 1e6, DPT_STOP_DELTA. */
+ * stall_ratio 0.5, stall_patience 2, check_every 1, blowup 1e6, DPT_STOP_DELTA,
+ * ramp_alpha 0. */
 void dpt_options_default(dpt_options *o);
 
 /* Host-only argument check (no device call): pointer/size/enum sanity and, for
@@ -154,8 +168,10 @@ int dpt_validate(const dpt_problem *p, const dpt_options *o);
  * z0 == NULL starts from A^(0) = I (Sec. II.B); otherwise z0 holds an n*n start
  * in the eigenvector layout above, same dtype and memory kind as the problem
  * (its diagonal is taken as 1: the chart z_k[k] = 1).  This warm start is the
- * paper's refinement of approximate eigenvectors (Sec. II.H, last paragraph);
- * dense problems only (z0 must be NULL for a CSR Delta).  A CSR Delta in device
+ * paper's refinement of approximate eigenvectors (Sec. II.H, last paragraph),
+ * and resumes an interrupted iteration: continuing from the exported iterate of
+ * k steps reproduces the uninterrupted iteration (bitwise in FP32 and FP64
+ * phases, dense and CSR).  A CSR Delta in device
  * memory is structure-checked on the device (same rules as dpt_validate) and
  * borrowed: row pointers and indices always, values when their dtype is the
  * state's (FP64 for DPT_FP64, else FP32).
@@ -177,6 +193,13 @@ int dpt_step(dpt_handle h, int nsteps, double *last_delta);
  * bitwise as with one launch per step.
  * Returns the status (also in r->status when r != NULL) or an error. */
 int dpt_solve(dpt_handle h, dpt_result *r);
+
+/* Per-row retirement record of a handle solved with DPT_STOP_ROW: retired_at
+ * (host, n entries, or NULL) receives for each row the number of applications
+ * of F after which it was frozen (0: still running); *rows_multiplied (or NULL)
+ * the number of rows the products have run on so far, summed over the product
+ * steps (ld per step without retirement; ld = padded order). */
+int dpt_row_status(dpt_handle h, int32_t *retired_at, int64_t *rows_multiplied);
 
 /* E_k = theta_k + lambda (Delta z_k)[k] for all k from the current iterate
  * (FP64 accumulation).  E: n doubles in memory kind `mem`. */
@@ -225,6 +248,48 @@ int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, doub
 int dpt_dominant_noalloc(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval,
                          void *eigvec, dpt_result *r);
 
+/* Homotopy continuation (Sec. III, Discussion): for a coupling outside the
+ * iteration's convergence domain, lambda is split into `stages` equal parts.
+ * Stage q diagonalises D + (q lambda / stages) Delta by a full FP64 D-PT solve
+ * written in the eigenbasis of the previous stage, where the problem is the
+ * diagonal matrix of the previous eigenvalues perturbed by (lambda / stages)
+ * B^-1 Delta B (B: the previous eigenvectors as columns).  The basis and its
+ * inverse are updated with FP64 matrix-core products: symmetric Delta keeps
+ * orthonormal eigenvector rows (B^-1 = B^T); otherwise the left eigenvectors come
+ * from the same iteration on the transposed stage perturbation.  With
+ * stages = 1 this is dpt_solve in FP64.  Dense problems; o->precision must be
+ * DPT_FP64 and every stage uses o's tol, max_iter and stopping rule, with a
+ * stall ratio of at least 0.9 (stages can contract slowly near the rounding
+ * floor) and without the ramp.  Outputs in p->mem memory: E (n eigenvalues, continued from
+ * theta by index) and Z (n*n, z_dtype, eigenvector layout above, Z[k*n+k] = 1).
+ * r->iters sums the D-PT iterations of all stage solves.  Returns the worst
+ * stage status (the continuation stops at the first stage that does not reach
+ * DPT_OK; outputs then hold the last completed stage), DPT_EINVAL, DPT_ENOMEM
+ * or DPT_EDEVICE. */
+int dpt_homotopy(const dpt_problem *p, const dpt_options *o, int32_t stages, double *E, void *Z, int z_dtype,
+                 dpt_result *r);
+
+/* Rayleigh-Schroedinger series, the comparator of Sec. II.D-F (recursion eq.
+ * ARS-alpha, Supplement B), in FP64 on the GPU:
+ *   a^(0) = I,  a^(l) = gap (.) (a^(l-1) Delta' - sum_{s<l} diag(a^(s) Delta') a^(l-1-s)),
+ * one FP64 matrix-core product a^(l-1) Delta' per order.  Outputs: eps (host,
+ * order*n doubles) with eps[(l-1)*n + k] = eps_k^(l) = (a^(l-1) Delta')_kk, the
+ * order-l eigenvalue coefficient (E_RS = theta + sum_l lambda^l eps^(l));
+ * coef_max (host, order doubles or NULL) = max |a^(l)|; Z (or NULL; n*n values
+ * of z_dtype in p->mem memory) = the partial sum sum_{l=0}^{order} lambda^l a^(l)
+ * in the eigenvector layout above.  Dense problems; 1 <= order <= 4096; memory
+ * order+1 coefficient matrices.  Returns DPT_OK, DPT_EINVAL, DPT_ENOMEM or
+ * DPT_EDEVICE. */
+int dpt_rs_series(const dpt_problem *p, int32_t order, double *eps, double *coef_max, void *Z, int z_dtype);
+
+/* Measurement probe, not part of the method: rate of random gathers of 512-byte
+ * rows from a panel of panel_rows rows (the access pattern of the CSR product's
+ * state gathers), `gathers` runs per pass (rounded up to the probe's grid),
+ * averaged over reps passes after one warm-up, on the default stream.
+ * *ms_per_pass and *gbs (gathered bytes / time) receive the result.  Returns
+ * DPT_OK, DPT_EINVAL or DPT_EDEVICE. */
+int dpt_probe_gather(int64_t panel_rows, int64_t gathers, int reps, double *ms_per_pass, double *gbs);
+
 /* ---- kernel timing --------------------------------------------------------
  * Device time of the library's kernels, measured with HIP events recorded on
  * the handle's stream around each launch (accumulated per kernel class).
@@ -271,6 +336,9 @@ typedef struct dpt_serve_config {
     int32_t autotune;       /* 1: time 64x64 against 128x128 fused-step tiles per     *
                              * phase and size at open and keep the faster; 0: 128x128 *
                              * tiles from padded order 1024 up                       */
+    void *stream;           /* hipStream_t for all of the server's device work (the   *
+                             * caller keeps ownership and enqueues nothing on it      *
+                             * while the server is open), or NULL: an own stream      */
 } dpt_serve_config;
 
 /* Seconds since dpt_serve_open on a monotonic clock. */
@@ -287,9 +355,9 @@ typedef struct dpt_serve_stats {
                                             * tiles in the BF16 / FP32 phase; -1: none */
 } dpt_serve_stats;
 
-/* Start a server on the current device (creates its own stream, the device
- * arena of cfg->budget_bytes and a 256 MiB pinned host staging ring for
- * submitted matrices).  Returns DPT_OK, DPT_EINVAL, DPT_ENOMEM (arena or ring
+/* Start a server on the current device (on cfg->stream, or a stream of its own,
+ * with the device arena of cfg->budget_bytes and a 256 MiB pinned host staging
+ * ring for submitted matrices).  Returns DPT_OK, DPT_EINVAL, DPT_ENOMEM (arena or ring
  * allocation) or DPT_EDEVICE. */
 int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg);
 

@@ -116,6 +116,24 @@ struct Controller {
         return CONTINUE;
     }
 
+    // A step of the coupling ramp (Supplement E): the map changes from step to
+    // step, so neither convergence nor stall nor the contraction ratios are
+    // judged; a non-finite or blown-up iterate still ends the solve.
+    Action update_ramping(double dl, double wm) {
+        last = dl;
+        if (!std::isfinite(dl) || !(wm <= o.blowup)) {
+            status = DPT_DIVERGED;
+            return DONE;
+        }
+        return CONTINUE;
+    }
+
+    // Every row met its own stopping test (DPT_STOP_ROW).
+    void finish_ok(double dl) {
+        last = dl;
+        status = DPT_OK;
+    }
+
     void fill(dpt_result *r) const {
         if (!r) return;
         r->status = status;

@@ -65,7 +65,13 @@ bool valid_options(const dpt_options *o) {
     if (!(o->stall_ratio >= 0.0) || !(o->stall_ratio <= 1.0)) return false;
     if (o->stall_patience < 1 || o->check_every < 1) return false;
     if (!(o->blowup > 0.0)) return false;
-    if (o->stop_rule != DPT_STOP_DELTA && o->stop_rule != DPT_STOP_ESTIMATE) return false;
+    if (o->stop_rule != DPT_STOP_DELTA && o->stop_rule != DPT_STOP_ESTIMATE && o->stop_rule != DPT_STOP_ROW)
+        return false;
+    if (o->stop_rule == DPT_STOP_ROW &&
+        ((o->precision != DPT_FP32 && o->precision != DPT_FP64 && o->precision != DPT_BF16_FP32) ||
+         o->fp64_final_tol != 0.0))
+        return false;
+    if (!(o->ramp_alpha >= 0.0) || !(o->ramp_alpha < 1.0)) return false;
     if (o->reserved != 0) return false;
     return true;
 }
@@ -297,6 +303,18 @@ struct dpt_ctx {
     int cur = 0;
     int phase = PH_FP32;
     bool at_identity = true;
+    double ramp_ak = 1.0;       // ramp_alpha^k after k applications of F
+    bool last_ramping = false;  // the last application used a ramped coupling
+
+    // per-row retirement (DPT_STOP_ROW)
+    std::vector<int32_t> retired_at;  // per row: applications of F when frozen, 0 running
+    std::vector<int32_t> active;      // running rows, ascending
+    int32_t *rowmap = nullptr;        // device: running rows padded with -1 to map_rows
+    int32_t *newly = nullptr;         // device: rows frozen by the last step
+    double *rowdelta = nullptr;       // device: per map entry, the row's delta
+    int64_t list_rows = 0;            // entries of rowmap in use
+    int64_t map_rows = 0;             // rows the products run on; 0: all (nothing frozen yet)
+    int64_t rows_multiplied = 0;      // rows the products ran on, summed over product steps
     bool w0_dirty = false;  // W32[0] not yet cleared to the identity state (see clean_identity)
     int64_t k = 0;
 
@@ -307,7 +325,8 @@ struct dpt_ctx {
     ~dpt_ctx() {
         if (sp) sparse_destroy(sp);
         void *own[] = {theta, dvec, evec, stats, db16, W32[0], W32[1], Wb[0], Wb[1], W64[0], W64[1],
-                       dq8, ds8, Wq8[0], Wq8[1], Ws8[0], Ws8[1], small_hist, Dx3, Wx3[0], Wx3[1]};
+                       dq8, ds8, Wq8[0], Wq8[1], Ws8[0], Ws8[1], small_hist, Dx3, Wx3[0], Wx3[1],
+                       rowmap, newly, rowdelta};
         for (void *p : own) dfree(p);
         if (dT32 && dT32 != d32) dfree(dT32);
         if (dT64 && dT64 != d64) dfree(dT64);
@@ -411,15 +430,31 @@ struct DeviceTemp {
     }
 };
 
-StepArgs step_args(dpt_ctx *c, unsigned long long *slot) {
+StepArgs step_args(dpt_ctx *c, unsigned long long *slot, double lambda) {
     StepArgs a;
     a.n = c->n;
     a.ld = c->ld;
-    a.lambda = c->lambda;
+    a.lambda = lambda;
     a.theta = c->theta;
     a.d = c->dvec;
     a.stat = slot;
     return a;
+}
+
+StepArgs step_args(dpt_ctx *c, unsigned long long *slot) { return step_args(c, slot, c->lambda); }
+
+// Coupling of the next application of F (Supplement E's ramp): lambda (1 -
+// alpha^k) for the k-th application while alpha^k >= 2^-53, lambda otherwise.
+double next_lambda(const dpt_ctx *c, bool *ramping) {
+    *ramping = false;
+    if (c->opt.ramp_alpha > 0.0) {
+        const double ak = c->ramp_ak * c->opt.ramp_alpha;
+        if (ak >= 0x1p-53) {
+            *ramping = true;
+            return c->lambda * (1.0 - ak);
+        }
+    }
+    return c->lambda;
 }
 
 // Clear W32[0] to the identity state if it has not been written yet; every
@@ -459,11 +494,21 @@ int enter_fp64(dpt_ctx *c) {
     return DPT_OK;
 }
 
-// One application of F in the current phase; the stats land in ring slot k.
-int dense_step(dpt_ctx *c) {
+// One application of F with coupling lam in the current phase; the stats land
+// in ring slot k.
+int dense_step(dpt_ctx *c, double lam) {
     const int slot = (int)(c->k % kStatRing);
     unsigned long long *st = c->stats + 2 * slot;
-    const StepArgs a = step_args(c, st);
+    StepArgs a = step_args(c, st, lam);
+    if (c->map_rows > 0 && !c->at_identity) {  // frozen rows are left out of the product
+        a.rowmap = c->rowmap;
+        a.rows = c->map_rows;
+    }
+    if (!c->retired_at.empty() && c->active.empty()) {  // every row frozen: nothing changes
+        DPT_TRY(launch_zero_u64(st, 2, c->stream));
+        c->k += 1;
+        return DPT_OK;
+    }
     const int nx = c->cur ^ 1;
     hipStream_t s = c->stream;
     Profiler &pf = c->prof;
@@ -507,6 +552,7 @@ int dense_step(dpt_ctx *c) {
         }
         pf.end(s);
         DPT_TRY(e);
+        c->rows_multiplied += a.rowmap ? a.rows : c->ld;
     }
     if (nx == 0 && c->phase != PH_FP64) c->w0_dirty = false;  // the step wrote all of W32[0]
     c->cur = nx;
@@ -516,7 +562,14 @@ int dense_step(dpt_ctx *c) {
 }
 
 int do_step(dpt_ctx *c) {
-    return c->sp ? sparse_step(c->sp, c->lambda, c->theta, c->stats, &c->k, c->stream, &c->prof) : dense_step(c);
+    bool ramping = false;
+    const double lam = next_lambda(c, &ramping);
+    const int rc = c->sp ? sparse_step(c->sp, lam, c->theta, c->stats, &c->k, c->stream, &c->prof)
+                         : dense_step(c, lam);
+    if (rc != DPT_OK) return rc;
+    c->ramp_ak *= c->opt.ramp_alpha > 0.0 ? c->opt.ramp_alpha : 1.0;
+    c->last_ramping = ramping;
+    return DPT_OK;
 }
 
 // Copy the stats of steps [k0, k1) to the host mirror and synchronise.
@@ -549,8 +602,11 @@ void stat_of(dpt_ctx *c, int64_t step, double *delta, double *wmax) {
 constexpr int kSmallBatch = 16;
 
 bool small_batch_ok(const dpt_ctx *c) {
+    if (c->opt.stop_rule == DPT_STOP_ROW) return false;  // rows are judged one by one after every step
+    bool ramping = false;
+    (void)next_lambda(c, &ramping);  // a batch runs at one coupling: not while the ramp runs
     return !c->sp && c->ld == 64 && (c->phase == PH_FP32 || c->phase == PH_FP64) && c->opt.check_every == 1 &&
-           !c->prof.on;
+           !c->prof.on && !ramping;
 }
 
 // Up to kSmallBatch steps; *taken gets the number the controller consumed and
@@ -755,6 +811,95 @@ int init_dense(dpt_ctx *c, const dpt_problem *p, const void *z0) {
     return DPT_OK;
 }
 
+// Warm start of a CSR problem: z0 (problem's dtype and memory kind) becomes the
+// transposed state; a host z0 is uploaded through a temporary device copy.
+int sparse_warm_start(dpt_ctx *c, const dpt_problem *p, const void *z0) {
+    const size_t bytes = (size_t)(c->n * c->n) * (p->dtype == DPT_DTYPE_F64 ? 8 : 4);
+    DeviceTemp tmp;
+    tmp.s = c->stream;
+    if (p->mem == DPT_MEM_HOST) {
+        DPT_TRY(hipMalloc(&tmp.p, bytes));
+        DPT_TRY(hipMemcpyAsync(tmp.p, z0, bytes, hipMemcpyHostToDevice, c->stream));
+        z0 = tmp.p;
+    }
+    DPT_TRY(sparse_load_state(c->sp, z0, p->dtype == DPT_DTYPE_F64, c->stream));
+    if (tmp.p) DPT_TRY(hipStreamSynchronize(c->stream));
+    return DPT_OK;
+}
+
+// The phase in which DPT_STOP_ROW retires rows.
+bool row_phase(const dpt_ctx *c) {
+    return c->opt.stop_rule == DPT_STOP_ROW && !c->sp &&
+           (c->opt.precision == DPT_FP64 ? c->phase == PH_FP64 : c->phase == PH_FP32);
+}
+
+// Upload the running rows as the product's row list (padded with -1 to the
+// product tile, at most ld entries).
+int upload_rowmap(dpt_ctx *c) {
+    const int64_t tile = row_tile(c->ld);
+    const int64_t cnt = (int64_t)c->active.size();
+    const int64_t rows = std::min<int64_t>(c->ld, (cnt + tile - 1) / tile * tile);
+    std::vector<int32_t> h((size_t)rows, -1);
+    std::copy(c->active.begin(), c->active.end(), h.begin());
+    DPT_TRY(hipMemcpyAsync(c->rowmap, h.data(), sizeof(int32_t) * (size_t)rows, hipMemcpyHostToDevice, c->stream));
+    DPT_TRY(hipStreamSynchronize(c->stream));  // h is freed on return
+    c->list_rows = rows;
+    c->map_rows = (int64_t)c->active.size() < c->n ? rows : 0;  // the full fast kernels until a row freezes
+    return DPT_OK;
+}
+
+// After a step of the retiring phase: freeze the running rows whose own delta is
+// below tol (their value goes to both state buffers), shrink the row list.
+// *left receives the number of rows still running.
+int retire_rows(dpt_ctx *c, int64_t *left) {
+    if (!c->rowmap) {
+        DPT_TRY(dalloc(&c->rowmap, (size_t)c->ld));
+        DPT_TRY(dalloc(&c->newly, (size_t)c->ld));
+        DPT_TRY(dalloc(&c->rowdelta, (size_t)c->ld));
+        c->retired_at.assign((size_t)c->n, 0);
+        c->active.resize((size_t)c->n);
+        for (int64_t i = 0; i < c->n; ++i) c->active[(size_t)i] = (int32_t)i;
+        int rc = upload_rowmap(c);
+        if (rc != DPT_OK) return rc;
+    }
+    const int64_t rows = c->list_rows;
+    const bool f64 = c->phase == PH_FP64;
+    DPT_TRY(f64 ? launch_row_delta_f64(c->W64[c->cur], c->W64[c->cur ^ 1], c->rowmap, rows, c->ld, c->rowdelta,
+                                       c->stream)
+                : launch_row_delta_f32(c->W32[c->cur], c->W32[c->cur ^ 1], c->rowmap, rows, c->ld, c->rowdelta,
+                                       c->stream));
+    std::vector<double> hd((size_t)rows);
+    DPT_TRY(hipMemcpyAsync(hd.data(), c->rowdelta, sizeof(double) * (size_t)rows, hipMemcpyDeviceToHost, c->stream));
+    DPT_TRY(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> keep, frozen;
+    for (size_t i = 0; i < c->active.size(); ++i) {
+        const int32_t r = c->active[i];
+        if (hd[i] < c->opt.tol) {
+            frozen.push_back(r);
+            c->retired_at[(size_t)r] = (int32_t)c->k;
+        } else {
+            keep.push_back(r);
+        }
+    }
+    if (!frozen.empty()) {
+        DPT_TRY(hipMemcpyAsync(c->newly, frozen.data(), sizeof(int32_t) * frozen.size(), hipMemcpyHostToDevice,
+                               c->stream));
+        const int nx = c->cur ^ 1;
+        DPT_TRY(f64 ? launch_copy_rows_f64(c->W64[nx], c->W64[c->cur], c->newly, (int64_t)frozen.size(), c->ld,
+                                           c->stream)
+                    : launch_copy_rows_f32(c->W32[nx], c->W32[c->cur], c->newly, (int64_t)frozen.size(), c->ld,
+                                           c->stream));
+        c->active.swap(keep);
+        if (!c->active.empty()) {
+            int rc = upload_rowmap(c);
+            if (rc != DPT_OK) return rc;
+        }
+        DPT_TRY(hipStreamSynchronize(c->stream));  // `frozen` is freed on return
+    }
+    *left = (int64_t)c->active.size();
+    return DPT_OK;
+}
+
 // E = theta + lambda d from the current state, into c->evec.
 int compute_eigenvalues(dpt_ctx *c) {
     int rc = clean_identity(c);
@@ -787,6 +932,7 @@ void dpt_options_default(dpt_options *o) {
     o->stall_patience = 2;
     o->check_every = 1;
     o->stop_rule = DPT_STOP_DELTA;
+    o->ramp_alpha = 0.0;
     o->reserved = 0;
 }
 
@@ -816,13 +962,13 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
     if (!h) return DPT_EINVAL;
     int rc = dpt_validate(p, o);
     if (rc != DPT_OK) return rc;
-    if (p->format == DPT_CSR && z0) return DPT_EINVAL;  // warm start: dense problems only
     if (o && (o->precision == DPT_FP8_FP32 || o->precision == DPT_BF16_X3) &&
         (p->format != DPT_DENSE || !step_large_supported(pad_order(p->n))))
         return DPT_EINVAL;  // the FP8 and split-BF16 products exist for large dense problems only
     rc = check_device();
     if (rc != DPT_OK) return rc;
     if (!device_inputs_ok(p, z0)) return DPT_EINVAL;
+    if (o && o->stop_rule == DPT_STOP_ROW && p->format != DPT_DENSE) return DPT_EINVAL;  // dense rows only
     dpt_ctx *c = new (std::nothrow) dpt_ctx();
     if (!c) return DPT_ENOMEM;
     auto fail = [&](int code) {
@@ -869,6 +1015,7 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
         rc = sparse_create(&c->sp, p, c->opt.precision == DPT_FP64, c->ld, c->stream);
         if (rc == DPT_OK && !c->sp) rc = DPT_ENOMEM;
         if (rc == DPT_OK) c->phase = c->opt.precision == DPT_FP64 ? PH_FP64 : PH_FP32;
+        if (rc == DPT_OK && z0) rc = sparse_warm_start(c, p, z0);
     } else {
         rc = init_dense(c, p, z0);
     }
@@ -934,6 +1081,20 @@ int dpt_solve(dpt_handle h, dpt_result *r) {
         checked = h->k;
         double dl, wm;
         stat_of(h, h->k - 1, &dl, &wm);
+        if (h->last_ramping) {  // during the ramp only divergence ends the solve
+            if (ctl.update_ramping(dl, wm) == Controller::DONE) done = true;
+            continue;
+        }
+        if (row_phase(h) && std::isfinite(dl)) {  // per-row retirement
+            int64_t left = 0;
+            rc = retire_rows(h, &left);
+            if (rc != DPT_OK) return rc;
+            if (left == 0) {
+                ctl.finish_ok(dl);
+                done = true;
+                continue;
+            }
+        }
         switch (ctl.update(dl, wm)) {
             case Controller::TO_FP32:
                 rc = enter_fp32(h);
@@ -953,6 +1114,18 @@ int dpt_solve(dpt_handle h, dpt_result *r) {
     if (hipStreamSynchronize(h->stream) != hipSuccess) return DPT_EDEVICE;
     ctl.fill(r);
     return ctl.status;
+}
+
+// After a per-row solve, dpt_step keeps applying F to the rows still running
+// only; once every row is frozen a step changes nothing (delta 0).
+int dpt_row_status(dpt_handle h, int32_t *retired_at, int64_t *rows_multiplied) {
+    if (!h) return DPT_EINVAL;
+    if (retired_at) {
+        for (int64_t i = 0; i < h->n; ++i)
+            retired_at[i] = h->retired_at.empty() ? 0 : h->retired_at[(size_t)i];
+    }
+    if (rows_multiplied) *rows_multiplied = h->rows_multiplied;
+    return DPT_OK;
 }
 
 int dpt_eigenvalues(dpt_handle h, double *E, int mem) {

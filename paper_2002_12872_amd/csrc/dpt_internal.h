@@ -36,6 +36,11 @@ struct StepArgs {
     const double *theta;       // ld entries (pad entries arbitrary but finite)
     const double *d;           // ld entries: d_n = (Delta z_n)[n] of the current state
     unsigned long long *stat;  // 2 u64 for this step (zeroed before the step)
+    // Per-row retirement: when rowmap is set, the step covers only the rows
+    // rowmap[0 .. rows) (rows a multiple of the product tile; -1 marks padding
+    // entries, which are neither read as rows nor written).  NULL: all ld rows.
+    const int32_t *rowmap = nullptr;
+    int64_t rows = 0;
 };
 
 // ---- dense kernels (kernels_dense.hip) -----------------------------------
@@ -55,6 +60,22 @@ hipError_t launch_cvt_f32_to_bf16(__bf16 *dst, const float *src, int64_t count, 
 hipError_t launch_cvt_f32_to_f64(double *dst, const float *src, int64_t count, hipStream_t s);
 hipError_t launch_transpose_f32(float *dst, const float *src, int64_t ld, hipStream_t s);
 hipError_t launch_transpose_f64(double *dst, const double *src, int64_t ld, hipStream_t s);
+// Per-row retirement helpers: out[i] = max_m |Wn[r][m] - Wo[r][m]| for the
+// mapped rows r = rowmap[i] (i < rows; padding entries give -1), and a copy of
+// the listed rows from src to dst.
+hipError_t launch_row_delta_f32(const float *Wn, const float *Wo, const int32_t *rowmap, int64_t rows, int64_t ld,
+                                double *out, hipStream_t s);
+hipError_t launch_row_delta_f64(const double *Wn, const double *Wo, const int32_t *rowmap, int64_t rows, int64_t ld,
+                                double *out, hipStream_t s);
+hipError_t launch_copy_rows_f32(float *dst, const float *src, const int32_t *rows, int64_t count, int64_t ld,
+                                hipStream_t s);
+hipError_t launch_copy_rows_f64(double *dst, const double *src, const int32_t *rows, int64_t count, int64_t ld,
+                                hipStream_t s);
+// Tile height of the products when a row map is in use: the row list is
+// padded to a multiple of it (at most ld).
+inline int64_t row_tile(int64_t ld) { return ld % 128 == 0 ? 128 : 64; }
+// C[i][j] = sum_k A[i][k] B[j][k] for ld x ld FP64 operands (ld a multiple of 64).
+hipError_t launch_gemm_nt_f64(const double *A, const double *B, double *C, int64_t ld, hipStream_t s);
 // *flag |= 1 when src != src^T anywhere (bitwise).  flag must be zeroed first.
 // Exact symmetry test of the padded ld x ld matrix (sets *flag on a difference);
 // when bf is not null the same pass writes bf16(src) into bf (ld x ld).

@@ -35,6 +35,10 @@ hipError_t sparse_eigenvalues(SparseState *sp, double lambda, const double *thet
 // out[i * n + j] = Z[i][j] (eigenvector i), float or double, device memory.
 hipError_t sparse_export(SparseState *sp, int64_t n, void *out, int out_f64, hipStream_t s);
 
+// Warm start: make z0 (device, n*n in the eigenvector layout of dpt.h, float or
+// double) the current iterate; its diagonal is taken as 1.
+hipError_t sparse_load_state(SparseState *sp, const void *z0, int z0_f64, hipStream_t s);
+
 // ||M z_j - E_j z_j||_2 for the host-given rows; res on the host.
 hipError_t sparse_residuals(SparseState *sp, double lambda, const double *theta, const double *evec,
                             const int64_t *rows, int64_t nrows, double *res, hipStream_t s);

@@ -234,7 +234,8 @@ __device__ __forceinline__ void load4(const double *p, double out[4]) {
 // over the whole padded row with 4-wide loads.
 // d_n = Delta[n][n] + sum_k W[n][k] Delta[n][k] in FP64 for row n with the whole
 // block (fixed reduction order), E_n = theta_n + lambda d_n when E is given;
-// row 0 clears the step's statistics when stat_clear is given.
+// the caller passes stat_clear to exactly one block, which clears the step's
+// statistics.
 template <typename TW, typename TD>
 __device__ __forceinline__ void prepass_row(const TW *__restrict__ W, const TD *__restrict__ D, const StepArgs &a,
                                             double *__restrict__ d, double *__restrict__ E,
@@ -257,7 +258,7 @@ __device__ __forceinline__ void prepass_row(const TW *__restrict__ W, const TD *
         const double dn = (double)dl[n] + ((red[0] + red[1]) + (red[2] + red[3]));
         d[n] = dn;
         if (E) E[n] = a.theta[n] + a.lambda * dn;
-        if (stat_clear && n == 0) {
+        if (stat_clear) {
             stat_clear[0] = 0ull;
             stat_clear[1] = 0ull;
         }
@@ -268,7 +269,12 @@ template <typename TW, typename TD>
 __global__ __launch_bounds__(256) void k_prepass(const TW *__restrict__ W, const TD *__restrict__ D, StepArgs a,
                                                  double *__restrict__ d, double *__restrict__ E,
                                                  unsigned long long *stat_clear) {
-    prepass_row(W, D, a, d, E, stat_clear, (int64_t)blockIdx.x);
+    int64_t n = blockIdx.x;
+    if (a.rowmap) {  // retired rows keep their d (not needed: they are not updated)
+        n = a.rowmap[blockIdx.x];
+        if (n < 0) return;
+    }
+    prepass_row(W, D, a, d, E, blockIdx.x == 0 ? stat_clear : nullptr, n);
 }
 
 // --------------------------------------------------------- fused MFMA step
@@ -333,7 +339,9 @@ struct PolF64 {
 
 // One output tile (tm, tn) of one fused step; called by the single-problem
 // kernel below and by the grouped serving kernel (one tile per work item).
-template <class P, int BM, int BN, int BK, int WM, int WN, typename S>
+// PLAIN: the same product without the update, Wnew = A B^T (a plain NT GEMM of
+// two ld x ld operands; deltaT and Wold are not read, no statistics).
+template <class P, int BM, int BN, int BK, int WM, int WN, typename S, bool PLAIN = false>
 __device__ __forceinline__ void step_tile(const typename P::in_t *__restrict__ A, const typename P::in_t *__restrict__ B,
                                           const S *__restrict__ deltaT, const S *__restrict__ Wold,
                                           S *__restrict__ Wnew, __bf16 *__restrict__ Wbnew, const StepArgs &a, int tm,
@@ -370,15 +378,22 @@ __device__ __forceinline__ void step_tile(const typename P::in_t *__restrict__ A
 #pragma unroll
             for (int r = 0; r < P::NACC; ++r) acc[i][j][r] = 0;
 
-    // global -> register staging (16-byte chunks), double-buffered LDS
+    // global -> register staging (16-byte chunks), double-buffered LDS; with a
+    // row map, A row r of the tile is W row rowmap[row0 + r] (padding: row 0,
+    // whose products are not stored)
     const in_t *gA = A + row0 * ld;
     const in_t *gB = B + col0 * ld;
-    u32x4_t ra[A_CH], rb[B_CH];
+    const in_t *pa[A_CH];
 #pragma unroll
     for (int i = 0; i < A_CH; ++i) {
         const int c = tid + i * NT;
-        ra[i] = *reinterpret_cast<const u32x4_t *>(gA + (int64_t)(c / CPR) * ld + (c % CPR) * VEC);
+        int64_t r = row0 + c / CPR;
+        if (a.rowmap) r = max(a.rowmap[r], 0);
+        pa[i] = (a.rowmap ? A + r * ld : gA + (int64_t)(c / CPR) * ld) + (c % CPR) * VEC;
     }
+    u32x4_t ra[A_CH], rb[B_CH];
+#pragma unroll
+    for (int i = 0; i < A_CH; ++i) ra[i] = *reinterpret_cast<const u32x4_t *>(pa[i]);
 #pragma unroll
     for (int i = 0; i < B_CH; ++i) {
         const int c = tid + i * NT;
@@ -405,10 +420,7 @@ __device__ __forceinline__ void step_tile(const typename P::in_t *__restrict__ A
         if (more) {
             const int64_t koff = (int64_t)(kt + 1) * BK;
 #pragma unroll
-            for (int i = 0; i < A_CH; ++i) {
-                const int c = tid + i * NT;
-                ra[i] = *reinterpret_cast<const u32x4_t *>(gA + (int64_t)(c / CPR) * ld + koff + (c % CPR) * VEC);
-            }
+            for (int i = 0; i < A_CH; ++i) ra[i] = *reinterpret_cast<const u32x4_t *>(pa[i] + koff);
 #pragma unroll
             for (int i = 0; i < B_CH; ++i) {
                 const int c = tid + i * NT;
@@ -447,6 +459,18 @@ __device__ __forceinline__ void step_tile(const typename P::in_t *__restrict__ A
         __syncthreads();
     }
 
+    if constexpr (PLAIN) {
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t m = col0 + wc * WTN + j * P::MI + P::acc_col(lane);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int r = 0; r < P::NACC; ++r)
+                    Wnew[(row0 + wr * WTM + i * P::MI + P::acc_row(r, lane)) * ld + m] = (S)acc[i][j][r];
+        }
+        return;
+    }
     // Epilogue: C = Delta^T (exact, state precision) + acc; update of eq. (dyn).
     const S lam = (S)a.lambda;
     double dmax = 0.0, wmax = 0.0;
@@ -459,7 +483,11 @@ __device__ __forceinline__ void step_tile(const typename P::in_t *__restrict__ A
         for (int i = 0; i < TM; ++i) {
 #pragma unroll
             for (int r = 0; r < P::NACC; ++r) {
-                const int64_t n = row0 + wr * WTM + i * P::MI + P::acc_row(r, lane);
+                int64_t n = row0 + wr * WTM + i * P::MI + P::acc_row(r, lane);
+                if (a.rowmap) {
+                    n = a.rowmap[n];
+                    if (n < 0) continue;  // padding of the row list
+                }
                 const int64_t idx = n * ld + m;
                 const S c = (S)acc[i][j][r] + deltaT[idx];
                 const S wo = Wold[idx];
@@ -490,6 +518,48 @@ __global__ __launch_bounds__(WM *WN * 64) void k_step_gemm(const typename P::in_
     int tm, tn;
     tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
     step_tile<P, BM, BN, BK, WM, WN, S>(A, B, deltaT, Wold, Wnew, Wbnew, a, tm, tn);
+}
+
+// --------------------------------------------------- per-row retirement
+// out[i] = max_m |Wn[r][m] - Wo[r][m]| of row r = rowmap[i] (one block per
+// entry; -1 for padding entries).
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_delta(const T *__restrict__ Wn, const T *__restrict__ Wo,
+                                                   const int32_t *__restrict__ rowmap, int64_t ld,
+                                                   double *__restrict__ out) {
+    const int32_t r = rowmap[blockIdx.x];
+    if (r < 0) {
+        if (threadIdx.x == 0) out[blockIdx.x] = -1.0;
+        return;
+    }
+    __shared__ double red[4];
+    double m = 0.0;
+    for (int64_t k = threadIdx.x; k < ld; k += 256) m = fmax(m, fabs((double)Wn[r * ld + k] - (double)Wo[r * ld + k]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// dst row rows[i] = src row rows[i] (one block per listed row).
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_rows(T *__restrict__ dst, const T *__restrict__ src,
+                                                   const int32_t *__restrict__ rows, int64_t ld) {
+    const int64_t r = rows[blockIdx.x];
+    for (int64_t k = threadIdx.x; k < ld; k += 256) dst[r * ld + k] = src[r * ld + k];
+}
+
+// Plain NT product C = A B^T of ld x ld FP64 operands (basis changes of the
+// homotopy continuation), on the tiles of the FP64 step.
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM *WN * 64) void k_gemm_nt_f64(const double *__restrict__ A,
+                                                             const double *__restrict__ B, double *__restrict__ C,
+                                                             StepArgs a, int tiles_m, int tiles_n) {
+    int tm, tn;
+    tile_coords<8>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    step_tile<PolF64, BM, BN, BK, WM, WN, double, true>(A, B, (const double *)nullptr, (const double *)nullptr, C,
+                                                        (__bf16 *)nullptr, a, tm, tn);
 }
 
 // --------------------------------------------------- small problems (ld 64)
@@ -688,7 +758,8 @@ template <class P, int BM, int BN, int BK, int WM, int WN, typename S>
 hipError_t launch_gemm(const StepArgs &a, const typename P::in_t *A, const typename P::in_t *B, const S *deltaT,
                        const S *Wold, S *Wnew, __bf16 *Wbnew, hipStream_t s) {
     if (a.ld % BM || a.ld % BN || a.ld % BK) return hipErrorInvalidValue;
-    const int tiles_m = (int)(a.ld / BM), tiles_n = (int)(a.ld / BN);
+    if (a.rowmap && (a.rows % BM || a.rows < BM || a.rows > a.ld)) return hipErrorInvalidValue;
+    const int tiles_m = (int)((a.rowmap ? a.rows : a.ld) / BM), tiles_n = (int)(a.ld / BN);
     const unsigned int blocks = (unsigned int)tiles_m * (unsigned int)tiles_n;
     hipLaunchKernelGGL((k_step_gemm<P, BM, BN, BK, WM, WN, S>), dim3(blocks), dim3(WM * WN * 64), 0, s, A, B,
                        deltaT, Wold, Wnew, Wbnew, a, tiles_m, tiles_n);
@@ -808,21 +879,21 @@ hipError_t launch_first_iterate_f64(const StepArgs &a, const double *deltaT, dou
 
 hipError_t launch_prepass_f32_f32(const float *W, const float *D, const StepArgs &a, double *d, double *E,
                                   unsigned long long *stat_clear, hipStream_t s) {
-    hipLaunchKernelGGL((k_prepass<float, float>), dim3((unsigned int)a.n), dim3(256), 0, s, W, D, a, d, E,
+    hipLaunchKernelGGL((k_prepass<float, float>), dim3((unsigned int)(a.rowmap ? a.rows : a.n)), dim3(256), 0, s, W, D, a, d, E,
                        stat_clear);
     return hipGetLastError();
 }
 
 hipError_t launch_prepass_f32_f64(const float *W, const double *D, const StepArgs &a, double *d, double *E,
                                   unsigned long long *stat_clear, hipStream_t s) {
-    hipLaunchKernelGGL((k_prepass<float, double>), dim3((unsigned int)a.n), dim3(256), 0, s, W, D, a, d, E,
+    hipLaunchKernelGGL((k_prepass<float, double>), dim3((unsigned int)(a.rowmap ? a.rows : a.n)), dim3(256), 0, s, W, D, a, d, E,
                        stat_clear);
     return hipGetLastError();
 }
 
 hipError_t launch_prepass_f64_f64(const double *W, const double *D, const StepArgs &a, double *d, double *E,
                                   unsigned long long *stat_clear, hipStream_t s) {
-    hipLaunchKernelGGL((k_prepass<double, double>), dim3((unsigned int)a.n), dim3(256), 0, s, W, D, a, d, E,
+    hipLaunchKernelGGL((k_prepass<double, double>), dim3((unsigned int)(a.rowmap ? a.rows : a.n)), dim3(256), 0, s, W, D, a, d, E,
                        stat_clear);
     return hipGetLastError();
 }
@@ -839,6 +910,13 @@ hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *D
 
 hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta, const float *deltaT, float *Wn,
                            __bf16 *Wbn, hipStream_t s) {
+    // a row map runs on the general kernel's 128-row tiles (the large kernel's
+    // direct-to-LDS loads assume contiguous tile rows)
+    if (a.rowmap) {
+        if (row_tile(a.ld) == 128)
+            return launch_gemm<PolF32, 128, 128, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
+        return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
+    }
     if (!Wbn && step_large_preferred(a.ld)) return launch_step_f32_large(a, W, Delta, deltaT, Wn, s);
     if (a.ld % 256 == 0 && a.ld >= 1024)
         return launch_gemm<PolF32, 128, 128, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
@@ -851,9 +929,54 @@ hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta
 // 128-wide tiles leave CUs idle.
 hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT, double *Wn,
                            hipStream_t s) {
-    if (a.ld >= 4096 && a.ld % 128 == 0)
+    if ((a.ld >= 4096 || a.rowmap) && row_tile(a.ld) == 128)
         return launch_gemm<PolF64, 128, 128, 32, 4, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
     return launch_gemm<PolF64, 64, 64, 16, 2, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
+}
+
+hipError_t launch_row_delta_f32(const float *Wn, const float *Wo, const int32_t *rowmap, int64_t rows, int64_t ld,
+                                double *out, hipStream_t s) {
+    if (rows < 1) return hipSuccess;
+    hipLaunchKernelGGL((k_row_delta<float>), dim3((unsigned int)rows), dim3(256), 0, s, Wn, Wo, rowmap, ld, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_delta_f64(const double *Wn, const double *Wo, const int32_t *rowmap, int64_t rows, int64_t ld,
+                                double *out, hipStream_t s) {
+    if (rows < 1) return hipSuccess;
+    hipLaunchKernelGGL((k_row_delta<double>), dim3((unsigned int)rows), dim3(256), 0, s, Wn, Wo, rowmap, ld, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_rows_f32(float *dst, const float *src, const int32_t *rows, int64_t count, int64_t ld,
+                                hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    hipLaunchKernelGGL((k_copy_rows<float>), dim3((unsigned int)count), dim3(256), 0, s, dst, src, rows, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_rows_f64(double *dst, const double *src, const int32_t *rows, int64_t count, int64_t ld,
+                                hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    hipLaunchKernelGGL((k_copy_rows<double>), dim3((unsigned int)count), dim3(256), 0, s, dst, src, rows, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_nt_f64(const double *A, const double *B, double *C, int64_t ld, hipStream_t s) {
+    StepArgs a{};
+    a.n = ld;
+    a.ld = ld;
+    if (ld >= 4096 && ld % 128 == 0) {
+        const int t = (int)(ld / 128);
+        hipLaunchKernelGGL((k_gemm_nt_f64<128, 128, 32, 4, 2>), dim3((unsigned int)(t * t)), dim3(512), 0, s, A, B, C,
+                           a, t, t);
+    } else {
+        if (ld % 64) return hipErrorInvalidValue;
+        const int t = (int)(ld / 64);
+        hipLaunchKernelGGL((k_gemm_nt_f64<64, 64, 16, 2, 2>), dim3((unsigned int)(t * t)), dim3(256), 0, s, A, B, C, a,
+                           t, t);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_small_steps_f32(const float *Wcur, float *hist, const float *D, const float *DT, const StepArgs &a,

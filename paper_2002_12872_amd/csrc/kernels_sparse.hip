@@ -275,6 +275,29 @@ __global__ __launch_bounds__(256) void k_sp_export(const T *__restrict__ ZT, int
     }
 }
 
+// Warm start: eigenvectors z0[k * n + m] = z_k[m] (device, TS) into the
+// transposed panel-major state, ZT[m][k] = z_k[m], unit diagonal, zeros in the
+// padding; 64 x 64 tiles transposed through LDS (row k read along m, panel row
+// m written along k).
+template <typename TS, typename T>
+__global__ __launch_bounds__(256) void k_sp_load(const TS *__restrict__ z0, int64_t n, int64_t ld,
+                                                 T *__restrict__ ZT) {
+    __shared__ T tile[64][65];
+    const int64_t bx = blockIdx.x, by = blockIdx.y;  // eigenvectors bx*64.., components by*64..
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t k = bx * 64 + r, m = by * 64 + tx;
+        T v = (T)0;
+        if (k < n && m < n) v = k == m ? (T)1 : (T)z0[k * n + m];
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t m = by * 64 + r, k = bx * 64 + tx;
+        ZT[Panel<T>::at(m, k, ld)] = tile[tx][r];
+    }
+}
+
 // Residual of eigenvector j = rows[blockIdx.x]; partial sum of squares per block.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sp_residual(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
@@ -814,6 +837,28 @@ hipError_t sparse_export(SparseState *sp, int64_t n, void *out, int out_f64, hip
     return hipGetLastError();
 }
 
+hipError_t sparse_load_state(SparseState *sp, const void *z0, int z0_f64, hipStream_t s) {
+    const dim3 grid((unsigned int)(sp->ld / 64), (unsigned int)(sp->ld / 64));
+    if (sp->fp64) {
+        if (z0_f64)
+            hipLaunchKernelGGL((k_sp_load<double, double>), grid, dim3(256), 0, s, (const double *)z0, sp->n, sp->ld,
+                               sp->ZT64[0]);
+        else
+            hipLaunchKernelGGL((k_sp_load<float, double>), grid, dim3(256), 0, s, (const float *)z0, sp->n, sp->ld,
+                               sp->ZT64[0]);
+    } else {
+        if (z0_f64)
+            hipLaunchKernelGGL((k_sp_load<double, float>), grid, dim3(256), 0, s, (const double *)z0, sp->n, sp->ld,
+                               sp->ZT32[0]);
+        else
+            hipLaunchKernelGGL((k_sp_load<float, float>), grid, dim3(256), 0, s, (const float *)z0, sp->n, sp->ld,
+                               sp->ZT32[0]);
+    }
+    sp->cur = 0;
+    sp->at_identity = false;
+    return hipGetLastError();
+}
+
 hipError_t sparse_residuals(SparseState *sp, double lambda, const double *theta, const double *evec,
                             const int64_t *rows, int64_t nrows, double *res, hipStream_t s) {
     int64_t *drows = nullptr;
@@ -881,26 +926,36 @@ hipError_t dominant_iterate(const dpt_problem *p, const dpt_options *o, const in
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int cur = 0;
+    double ak = 1.0;  // ramp_alpha^k (Supplement E's coupling ramp)
     while (out->iters < o->max_iter) {
         unsigned long long *st = b.stats + 2 * out->iters;
+        double lam = p->lambda;
+        bool ramping = false;
+        if (o->ramp_alpha > 0.0) {
+            ak *= o->ramp_alpha;
+            if (ak >= 0x1p-53) {
+                lam = p->lambda * (1.0 - ak);
+                ramping = true;
+            }
+        }
         if (out->iters == 0) {  // z = e_nstar: closed form
             if (csr)
                 hipLaunchKernelGGL((k_dom_first<T, true>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, rowptr,
-                                   col, val, n, nstar, p->lambda, theta, b.z[cur ^ 1], st);
+                                   col, val, n, nstar, lam, theta, b.z[cur ^ 1], st);
             else
                 hipLaunchKernelGGL((k_dom_first<T, false>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
-                                   (const int64_t *)nullptr, (const int *)nullptr, val, n, nstar, p->lambda, theta,
+                                   (const int64_t *)nullptr, (const int *)nullptr, val, n, nstar, lam, theta,
                                    b.z[cur ^ 1], st);
         } else if (csr) {
             hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, rowptr, col, val, nstar,
                                (const T *)b.z[cur], b.s);
             hipLaunchKernelGGL((k_dom_csr<T>), dim3(blocks_for(n, 32, kDomGrid)), dim3(256), 0, s, rowptr, col, val,
-                               n, nstar, p->lambda, theta, (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
+                               n, nstar, lam, theta, (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
         } else {
             hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, val, n, nstar, (const T *)b.z[cur],
                                b.s);
-            hipLaunchKernelGGL((k_dom_dense<T>), dim3(blocks_for(n, 4)), dim3(256), 0, s, val, n, nstar, p->lambda,
-                               theta, (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
+            hipLaunchKernelGGL((k_dom_dense<T>), dim3(blocks_for(n, 4)), dim3(256), 0, s, val, n, nstar, lam, theta,
+                               (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(hs, st, 16, hipMemcpyDeviceToHost, s);
@@ -915,7 +970,7 @@ hipError_t dominant_iterate(const dpt_problem *p, const dpt_options *o, const in
             out->status = DPT_DIVERGED;
             break;
         }
-        if (dl < o->tol) {
+        if (!ramping && dl < o->tol) {
             out->status = DPT_OK;
             break;
         }

@@ -178,6 +178,7 @@ struct dpt_server_ctx {
     dpt_serve_config cfg{};
     int device = 0, grid = 1024;
     hipStream_t stream = nullptr;
+    bool own_stream = true;
     unsigned char *arena_base = nullptr;
     Arena arena;
     size_t arena_used = 0;
@@ -221,7 +222,7 @@ struct dpt_server_ctx {
         if (table_h) (void)hipHostFree(table_h);
         if (stats_h) (void)hipHostFree(stats_h);
         if (ring.base) (void)hipHostFree(ring.base);
-        if (stream) (void)hipStreamDestroy(stream);
+        if (stream && own_stream) (void)hipStreamDestroy(stream);
         for (auto *r : pending) delete r;
         for (auto &kv : done) delete kv.second;
         for (auto *r : active) delete r;
@@ -613,6 +614,28 @@ struct dpt_server_ctx {
     }
 };
 
+namespace {
+// dst = (float) src (n x n), written in order (dst is pinned staging memory:
+// write-combined, slow to read and to write out of order), and whether the FP32
+// values are exactly symmetric, tested on the caller's cached array over 64 x 64
+// blocks with their mirrors (stops at the first mismatch).
+template <typename T>
+bool stage_and_test(const T *src, int64_t n, float *dst) {
+    const size_t nn = (size_t)(n * n);
+    for (size_t i = 0; i < nn; ++i) dst[i] = (float)src[i];
+    for (int64_t bi = 0; bi < n; bi += 64) {
+        const int64_t ie = std::min(bi + 64, n);
+        for (int64_t bj = bi; bj < n; bj += 64) {
+            const int64_t je = std::min(bj + 64, n);
+            for (int64_t i = bi; i < ie; ++i)
+                for (int64_t j = std::max(bj, i + 1); j < je; ++j)
+                    if ((float)src[i * n + j] != (float)src[j * n + i]) return false;
+        }
+    }
+    return true;
+}
+}  // namespace
+
 extern "C" {
 
 int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
@@ -627,7 +650,14 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     c->grid = cfg->grid_blocks > 0 ? cfg->grid_blocks : 1024;
     c->t0 = std::chrono::steady_clock::now();
     hipError_t e = hipGetDevice(&c->device);
-    if (e == hipSuccess) e = hipStreamCreate(&c->stream);
+    if (e == hipSuccess) {
+        if (cfg->stream) {  // the caller's stream: used, never destroyed
+            c->stream = (hipStream_t)cfg->stream;
+            c->own_stream = false;
+        } else {
+            e = hipStreamCreate(&c->stream);
+        }
+    }
     if (e == hipSuccess) e = hipMalloc((void **)&c->arena_base, (size_t)cfg->budget_bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&c->table_d, sizeof(GroupTable));
     if (e == hipSuccess) e = hipMalloc((void **)&c->stats_d, 16 * (size_t)cfg->max_slots);
@@ -663,6 +693,7 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     return DPT_OK;
 }
 
+
 int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o, int want_eigenvectors,
                      int64_t *ticket) {
     if (!srv || !ticket) return DPT_EINVAL;
@@ -675,6 +706,8 @@ int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o,
         dpt_options_default(&opt);
     }
     if (opt.precision != DPT_FP32 && opt.precision != DPT_BF16_FP32) return DPT_EINVAL;
+    if (opt.ramp_alpha != 0.0) return DPT_EINVAL;  // the engine runs the autonomous map
+    if (opt.stop_rule == DPT_STOP_ROW) return DPT_EINVAL;  // requests retire whole
     Request *r = new (std::nothrow) Request();
     if (!r) return DPT_ENOMEM;
     r->n = p->n;
@@ -724,24 +757,10 @@ int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o,
     }
     if (!dst) dst = r->delta.data();
     std::memcpy(r->theta.data(), p->theta, sizeof(double) * (size_t)p->n);
-    if (p->dtype == DPT_DTYPE_F64) {
-        const double *src = (const double *)p->delta;
-        for (size_t i = 0; i < nn; ++i) dst[i] = (float)src[i];
-    } else {
-        std::memcpy(dst, p->delta, nn * 4);
-    }
-    // exact symmetry test over 64 x 64 blocks (the mirrored block stays in cache)
-    bool sym = true;
-    const int64_t n = p->n;
-    const float *dl = dst;
-    for (int64_t bi = 0; bi < n && sym; bi += 64)
-        for (int64_t bj = bi; bj < n && sym; bj += 64)
-            for (int64_t i = bi; i < std::min(bi + 64, n) && sym; ++i)
-                for (int64_t j = std::max(bj, i + 1); j < std::min(bj + 64, n); ++j)
-                    if (!(dl[(size_t)(i * n + j)] == dl[(size_t)(j * n + i)])) {
-                        sym = false;
-                        break;
-                    }
+    // FP32 copy into the staging ring; symmetry of the FP32 values tested on the
+    // caller's array (not on the pinned copy).
+    const bool sym = p->dtype == DPT_DTYPE_F64 ? stage_and_test<double>((const double *)p->delta, p->n, dst)
+                                               : stage_and_test<float>((const float *)p->delta, p->n, dst);
     r->symmetric = sym;
     if (request_bytes(r->ld, r->bf16, r->symmetric) > (size_t)srv->cfg.budget_bytes) return drop(DPT_ENOMEM);
     {

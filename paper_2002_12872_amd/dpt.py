@@ -24,7 +24,7 @@ DPT_FP64, DPT_FP32, DPT_BF16_FP32, DPT_FP8_FP32, DPT_BF16_X3 = 0, 1, 2, 3, 4
 DPT_DENSE, DPT_CSR = 0, 1
 DPT_MEM_HOST, DPT_MEM_DEVICE = 0, 1
 DPT_DTYPE_F64, DPT_DTYPE_F32 = 0, 1
-DPT_STOP_DELTA, DPT_STOP_ESTIMATE = 0, 1
+DPT_STOP_DELTA, DPT_STOP_ESTIMATE, DPT_STOP_ROW = 0, 1, 2
 
 
 class DptError(RuntimeError):
@@ -56,6 +56,7 @@ class Options(ctypes.Structure):
         ("fp64_final_tol", ctypes.c_double),
         ("stall_ratio", ctypes.c_double),
         ("blowup", ctypes.c_double),
+        ("ramp_alpha", ctypes.c_double),
         ("max_iter", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("stall_patience", ctypes.c_int32),
@@ -89,7 +90,7 @@ class Profile(ctypes.Structure):
 class ServeConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class ServeTimes(ctypes.Structure):
@@ -120,6 +121,13 @@ _FUNCS = {
     "dpt_dominant_noalloc": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_int64,
                                             ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
                                             ctypes.POINTER(Result)]),
+    "dpt_homotopy": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Result)]),
+    "dpt_rs_series": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int]),
+    "dpt_row_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "dpt_probe_gather": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "dpt_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "dpt_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Profile)]),
     "dpt_serve_open": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ServeConfig)]),
@@ -250,12 +258,12 @@ class ProblemSpec:
 
 
 def options(tol=1e-6, max_iter=200, precision=DPT_FP32, fp64_final_tol=0.0, stall_ratio=0.5,
-            stall_patience=2, check_every=1, blowup=1e6, stop_rule=DPT_STOP_DELTA):
+            stall_patience=2, check_every=1, blowup=1e6, stop_rule=DPT_STOP_DELTA, ramp_alpha=0.0):
     o = Options()
     load_library().dpt_options_default(ctypes.byref(o))
     o.tol, o.max_iter, o.precision = tol, max_iter, precision
     o.fp64_final_tol, o.stall_ratio, o.stall_patience = fp64_final_tol, stall_ratio, stall_patience
-    o.check_every, o.blowup, o.stop_rule = check_every, blowup, stop_rule
+    o.check_every, o.blowup, o.stop_rule, o.ramp_alpha = check_every, blowup, stop_rule, ramp_alpha
     return o
 
 
@@ -398,6 +406,74 @@ def dpt_dominant_noalloc(problem: ProblemSpec, opts: Options, out, index: int = 
                            "history": hist[:min(r.iters, history_cap)].copy()}
 
 
+def dpt_homotopy(problem: ProblemSpec, opts: Options, stages: int, E=None, Z=None, z_dtype=np.float64):
+    """Homotopy continuation in ``stages`` FP64 stages.  Outputs default to host
+    arrays (device tensors for a device problem).  Returns (E, Z, result dict)."""
+    st = problem.struct
+    n = st.n
+    if E is None or Z is None:
+        if problem.device:
+            import torch
+            E = torch.empty(n, dtype=torch.float64, device="cuda") if E is None else E
+            Z = torch.empty((n, n), dtype=torch.float64 if z_dtype == np.float64 else torch.float32,
+                            device="cuda") if Z is None else Z
+        else:
+            E = np.empty(n, np.float64) if E is None else E
+            Z = np.empty((n, n), z_dtype) if Z is None else Z
+    ep, _, _, ek = _info(E)
+    zp, zdt, _, zk = _info(Z)
+    r = Result()
+    rc = load_library().dpt_homotopy(ctypes.byref(st), ctypes.byref(opts), int(stages), ep, zp, _dtype_code(zdt),
+                                     ctypes.byref(r))
+    if rc < 0:
+        raise DptError(rc, "dpt_homotopy")
+    return E, Z, {"status": r.status, "iters": r.iters}
+
+
+def dpt_rs_series(problem: ProblemSpec, order: int, want_z: bool = True):
+    """Rayleigh-Schroedinger coefficients on the GPU.  Returns (eps (order, n),
+    coef_max (order,), Z partial sum (n, n) host array or None); a device problem
+    gets Z as a device tensor."""
+    st = problem.struct
+    n = st.n
+    eps = np.empty((order, n), np.float64)
+    cmax = np.empty(order, np.float64)
+    z = None
+    zp = None
+    if want_z:
+        if problem.device:
+            import torch
+            z = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        else:
+            z = np.empty((n, n), np.float64)
+        zp, _, _, _ = _info(z)
+    rc = load_library().dpt_rs_series(ctypes.byref(st), int(order), eps.ctypes.data, cmax.ctypes.data, zp,
+                                      DPT_DTYPE_F64)
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_rs_series")
+    return eps, cmax, z
+
+
+def dpt_row_status(h: Handle):
+    """(retired_at (n,) int32, rows_multiplied) of a DPT_STOP_ROW solve."""
+    out = np.zeros(h.n, np.int32)
+    rm = ctypes.c_int64()
+    rc = load_library().dpt_row_status(h.ptr, out.ctypes.data, ctypes.byref(rm))
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_row_status")
+    return out, rm.value
+
+
+def dpt_probe_gather(panel_rows: int, gathers: int, reps: int = 5):
+    """(ms per pass, GB/s) of random 512-byte row gathers from a panel (measurement probe)."""
+    ms, gbs = ctypes.c_double(), ctypes.c_double()
+    rc = load_library().dpt_probe_gather(int(panel_rows), int(gathers), int(reps), ctypes.byref(ms),
+                                         ctypes.byref(gbs))
+    if rc != DPT_OK:
+        raise DptError(rc, "dpt_probe_gather")
+    return ms.value, gbs.value
+
+
 def dpt_profile_enable(h: Handle, on: bool = True) -> None:
     rc = load_library().dpt_profile_enable(h.ptr, int(bool(on)))
     if rc != DPT_OK:
@@ -434,8 +510,11 @@ class Server:
             self.ptr = None
 
 
-def dpt_serve_open(budget_bytes, max_slots=256, use_graph=True, grid_blocks=0, autotune=False) -> Server:
-    cfg = ServeConfig(int(budget_bytes), int(max_slots), int(bool(use_graph)), int(grid_blocks), int(bool(autotune)))
+def dpt_serve_open(budget_bytes, max_slots=256, use_graph=True, grid_blocks=0, autotune=False,
+                   stream=None) -> Server:
+    """stream: a hipStream_t (e.g. torch.cuda.Stream().cuda_stream) for the server's work, or None."""
+    cfg = ServeConfig(int(budget_bytes), int(max_slots), int(bool(use_graph)), int(grid_blocks), int(bool(autotune)),
+                      stream)
     h = ctypes.c_void_p()
     rc = load_library().dpt_serve_open(ctypes.byref(h), ctypes.byref(cfg))
     if rc != DPT_OK:

@@ -138,12 +138,20 @@ def test_validate_rejects_bad_csr(bad):
 @pytest.mark.parametrize("field,value", [
     ("tol", 0.0), ("tol", -1.0), ("tol", float("nan")), ("max_iter", -1), ("precision", 5),
     ("fp64_final_tol", -1.0), ("stall_ratio", 1.5), ("stall_patience", 0), ("check_every", 0),
-    ("blowup", 0.0), ("stop_rule", 2), ("reserved", 1),
+    ("blowup", 0.0), ("stop_rule", 3), ("reserved", 1), ("ramp_alpha", 1.0), ("ramp_alpha", -0.5),
+    ("ramp_alpha", float("nan")),
 ])
 def test_validate_rejects_bad_options(field, value):
     o = dpt.options()
     setattr(o, field, value)
     assert dpt.dpt_validate(_spec(), o) == dpt.DPT_EINVAL
+
+
+@pytest.mark.parametrize("precision,fp64_final_tol,ok", [
+    (1, 0.0, True), (0, 0.0, True), (2, 0.0, True), (3, 0.0, False), (4, 0.0, False), (2, 1e-10, False)])
+def test_per_row_rule_only_with_its_precisions(precision, fp64_final_tol, ok):
+    o = dpt.options(precision=precision, fp64_final_tol=fp64_final_tol, stop_rule=dpt.DPT_STOP_ROW)
+    assert dpt.dpt_validate(_spec(), o) == (dpt.DPT_OK if ok else dpt.DPT_EINVAL)
 
 
 def test_init_rejects_invalid_before_touching_device():

@@ -1,0 +1,90 @@
+"""Per-row retirement (DPT_STOP_ROW; Sec. II.B: row n evolves under its own map).
+
+Against the oracle's per-row stop (each row frozen after the first step whose
+own delta is below tol): the step each row freezes on, and the rows
+themselves (FP64: 1e-12; FP32: the FP32 bar against the converged oracle).
+Frozen rows stay bitwise unchanged by later products, and the products run on
+fewer rows (rows_multiplied) when rows freeze at different steps, as on the
+delta-potential of Sec. II.F, whose lowest level converges last.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from helpers import rel_eig_error, small_problem
+
+pytestmark = pytest.mark.gpu
+
+dpt = pytest.importorskip("paper_2002_12872_amd.dpt")
+
+
+def row_solve(theta, delta, lam, precision, tol, max_iter=200):
+    h = dpt.dpt_init(dpt.ProblemSpec(theta, delta, lam, stream=0),
+                     dpt.options(tol=tol, max_iter=max_iter, precision=precision, stop_rule=dpt.DPT_STOP_ROW))
+    return h, dpt.dpt_solve(h)
+
+
+@pytest.mark.parametrize("n", [100, 300, 1100])
+def test_fp64_rows_freeze_on_the_oracle_step(n):
+    theta, delta = workloads.delta_potential(n)
+    h, res = row_solve(theta, delta, 1.0, dpt.DPT_FP64, 1e-12)
+    ref = oracle.iterate(theta, delta, 1.0, max_iter=200, tol=1e-12, per_row=True)
+    assert res["status"] == dpt.DPT_OK and ref["status"] == oracle.OR_OK
+    assert res["iters"] == ref["iters"]
+    at, rows_mult = dpt.dpt_row_status(h)
+    assert np.array_equal(at, ref["row_iters"])
+    assert len(set(at.tolist())) > 2                   # rows freeze on different steps
+    z = dpt.dpt_eigenvectors(h)
+    assert np.max(np.abs(z - ref["z"])) <= 1e-12 * max(1.0, np.abs(ref["z"]).max())
+    assert rel_eig_error(dpt.dpt_eigenvalues(h), ref["e"], theta) <= 1e-12
+    ld = (n + 255) // 256 * 256 if n >= 1024 else (n + 63) // 64 * 64
+    tile = 128 if ld % 128 == 0 else 64
+    if ld > tile:                                      # row lists are padded to the product tile
+        assert rows_mult < ld * (res["iters"] - 1)      # products skipped frozen rows
+
+
+def test_frozen_rows_stay_bitwise_and_running_rows_continue():
+    n = 1100
+    theta, delta = workloads.delta_potential(n)
+    h, res = row_solve(theta, delta, 1.0, dpt.DPT_FP64, 1e-12, max_iter=9)
+    assert res["status"] == dpt.DPT_NOT_CONVERGED
+    at, _ = dpt.dpt_row_status(h)
+    frozen = at > 0
+    assert frozen.any() and not frozen.all()
+    z0 = dpt.dpt_eigenvectors(h)
+    dpt.dpt_step(h, 2)
+    z1 = dpt.dpt_eigenvectors(h)
+    assert np.array_equal(z1[frozen], z0[frozen])
+    assert np.max(np.abs(z1[~frozen] - z0[~frozen])) > 0.0
+    ref = oracle.iterate(theta, delta, 1.0, rows=np.nonzero(~frozen)[0], max_iter=11, fixed_steps=True)
+    assert np.max(np.abs(z1[~frozen] - ref["z"])) <= 1e-12 * max(1.0, np.abs(ref["z"]).max())
+
+
+@pytest.mark.parametrize("precision", [dpt.DPT_FP32, dpt.DPT_BF16_FP32])
+def test_fp32_rows_reach_the_fp32_bar(precision):
+    n = 4096
+    theta, delta = workloads.delta_potential(n)
+    delta = delta.astype(np.float32)
+    h, res = row_solve(theta, delta, 1.0, precision, 1e-6)
+    assert res["status"] == dpt.DPT_OK
+    at, rows_mult = dpt.dpt_row_status(h)
+    assert at.min() >= 1 and at.max() == res["iters"]
+    rows = workloads.sample_rows(n, 48)
+    ref = oracle.iterate(theta, delta.astype(np.float64), 1.0, rows=rows, max_iter=200, tol=1e-14)
+    assert rel_eig_error(dpt.dpt_eigenvalues(h)[rows], ref["e"], theta) <= 1e-5
+    z = dpt.dpt_eigenvectors(h)[rows]
+    assert np.max(np.abs(z - ref["z"])) / np.max(np.abs(ref["z"] - np.eye(n)[rows])) <= 1e-5
+    assert rows_mult < n * (res["iters"] - 1)
+
+
+def test_per_row_rule_rejections():
+    th, ip, ix, v = workloads.sparse_sym(0, n=200)
+    with pytest.raises(dpt.DptError):
+        dpt.dpt_init(dpt.ProblemSpec(th, (ip, ix, v), 1.0, stream=0), dpt.options(stop_rule=dpt.DPT_STOP_ROW))
+    theta, delta = small_problem(64, 1)
+    srv = dpt.dpt_serve_open(64 << 20, max_slots=4)
+    with pytest.raises(dpt.DptError):
+        dpt.dpt_serve_submit(srv, dpt.ProblemSpec(theta, delta.astype(np.float32), 1.0, stream=0),
+                             dpt.options(precision=dpt.DPT_BF16_FP32, stop_rule=dpt.DPT_STOP_ROW))
+    dpt.dpt_serve_close(srv)

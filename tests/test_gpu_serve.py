@@ -192,3 +192,24 @@ def test_large_problems_and_tile_autotuner(autotune):
         ref = oracle.iterate(th, de.astype(np.float64), 1.0, rows=rows, max_iter=200, tol=1e-14)
         assert rel_eig_error(res["E"][rows], ref["e"], th) <= 1e-5
         assert np.max(np.abs(res["Z"][rows] - ref["z"])) <= 1e-5 * np.max(np.abs(ref["z"] - np.eye(n)[rows]))
+
+
+def test_server_on_the_callers_stream():
+    """dpt_serve_open on a caller-provided stream: same results as on the
+    server's own stream (bitwise), and the stream stays usable afterwards."""
+    import torch
+    probs = [request(*m) for m in MIX[:5]]
+    s = torch.cuda.Stream()
+    a = dpt.dpt_serve_open(1 << 30, max_slots=16, stream=s.cuda_stream)
+    ra = run_all(a, probs)
+    dpt.dpt_serve_close(a)
+    b = dpt.dpt_serve_open(1 << 30, max_slots=16)
+    rb = run_all(b, probs)
+    dpt.dpt_serve_close(b)
+    for x, y in zip(ra, rb):
+        assert x["status"] == dpt.DPT_OK
+        assert np.array_equal(x["E"], y["E"]) and np.array_equal(x["Z"], y["Z"])
+    with torch.cuda.stream(s):
+        t = torch.ones(16, device="cuda") * 2
+    s.synchronize()
+    assert float(t.sum()) == 32.0
