@@ -800,6 +800,9 @@ def main():
                    "n": n, "tol": args.tol, "stop_rule": args.stop_rule,
                    "step": "one full solve (init+solve+readout)"},
         "iters_per_solve": [r["iters"] for r in results],
+        # the first application of the map is the closed form F(I): one product fewer
+        "products_per_solve": [r["iters"] - 1 for r in results],
+        "product_steps_per_s": round(gemm_steps / elapsed, 3),
         "iters_bf16_fp32": [results[0]["iters_bf16"], results[0]["iters_fp32"]],
         "delta_history": [float("%.3g" % x) for x in results[0]["history"]],
         "solve_tflops": round(gemm_steps * flop / elapsed / 1e12, 2),

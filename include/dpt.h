@@ -138,8 +138,9 @@ typedef struct dpt_options {
  * delta_k(n) = max_m |Z_k[n][m] - Z_{k-1}[n][m]| is below tol, and later products
  * run on the remaining rows only (row list padded to the product tile); the
  * solve ends with DPT_OK when no row is left.  The phases before the final one
- * follow the delta rule.  Dense problems with those precisions and
- * fp64_final_tol = 0 only (DPT_EINVAL otherwise); see dpt_row_status. */
+ * follow the delta rule.  Dense problems with those precisions,
+ * fp64_final_tol = 0 and check_every = 1 only (DPT_EINVAL otherwise); see
+ * dpt_row_status. */
 #define DPT_STOP_ROW 2
 
 typedef struct dpt_result {

@@ -69,7 +69,7 @@ bool valid_options(const dpt_options *o) {
         return false;
     if (o->stop_rule == DPT_STOP_ROW &&
         ((o->precision != DPT_FP32 && o->precision != DPT_FP64 && o->precision != DPT_BF16_FP32) ||
-         o->fp64_final_tol != 0.0))
+         o->fp64_final_tol != 0.0 || o->check_every != 1))  // rows are judged after every step
         return false;
     if (!(o->ramp_alpha >= 0.0) || !(o->ramp_alpha < 1.0)) return false;
     if (o->reserved != 0) return false;

@@ -147,10 +147,12 @@ def test_validate_rejects_bad_options(field, value):
     assert dpt.dpt_validate(_spec(), o) == dpt.DPT_EINVAL
 
 
-@pytest.mark.parametrize("precision,fp64_final_tol,ok", [
-    (1, 0.0, True), (0, 0.0, True), (2, 0.0, True), (3, 0.0, False), (4, 0.0, False), (2, 1e-10, False)])
-def test_per_row_rule_only_with_its_precisions(precision, fp64_final_tol, ok):
-    o = dpt.options(precision=precision, fp64_final_tol=fp64_final_tol, stop_rule=dpt.DPT_STOP_ROW)
+@pytest.mark.parametrize("precision,fp64_final_tol,check_every,ok", [
+    (1, 0.0, 1, True), (0, 0.0, 1, True), (2, 0.0, 1, True), (3, 0.0, 1, False), (4, 0.0, 1, False),
+    (2, 1e-10, 1, False), (1, 0.0, 2, False)])
+def test_per_row_rule_only_with_its_precisions(precision, fp64_final_tol, check_every, ok):
+    o = dpt.options(precision=precision, fp64_final_tol=fp64_final_tol, check_every=check_every,
+                    stop_rule=dpt.DPT_STOP_ROW)
     assert dpt.dpt_validate(_spec(), o) == (dpt.DPT_OK if ok else dpt.DPT_EINVAL)
 
 
