@@ -94,7 +94,8 @@ def serving_bench(args):
     one-at-a-time FP32 service rate mu_1 is measured first on the trace's
     problems; arrivals are Poisson at rate mu_1.  Engine latencies come from its
     own submit/finish timestamps; the one-at-a-time latencies from its measured
-    service times through a FIFO single-server queue on the same arrivals.
+    service times through a FIFO single-server queue on the same arrivals, and
+    observed in real time on the same arrivals (one_at_a_time_fp32_observed).
     """
     import numpy as np
 
@@ -172,13 +173,34 @@ def serving_bench(args):
         return {"solves_per_s": round(count / (fin[-1] - arr[0]), 2),
                 "p50_ms": round(1e3 * percentile(lat_b, 50), 3), "p99_ms": round(1e3 * percentile(lat_b, 99), 3)}
 
+    def base_observed(arr):
+        """One-at-a-time FP32 solves in real time on the arrival times arr: each
+        request starts when it has arrived and the previous one is done."""
+        t0 = time.perf_counter()
+        lat = np.empty(count)
+        for i, sp in enumerate(specs):
+            delay = arr[i] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            h = dpt.dpt_init(sp, o_fp32)
+            dpt.dpt_solve(h, history_cap=0)
+            dpt.dpt_eigenvalues(h)
+            dpt.dpt_destroy(h)
+            lat[i] = (time.perf_counter() - t0) - arr[i]
+        span = (time.perf_counter() - t0) - arr[0]
+        return {"solves_per_s": round(count / span, 2), "p50_ms": round(1e3 * percentile(lat, 50), 3),
+                "p99_ms": round(1e3 * percentile(lat, 99), 3), "observed": True}
+
     eng = engine_run(arrivals)
     eng2 = engine_run(arrivals / 2.0)
     burst = engine_run(None)
     base2 = base_at(2.0)
+    base_obs = base_observed(arrivals)
     return {"requests": count, "arrival_rate_per_s": round(mu1, 2), "tol": 1e-5,
             "engine_bf16_fp32": eng, "one_at_a_time_fp32": base,
+            "one_at_a_time_fp32_observed": base_obs,
             "p99_speedup": round(base["p99_ms"] / eng["p99_ms"], 2),
+            "p99_speedup_observed": round(base_obs["p99_ms"] / eng["p99_ms"], 2),
             "at_2x_rate": {"engine_bf16_fp32": eng2, "one_at_a_time_fp32": base2},
             "burst_all_at_t0": {"engine_solves_per_s": burst["solves_per_s"],
                                 "one_at_a_time_solves_per_s": round(mu1, 2),
@@ -328,6 +350,32 @@ def paper_scale_dominant():
             "frac_hbm_peak": round(it_bytes / per_iter / 1e9 / PEAK_HBM_GBS, 3),
             "eigenvalue": ev, "generation_s": round(gen_s, 1),
             "paper": "4 iterations, 3 s (Mathematica on a desktop CPU, 1e8 nnz; Sec. II.H)"}
+
+
+def vendor_gemm_reference(n):
+    """The vendor library's plain GEMM (torch.matmul -> hipBLASLt) at the same
+    size, for context: the fused steps add the update, the BF16 shadow and the
+    statistics to a product of this shape."""
+    import torch
+    out = {}
+    for name, dt, reps in (("bf16", torch.bfloat16, 5), ("fp32", torch.float32, 3)):
+        a = torch.randn(n, n, device="cuda").to(dt)
+        b = torch.randn(n, n, device="cuda").to(dt)
+        torch.matmul(a, b)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            torch.matmul(a, b)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        peak = PEAK_BF16_TFLOPS if name == "bf16" else PEAK_FP32_TFLOPS
+        tf = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        out[name] = {"ms": round(ms, 3), "tflops": round(tf, 1), "frac_peak": round(tf / peak, 3)}
+        del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def next_rows_bench():
@@ -812,6 +860,7 @@ def main():
         "fp32": fp32,
         "speedup_vs_fp32": (round(fp32["ms_per_solve"] / ms_per_solve, 3) if fp32 else None),
         "other_stop_rule": {"rule": other, **other_rule},
+        "vendor_plain_gemm_same_size": vendor_gemm_reference(n),
         "fp8_fp32_experiment": fp8,
         "bf16_x3_experiment": x3,
         "bf16_fp32_fp64_to_1e-10": fp64_final,

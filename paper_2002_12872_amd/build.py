@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ_DIR = os.path.join(HERE, "_build")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libdpt.so")
-SOURCES = ["kernels_dense.hip", "kernels_gemm_large.hip", "kernels_sparse.hip", "homotopy.hip", "rs_series.hip",
+SOURCES = ["kernels_dense.hip", "kernels_gemm_large.hip", "kernels_gemm_f64.hip", "kernels_sparse.hip",
+           "homotopy.hip", "rs_series.hip",
            "probe.hip", "dpt_api.cpp", "serve.cpp"]
 ARCH = "gfx950"
 

@@ -410,11 +410,18 @@ int ensure_f64(dpt_ctx *c) {
             DPT_TRY(launch_transpose_f64(c->dT64, c->d64, c->ld, c->stream));
         }
     }
-    for (int i = 0; i < 2; ++i)
-        if (!c->W64[i]) {
-            DPT_TRY(dalloc(&c->W64[i], (size_t)(c->ld * c->ld)));
-            DPT_TRY(launch_fill_zero(c->W64[i], sizeof(double) * (size_t)(c->ld * c->ld), c->stream));
+    if (!c->W64[0]) {  // both buffers, zeroed together (a failed second allocation releases the first)
+        DPT_TRY(dalloc(&c->W64[0], (size_t)(c->ld * c->ld)));
+        const hipError_t e = dalloc(&c->W64[1], (size_t)(c->ld * c->ld));
+        if (e != hipSuccess) {
+            dfree(c->W64[0]);
+            c->W64[0] = nullptr;
+            return map_err(e);
         }
+        void *zp[2] = {c->W64[0], c->W64[1]};
+        const size_t zb[2] = {sizeof(double) * (size_t)(c->ld * c->ld), sizeof(double) * (size_t)(c->ld * c->ld)};
+        DPT_TRY(launch_zero_many(zp, zb, 2, c->stream));
+    }
     return DPT_OK;
 }
 
@@ -612,12 +619,14 @@ bool small_batch_ok(const dpt_ctx *c) {
 // Up to kSmallBatch steps; *taken gets the number the controller consumed and
 // *act its last decision.  Every consumed step is counted in ctl and recorded
 // in r's history.
-// Steps to run speculatively: 4 at first, then the number the recent
-// contraction rate predicts until delta < tol (plus one), at most kSmallBatch.
-// The prediction only affects how many steps are computed and discarded.
+// Steps to run speculatively: a full batch at first (a step costs about a
+// microsecond at this size, a launch and read-back round trip 25-40), then the
+// number the recent contraction rate predicts until delta < tol (plus one), at
+// most kSmallBatch.  The prediction only affects how many steps are computed
+// and discarded.
 int small_batch_size(dpt_ctx *c, const Controller &ctl, int64_t consumed) {
     const int left = std::max(1, c->opt.max_iter - ctl.iters);
-    if (consumed < 3) return std::min(4, left);
+    if (consumed < 3) return std::min(kSmallBatch, left);
     double d1, d2, d3, w;
     stat_of(c, c->k - 1, &d1, &w);
     stat_of(c, c->k - 2, &d2, &w);
@@ -989,10 +998,14 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
     c->mem = p->mem;
     c->ld = p->format == DPT_CSR ? sparse_pad_order(p->n) : pad_order(p->n);
 
-    // theta: validate on the host, upload padded with zeros
+    // theta: validated on the host (device inputs are read back on the handle's
+    // stream), then placed on the device padded with zeros: a device-to-device
+    // copy for device inputs, one upload for host inputs
     std::vector<double> th((size_t)c->ld, 0.0);
     if (p->mem == DPT_MEM_DEVICE) {
-        if (hipMemcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost) != hipSuccess)
+        if (hipMemcpyAsync(th.data(), p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost, c->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
             return fail(DPT_EDEVICE);
         if (!theta_ok(th.data(), p->n)) return fail(DPT_EINVAL);
     } else {
@@ -1003,13 +1016,18 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
         return fail(DPT_ENOMEM);
     c->stats_host = new (std::nothrow) unsigned long long[2 * kStatRing];
     if (!c->stats_host) return fail(DPT_ENOMEM);
-    if (hipMemcpyAsync(c->theta, th.data(), sizeof(double) * (size_t)c->ld, hipMemcpyHostToDevice, c->stream) !=
-        hipSuccess)
-        return fail(DPT_EDEVICE);
-    if (launch_fill_zero(c->dvec, sizeof(double) * (size_t)c->ld, c->stream) != hipSuccess ||
-        launch_fill_zero(c->evec, sizeof(double) * (size_t)c->ld, c->stream) != hipSuccess ||
-        launch_zero_u64(c->stats, 2 * kStatRing, c->stream) != hipSuccess)
-        return fail(DPT_EDEVICE);
+    {
+        const bool dev = p->mem == DPT_MEM_DEVICE;
+        void *zp[4] = {c->dvec, c->evec, c->stats, c->theta + c->n};
+        const size_t zb[4] = {sizeof(double) * (size_t)c->ld, sizeof(double) * (size_t)c->ld,
+                              sizeof(unsigned long long) * 2 * kStatRing, sizeof(double) * (size_t)(c->ld - c->n)};
+        const int nz = dev && c->ld > c->n ? 4 : 3;  // the padding of a device-copied theta
+        if (launch_zero_many(zp, zb, nz, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->theta, dev ? p->theta : (const void *)th.data(),
+                           sizeof(double) * (size_t)(dev ? c->n : c->ld),
+                           dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return fail(DPT_EDEVICE);
+    }
 
     if (p->format == DPT_CSR) {
         rc = sparse_create(&c->sp, p, c->opt.precision == DPT_FP64, c->ld, c->stream);

@@ -46,6 +46,9 @@ struct StepArgs {
 // ---- dense kernels (kernels_dense.hip) -----------------------------------
 hipError_t launch_zero_u64(unsigned long long *p, int64_t count, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// Clears count (<= kZeroMany) buffers of bytes[i] (multiples of 4) in one launch.
+constexpr int kZeroMany = 8;
+hipError_t launch_zero_many(void *const *ptrs, const size_t *bytes, int count, hipStream_t s);
 
 // dst (ld x ld, Tdst) <- src (n x n row-major, Tsrc) with zero padding.
 hipError_t launch_pad_copy_f32_from_f32(float *dst, const float *src, int64_t n, int64_t ld, hipStream_t s);
@@ -74,6 +77,10 @@ hipError_t launch_copy_rows_f64(double *dst, const double *src, const int32_t *r
 // Tile height of the products when a row map is in use: the row list is
 // padded to a multiple of it (at most ld).
 inline int64_t row_tile(int64_t ld) { return ld % 128 == 0 ? 128 : 64; }
+// Large-tile FP64 step (kernels_gemm_f64.hip): ld a multiple of 128, ld >= 4096.
+bool step_f64_large_supported(int64_t ld);
+hipError_t launch_step_f64_large(const StepArgs &a, const double *W, const double *Delta, const double *deltaT,
+                                 double *Wn, hipStream_t s);
 // C[i][j] = sum_k A[i][k] B[j][k] for ld x ld FP64 operands (ld a multiple of 64).
 hipError_t launch_gemm_nt_f64(const double *A, const double *B, double *C, int64_t ld, hipStream_t s);
 // *flag |= 1 when src != src^T anywhere (bitwise).  flag must be zeroed first.

@@ -38,6 +38,19 @@ __global__ void k_fill_zero_u32(unsigned int *p, int64_t count) {
         p[i] = 0u;
 }
 
+// Up to kZeroMany buffers (word counts) cleared by one launch; blockIdx.y picks the buffer.
+struct ZeroMany {
+    unsigned int *p[kZeroMany];
+    int64_t words[kZeroMany];
+};
+
+__global__ void k_zero_many(ZeroMany z) {
+    unsigned int *p = z.p[blockIdx.y];
+    const int64_t cnt = z.words[blockIdx.y];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 __global__ void k_fill_zero_u32x4(uint4 *p, int64_t count) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -774,6 +787,20 @@ hipError_t launch_zero_u64(unsigned long long *p, int64_t count, hipStream_t s) 
     return hipGetLastError();
 }
 
+hipError_t launch_zero_many(void *const *ptrs, const size_t *bytes, int count, hipStream_t s) {
+    if (count < 1 || count > kZeroMany) return hipErrorInvalidValue;
+    ZeroMany z{};
+    int64_t most = 1;
+    for (int i = 0; i < count; ++i) {
+        if (bytes[i] % 4) return hipErrorInvalidValue;
+        z.p[i] = (unsigned int *)ptrs[i];
+        z.words[i] = (int64_t)(bytes[i] / 4);
+        most = std::max<int64_t>(most, z.words[i]);
+    }
+    hipLaunchKernelGGL(k_zero_many, dim3(grid_1d(most), (unsigned int)count), dim3(kThreads), 0, s, z);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
     if (bytes % 4) return hipErrorInvalidValue;
     if (bytes % 16 == 0 && ((uintptr_t)p & 15) == 0) {
@@ -929,6 +956,7 @@ hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta
 // 128-wide tiles leave CUs idle.
 hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT, double *Wn,
                            hipStream_t s) {
+    if (!a.rowmap && step_f64_large_supported(a.ld)) return launch_step_f64_large(a, W, Delta, deltaT, Wn, s);
     if ((a.ld >= 4096 || a.rowmap) && row_tile(a.ld) == 128)
         return launch_gemm<PolF64, 128, 128, 32, 4, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
     return launch_gemm<PolF64, 64, 64, 16, 2, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
