@@ -362,9 +362,14 @@ typedef struct dpt_serve_stats {
  * allocation) or DPT_EDEVICE. */
 int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg);
 
-/* Queue a dense problem given in host memory (DPT_MEM_HOST; copied before the
- * call returns, as FP32, into the staging ring when it takes at most half of
- * it: the call waits while the ring is full of not yet uploaded problems).
+/* Queue a dense problem.  DPT_MEM_HOST: theta and Delta are copied before the
+ * call returns (Delta as FP32), into the staging ring when they take at most
+ * half of it: the call waits while the ring is full of not yet uploaded
+ * problems.  DPT_MEM_DEVICE: theta is read back and checked during the call;
+ * theta and Delta (FP32 or FP64) are read on the server's stream when the
+ * problem is admitted, so they must be complete when the call is made and stay
+ * allocated and unchanged until the ticket's result has been polled; the
+ * transpose of Delta is always stored (its symmetry is not tested).
  * o->precision must be DPT_FP32 or DPT_BF16_FP32 (o may be NULL: defaults).
  * want_eigenvectors != 0 keeps Z for dpt_serve_poll.  Returns DPT_OK and a
  * ticket, DPT_EINVAL (bad problem, duplicate theta), DPT_ENOMEM (the problem

@@ -928,6 +928,11 @@ int compute_eigenvalues(dpt_ctx *c) {
 }  // namespace
 
 // ============================================================== C ABI
+namespace dpt {
+bool host_theta_ok(const double *theta, int64_t n) { return theta_ok(theta, n); }
+bool inputs_on_device(const dpt_problem *p) { return p->mem == DPT_MEM_DEVICE && device_inputs_ok(p, nullptr); }
+}  // namespace dpt
+
 extern "C" {
 
 void dpt_options_default(dpt_options *o) {

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dpt.h"
+
 namespace dpt {
 
 // stats slot layout: two u64 per step, holding the bit patterns of non-negative
@@ -196,6 +198,55 @@ struct GroupTable {
     int32_t prefix[kGroupLists][kServeMaxSlots + 1];
     GroupReq reqs[kServeMaxSlots];
 };
+
+// Admission of newly placed requests, one launch for all of them: the padded
+// FP32 Delta (and its BF16 copy, and its transpose unless DT is null: symmetric
+// problems alias DT to D), theta padded with zeros (when theta_src is not the
+// padded copy itself), and the closed-form first iterate F(I) with its BF16
+// shadow and statistics (skipped when W1 is null).  src is the n x n row-major
+// Delta (row stride n) in FP32 or FP64; theta_src has n entries; stat must be
+// zero.  Work items are the 64 x 64 tiles of each request's padded order.
+struct AdmitReq {
+    const void *src;
+    const double *theta_src;
+    double *theta;              // ld entries
+    float *D, *DT;              // DT null: symmetric (DT == D)
+    __bf16 *Db;                 // null: FP32 request
+    float *W1;                  // first iterate, or null
+    __bf16 *Wb1;                // its BF16 shadow, or null
+    unsigned long long *stat;   // 2 u64 (delta, max|W|), zero on entry
+    int64_t n, ld;
+    double lambda;
+    int32_t src_f64, pad_;
+};
+struct AdmitTable {
+    int32_t count, pad_;
+    int32_t prefix[kServeMaxSlots + 1];  // running sums of 64 x 64 tiles
+    AdmitReq reqs[kServeMaxSlots];
+};
+// Retirement, one launch for all finishing requests: E_n = theta_n + lambda d_n
+// of the current state into E (n entries per request) and the request's stats
+// cleared for the slot's next user.  One wave per (request, row).
+struct RetireReq {
+    const float *W, *D;
+    const double *theta;
+    double *E;
+    unsigned long long *stat;
+    int64_t n, ld;
+    double lambda;
+};
+struct RetireTable {
+    int32_t count, pad_;
+    int32_t prefix[kServeMaxSlots + 1];  // running sums of rows
+    RetireReq reqs[kServeMaxSlots];
+};
+hipError_t launch_group_admit(const AdmitTable *t, int grid, hipStream_t s);
+// Input checks shared with the single-problem entry points (dpt_api.cpp): theta
+// finite and pairwise distinct (host array); theta and Delta of a DPT_MEM_DEVICE
+// dense problem are device allocations.
+bool host_theta_ok(const double *theta, int64_t n);
+bool inputs_on_device(const dpt_problem *p);
+hipError_t launch_group_retire(const RetireTable *t, int grid, hipStream_t s);
 
 // Persistent grouped launches with a fixed grid (graph-capturable): the
 // pre-pass (also clears each request's stats) and the fused step for the

@@ -722,6 +722,96 @@ __global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict
     }
 }
 
+// Admission: one 64 x 64 tile (bi, bj) of one request per work item.  Thread t
+// owns column t & 63 and rows (t >> 6) + 4 k.  The source tile (rows bi, columns
+// bj) goes to D and Db in place and through LDS (pitch 65: conflict-free both
+// ways) to DT and the first iterate at tile (bj, bi): with state W = 0 the map
+// gives W1[p][q] = lambda Delta[q][p] / (theta_p - theta_q), the same quotient
+// as k_first_iterate.  Items of column tile 0 write the padded theta.
+__global__ __launch_bounds__(256) void k_group_admit(const AdmitTable *__restrict__ t) {
+    __shared__ float tile[64][65];
+    const int nreq = t->count;
+    const int total = nreq > 0 ? t->prefix[nreq] : 0;
+    const int col = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int r = find_segment(t->prefix, nreq, item);
+        const AdmitReq &q = t->reqs[r];
+        const int64_t n = q.n, ld = q.ld;
+        const int tpr = (int)(ld >> 6);
+        const int local = item - t->prefix[r];
+        const int bi = local / tpr, bj = local - bi * tpr;
+        const int64_t j = (int64_t)bj * 64 + col;
+        if (bj == 0 && r0 == 0 && q.theta != q.theta_src) {
+            const int64_t k = (int64_t)bi * 64 + col;
+            q.theta[k] = k < n ? q.theta_src[k] : 0.0;
+        }
+#pragma unroll 4
+        for (int k = 0; k < 16; ++k) {
+            const int rr = r0 + 4 * k;
+            const int64_t i = (int64_t)bi * 64 + rr;
+            float v = 0.0f;
+            if (i < n && j < n)
+                v = q.src_f64 ? (float)static_cast<const double *>(q.src)[i * n + j]
+                              : static_cast<const float *>(q.src)[i * n + j];
+            q.D[i * ld + j] = v;
+            if (q.Db) q.Db[i * ld + j] = (__bf16)v;
+            tile[rr][col] = v;
+        }
+        __syncthreads();
+        // transposed tile: position (p, qc) with p = bj*64 + rr, qc = bi*64 + col
+        const int64_t qc = (int64_t)bi * 64 + col;
+        const double th_q = qc < n ? q.theta_src[qc] : 0.0;
+        float amax = 0.0f;
+        bool bad = false;
+#pragma unroll 4
+        for (int k = 0; k < 16; ++k) {
+            const int rr = r0 + 4 * k;
+            const int64_t p = (int64_t)bj * 64 + rr, idx = p * ld + qc;
+            const float dt = tile[col][rr];
+            if (q.DT) q.DT[idx] = dt;
+            if (q.W1) {
+                float w = 0.0f;
+                if (p < n && qc < n && p != qc) w = gap_quotient<float>(q.lambda * (double)dt, q.theta_src[p], th_q);
+                q.W1[idx] = w;
+                if (q.Wb1) q.Wb1[idx] = (__bf16)w;
+                const float a = fabsf(w);
+                amax = a > amax ? a : amax;
+                bad |= !(a <= FLT_MAX);
+            }
+        }
+        if (q.W1) publish_stats_block(q.stat, (double)amax, (double)amax, bad);  // block-uniform
+        __syncthreads();  // the tile is reused by the block's next item
+    }
+}
+
+// Retirement: one wave per (request, row), the pre-pass sum in FP64 with the
+// fixed butterfly of k_group_prepass, then E_n = theta_n + lambda d_n; row 0
+// clears the request's stats.
+__global__ __launch_bounds__(256) void k_group_retire(const RetireTable *__restrict__ t) {
+    const int nreq = t->count;
+    const int total = nreq > 0 ? t->prefix[nreq] : 0;
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * 4;
+    for (int item = blockIdx.x * 4 + (threadIdx.x >> 6); item < total; item += nwaves) {
+        const int r = find_segment(t->prefix, nreq, item);
+        const RetireReq &q = t->reqs[r];
+        const int64_t row = item - t->prefix[r];
+        const float *w = q.W + row * q.ld;
+        const float *dl = q.D + row * q.ld;
+        double sum = 0.0;
+        for (int64_t k = lane; k < q.n; k += 64) sum += (double)w[k] * (double)dl[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+        if (lane == 0) {
+            q.E[row] = q.theta[row] + q.lambda * ((double)dl[row] + sum);
+            if (row == 0) {
+                q.stat[0] = 0ull;
+                q.stat[1] = 0ull;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ export
 template <typename TW, typename TO>
 __global__ void k_export(const TW *__restrict__ W, int64_t n, int64_t ld, TO *__restrict__ out) {
@@ -1062,6 +1152,16 @@ hipError_t launch_group_step(const GroupTable *t, int phase, int tile, int grid,
         hipLaunchKernelGGL((k_group_step<PH_FP32, 128>), dim3((unsigned int)grid), dim3(256), 0, s, t);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_group_admit(const AdmitTable *t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_admit, dim3((unsigned int)grid), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_retire(const RetireTable *t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_retire, dim3((unsigned int)grid), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

@@ -3,16 +3,21 @@
 // A worker thread owns one stream, a device arena of the configured budget
 // and a slot table.  Each engine step:
 //   1. admits waiting problems in FIFO order while the arena and the slots have
-//      room (upload, padded FP32/BF16 copies, transpose when unsymmetric);
-//   2. applies the map of eq. (dyn) (Kenmoe, Smerlak, Zadorin, arXiv:2002.12872,
-//      Sec. II.B) once to every admitted problem: the closed-form first iterate
-//      for new ones, then one persistent grouped pre-pass and one persistent
-//      grouped fused step per precision phase over a device work table (the
-//      three launches are a HIP graph replayed every step);
+//      room: one upload per host-submitted problem (theta and Delta staged
+//      together in a pinned ring), none for device-resident ones, then one
+//      grouped launch for all of them (padded FP32/BF16 copies, transpose, and
+//      the closed-form first iterate of eq. (dyn) of Kenmoe, Smerlak, Zadorin,
+//      arXiv:2002.12872, Sec. II.B);
+//   2. applies the map once to every other admitted problem: one persistent
+//      grouped pre-pass and one persistent grouped fused step per precision
+//      phase and tile shape over a device work table (a HIP graph replayed
+//      every step);
 //   3. reads every problem's (delta, max|W|) back and runs its own controller
 //      (the same stopping rule as dpt_solve);
-//   4. retires finished problems (eigenvalues and optional eigenvectors copied
-//      out), releasing their arena space for the next admissions.
+//   4. retires finished problems with one grouped launch (eigenvalues into a
+//      staging buffer, optional eigenvectors exported), releasing their arena
+//      space at once; their results are handed out after the next
+//      synchronisation of the stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +30,7 @@
 #include <cstddef>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -88,14 +94,20 @@ struct Request {
     double lambda = 0.0;
     dpt_options opt{};
     bool bf16 = false, symmetric = false, want_z = false;
-    std::vector<double> theta;  // ld entries (zero padded)
-    std::vector<float> delta;   // n*n row-major when it does not fit the pinned ring
-    float *delta_pinned = nullptr;  // n*n row-major in the pinned ring, until uploaded
+    // host submissions: theta (padded to ld) followed by the FP32 Delta (n*n
+    // row-major) in the pinned ring until uploaded, else in the two vectors
+    std::vector<double> theta;
+    std::vector<float> delta;
+    unsigned char *staged = nullptr;
     size_t ring_off = 0;
+    // device submissions: the caller's arrays, read at admission
+    const double *dev_theta = nullptr;
+    const void *dev_delta = nullptr;
+    bool dev_f64 = false;
     // device memory inside the arena
     size_t off = 0, bytes = 0;
     int slot = -1;
-    double *theta_d = nullptr, *d_d = nullptr, *e_d = nullptr;
+    double *theta_d = nullptr, *d_d = nullptr;
     float *W[2] = {nullptr, nullptr}, *D = nullptr, *DT = nullptr;
     __bf16 *Wb[2] = {nullptr, nullptr}, *Db = nullptr;
     int cur = 0;
@@ -158,10 +170,14 @@ struct PinnedRing {
     }
 };
 
+// Bytes of theta padded to ld: the staged block is theta, then Delta, and the
+// arena places W[0] right after theta, so one copy lands both.
+size_t theta_bytes(int64_t ld) { return round_up((size_t)ld * 8); }
+
 size_t request_bytes(int64_t ld, bool bf16, bool symmetric) {
     const size_t l = (size_t)ld, l2 = l * l;
-    size_t b = 3 * round_up(l * 8);          // theta, d, E
-    b += round_up(2 * l2 * 4);               // W[0], W[1] (W[1] doubles as upload staging)
+    size_t b = round_up(l * 8) + theta_bytes(ld);  // d, theta
+    b += round_up(2 * l2 * 4);               // W[0] (doubles as upload staging), W[1]
     b += round_up(l2 * 4);                   // D
     if (!symmetric) b += round_up(l2 * 4);   // D^T
     if (bf16) b += round_up(2 * l2 * 2) + round_up(l2 * 2);  // Wb[0..1], Db
@@ -170,6 +186,116 @@ size_t request_bytes(int64_t ld, bool bf16, bool symmetric) {
 
 double now_s(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// A few host threads that stage submitted matrices together with the calling
+// thread: a job is a number of parts, each run once.  One job at a time
+// (concurrent submitters queue); a job returns only when every part is done and
+// no pool thread is still inside it.
+class StagePool {
+  public:
+    ~StagePool() { stop(); }
+    void start(int threads) {
+        for (int i = 0; i < threads; ++i) th_.emplace_back([this] { loop(); });
+    }
+    void stop() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            quit_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_)
+            if (t.joinable()) t.join();
+        th_.clear();
+    }
+    void run(int parts, const std::function<void(int)> &f) {
+        std::lock_guard<std::mutex> jl(job_mu_);
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_done_.wait(lk, [&] { return active_ == 0; });
+            f_ = &f;
+            parts_ = parts;
+            next_.store(0);
+            done_ = 0;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_done_.wait(lk, [&] { return done_ == parts_ && active_ == 0; });
+        f_ = nullptr;
+    }
+
+  private:
+    void work() {
+        int mine = 0;
+        for (;;) {
+            const int k = next_.fetch_add(1);
+            if (k >= parts_) break;
+            (*f_)(k);
+            ++mine;
+        }
+        if (mine) {
+            std::lock_guard<std::mutex> lk(mu_);
+            done_ += mine;
+        }
+        cv_done_.notify_all();
+    }
+    void loop() {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_.wait(lk, [&] { return quit_ || gen_ != seen; });
+            if (quit_) return;
+            seen = gen_;
+            ++active_;
+            lk.unlock();
+            work();
+            lk.lock();
+            --active_;
+            cv_done_.notify_all();
+        }
+    }
+
+    std::vector<std::thread> th_;
+    std::mutex job_mu_, mu_;
+    std::condition_variable cv_, cv_done_;
+    const std::function<void(int)> *f_ = nullptr;
+    int parts_ = 0, done_ = 0, active_ = 0;
+    std::atomic<int> next_{0};
+    uint64_t gen_ = 0;
+    bool quit_ = false;
+};
+
+// dst = (float) src (n x n) and whether the FP32 values are exactly symmetric,
+// by block rows of 64: part b converts rows [64 b, 64 b + 64) in order (dst is
+// pinned staging memory, best written sequentially) and compares its 64 x 64
+// blocks at and right of the diagonal with their mirrors on the caller's
+// (cached) array, until some part has found a mismatch.  Large matrices use
+// the pool; parts touch disjoint rows of dst.
+template <typename T>
+bool stage_and_test(const T *src, int64_t n, float *dst, StagePool *pool) {
+    std::atomic<bool> asym{false};
+    const int parts = (int)((n + 63) / 64);
+    const std::function<void(int)> part = [&](int b) {
+        const int64_t bi = 64 * (int64_t)b, ie = std::min(bi + 64, n);
+        for (int64_t i = bi * n; i < ie * n; ++i) dst[i] = (float)src[i];
+        for (int64_t bj = bi; bj < n && !asym.load(std::memory_order_relaxed); bj += 64) {
+            const int64_t je = std::min(bj + 64, n);
+            for (int64_t i = bi; i < ie; ++i)
+                for (int64_t j = std::max(bj, i + 1); j < je; ++j)
+                    if ((float)src[i * n + j] != (float)src[j * n + i]) {
+                        asym.store(true, std::memory_order_relaxed);
+                        return;
+                    }
+        }
+    };
+    if (pool && n >= 256) {
+        pool->run(parts, part);
+    } else {
+        for (int b = 0; b < parts; ++b) part(b);
+    }
+    return !asym.load();
 }
 
 }  // namespace
@@ -183,7 +309,17 @@ struct dpt_server_ctx {
     Arena arena;
     size_t arena_used = 0;
     GroupTable *table_h = nullptr, *table_d = nullptr;
+    AdmitTable *admit_h = nullptr, *admit_d = nullptr;
+    RetireTable *retire_h = nullptr, *retire_d = nullptr;
     unsigned long long *stats_d = nullptr, *stats_h = nullptr;
+    // eigenvalues of retiring requests: device staging and its pinned mirror
+    double *e_stage_d = nullptr, *e_stage_h = nullptr;
+    size_t e_stage_cap = 0;  // doubles
+    // device submissions: theta is read back for validation on a stream of its own
+    hipStream_t submit_stream = nullptr;
+    std::mutex submit_mu;
+    StagePool stage_pool;  // host staging of submitted matrices
+    static constexpr int kStageThreads = 4;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::chrono::steady_clock::time_point t0;
@@ -206,6 +342,8 @@ struct dpt_server_ctx {
     std::unordered_map<int64_t, Request *> done;    // guarded by mu
     std::unordered_map<int64_t, int> live;          // ticket -> 1 (guarded by mu)
     std::vector<Request *> active;                  // worker only
+    std::vector<std::pair<Request *, size_t>> retiring;  // worker only: (request, E offset), copies in flight
+    std::vector<Request *> zero_w0;                 // worker only: admitted at their iteration cap
     std::vector<int> free_slots;                    // worker only
     int64_t next_id = 0;
     bool stop = false;
@@ -218,14 +356,22 @@ struct dpt_server_ctx {
         if (graph) (void)hipGraphDestroy(graph);
         if (arena_base) (void)hipFree(arena_base);
         if (table_d) (void)hipFree(table_d);
+        if (admit_d) (void)hipFree(admit_d);
+        if (retire_d) (void)hipFree(retire_d);
         if (stats_d) (void)hipFree(stats_d);
+        if (e_stage_d) (void)hipFree(e_stage_d);
         if (table_h) (void)hipHostFree(table_h);
+        if (admit_h) (void)hipHostFree(admit_h);
+        if (retire_h) (void)hipHostFree(retire_h);
         if (stats_h) (void)hipHostFree(stats_h);
+        if (e_stage_h) (void)hipHostFree(e_stage_h);
         if (ring.base) (void)hipHostFree(ring.base);
+        if (submit_stream) (void)hipStreamDestroy(submit_stream);
         if (stream && own_stream) (void)hipStreamDestroy(stream);
         for (auto *r : pending) delete r;
         for (auto &kv : done) delete kv.second;
         for (auto *r : active) delete r;
+        for (auto &rp : retiring) delete rp.first;
     }
 
     // ------------------------------------------------------------ worker
@@ -335,7 +481,9 @@ struct dpt_server_ctx {
         return e;
     }
 
-    hipError_t admit_one(Request *r, size_t off) {
+    // Places r in the arena at off, enqueues its upload (host submissions) and
+    // writes its entry of the admission table (index k).
+    hipError_t admit_one(Request *r, size_t off, int k) {
         r->off = off;
         r->bytes = request_bytes(r->ld, r->bf16, r->symmetric);
         r->slot = free_slots.back();
@@ -347,10 +495,9 @@ struct dpt_server_ctx {
             p += round_up(bytes);
             return q;
         };
-        r->theta_d = (double *)take(l * 8);
         r->d_d = (double *)take(l * 8);
-        r->e_d = (double *)take(l * 8);
-        float *wpair = (float *)take(2 * l2 * 4);
+        r->theta_d = (double *)take(theta_bytes(r->ld));
+        float *wpair = (float *)take(2 * l2 * 4);  // directly after theta
         r->W[0] = wpair;
         r->W[1] = wpair + l2;
         r->D = (float *)take(l2 * 4);
@@ -361,45 +508,58 @@ struct dpt_server_ctx {
             r->Wb[1] = bpair + l2;
             r->Db = (__bf16 *)take(l2 * 2);
         }
-        hipError_t e = hipMemcpyAsync(r->theta_d, r->theta.data(), l * 8, hipMemcpyHostToDevice, stream);
-        const float *src = r->delta_pinned ? r->delta_pinned : r->delta.data();
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(r->W[1], src, (size_t)(r->n * r->n) * 4, hipMemcpyHostToDevice, stream);
-        if (r->delta_pinned) {  // its ring space is given back once the stream is idle
+        const size_t nn = (size_t)(r->n * r->n);
+        hipError_t e = hipSuccess;
+        if (r->staged) {  // theta then Delta in one copy; the ring space is given back once the stream is idle
+            e = hipMemcpyAsync(r->theta_d, r->staged, theta_bytes(r->ld) + nn * 4, hipMemcpyHostToDevice, stream);
             staged.push_back(r->ring_off);
-            r->delta_pinned = nullptr;
+            r->staged = nullptr;
             idle_since_staged = false;
+        } else if (!r->dev_delta) {
+            e = hipMemcpyAsync(r->theta_d, r->theta.data(), l * 8, hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(r->W[0], r->delta.data(), nn * 4, hipMemcpyHostToDevice, stream);
         }
-        if (e == hipSuccess) e = launch_pad_copy_f32_from_f32(r->D, r->W[1], r->n, r->ld, stream);
-        if (e == hipSuccess && !r->symmetric) e = launch_transpose_f32(r->DT, r->D, r->ld, stream);
-        if (e == hipSuccess && r->bf16) e = launch_cvt_f32_to_bf16(r->Db, r->D, (int64_t)l2, stream);
-        // W[0] is the state at the identity (read if the request retires without
-        // a step); W[1] and the BF16 shadows are written in full by the first
-        // iterate and the first step before anything reads them
-        if (e == hipSuccess) e = launch_fill_zero(r->W[0], l2 * 4, stream);
-        if (e == hipSuccess) e = launch_fill_zero(r->d_d, l * 8, stream);
         r->ctl.start(r->opt, r->bf16 ? PH_BF16 : PH_FP32, false);
+        const bool capped = r->ctl.capped();  // retires at the identity: W[0] is cleared after the launch
+        if (capped) zero_w0.push_back(r);
+        AdmitReq &q = admit_h->reqs[k];
+        q.src = r->dev_delta ? r->dev_delta : (const void *)r->W[0];
+        q.src_f64 = r->dev_delta && r->dev_f64 ? 1 : 0;
+        q.theta_src = r->dev_delta ? r->dev_theta : r->theta_d;
+        q.theta = r->theta_d;
+        q.D = r->D;
+        q.DT = r->symmetric ? nullptr : r->DT;
+        q.Db = r->bf16 ? r->Db : nullptr;
+        q.W1 = capped ? nullptr : r->W[1];
+        q.Wb1 = capped || !r->bf16 ? nullptr : r->Wb[1];
+        q.stat = stats_d + 2 * r->slot;
+        q.n = r->n;
+        q.ld = r->ld;
+        q.lambda = r->lambda;
+        admit_h->prefix[k + 1] = admit_h->prefix[k] + (int32_t)((r->ld / 64) * (r->ld / 64));
         r->t_admit = now_s(t0);
         return e;
     }
 
     hipError_t admit() {
-        for (;;) {
+        int k = 0;
+        admit_h->prefix[0] = 0;
+        hipError_t e = hipSuccess;
+        while (e == hipSuccess && !free_slots.empty()) {
             Request *r;
             {
                 std::lock_guard<std::mutex> lk(mu);
-                if (pending.empty()) return hipSuccess;
+                if (pending.empty()) break;
                 r = pending.front();
             }
-            if (free_slots.empty()) return hipSuccess;
             size_t off;
-            if (!arena.alloc(request_bytes(r->ld, r->bf16, r->symmetric), &off)) return hipSuccess;  // FIFO
+            if (!arena.alloc(request_bytes(r->ld, r->bf16, r->symmetric), &off)) break;  // FIFO
             {
                 std::lock_guard<std::mutex> lk(mu);
                 pending.pop_front();
                 st.pending = (int64_t)pending.size();
             }
-            hipError_t e = admit_one(r, off);
+            e = admit_one(r, off, k++);
             active.push_back(r);
             arena_used += r->bytes;
             {
@@ -408,8 +568,17 @@ struct dpt_server_ctx {
                 st.peak_active = std::max<int64_t>(st.peak_active, (int64_t)active.size());
                 st.active = (int64_t)active.size();
             }
-            if (e != hipSuccess) return e;
         }
+        if (e == hipSuccess && k > 0) {
+            admit_h->count = k;
+            e = hipMemcpyAsync(admit_d, admit_h, offsetof(AdmitTable, reqs) + (size_t)k * sizeof(AdmitReq),
+                               hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = launch_group_admit(admit_d, grid, stream);
+        }
+        for (Request *r : zero_w0)
+            if (e == hipSuccess) e = launch_fill_zero(r->W[0], (size_t)(r->ld * r->ld) * 4, stream);
+        zero_w0.clear();
+        return e;
     }
 
     bool finished(const Request *r) const {
@@ -421,14 +590,11 @@ struct dpt_server_ctx {
         int nreq = 0;
         int cnt[kGroupLists] = {};
         int32_t rows = 0, tiles_sum[kGroupLists] = {};
-        std::vector<Request *> first, stepping;
+        std::vector<Request *> stepping;
         for (Request *r : active) {
             if (finished(r)) continue;  // e.g. max_iter = 0: retired without a step
             stepping.push_back(r);
-            if (r->at_identity) {
-                first.push_back(r);
-                continue;
-            }
+            if (r->at_identity) continue;
             const int nx = r->cur ^ 1;
             const bool bf = r->ctl.phase == PH_BF16;
             GroupReq &g = t.reqs[nreq];
@@ -460,20 +626,9 @@ struct dpt_server_ctx {
             t.prefix[L][cnt[L]] = tiles_sum[L];
             t.counts[1 + L] = cnt[L];
         }
+        // requests at the identity took their first iterate in the admission launch
         hipError_t e = hipSuccess;
-        for (Request *r : first) {
-            StepArgs a;
-            a.n = r->n;
-            a.ld = r->ld;
-            a.lambda = r->lambda;
-            a.theta = r->theta_d;
-            a.d = r->d_d;
-            a.stat = stats_d + 2 * r->slot;
-            if (e == hipSuccess) e = launch_zero_u64(a.stat, 2, stream);
-            if (e == hipSuccess)
-                e = launch_first_iterate_f32(a, r->DT, r->W[1], r->bf16 ? r->Wb[1] : nullptr, stream);
-        }
-        if (e == hipSuccess && nreq > 0) {
+        if (nreq > 0) {
             e = hipMemcpyAsync(table_d, table_h, offsetof(GroupTable, reqs) + (size_t)nreq * sizeof(GroupReq),
                                hipMemcpyHostToDevice, stream);
             if (e == hipSuccess) e = launch_grouped();
@@ -484,6 +639,7 @@ struct dpt_server_ctx {
         if (e == hipSuccess) idle_since_staged = true;
         if (e != hipSuccess) return e;
         const double t_now = now_s(t0);
+        hand_out(t_now);
         for (Request *r : stepping) {
             r->cur ^= 1;
             if (r->at_identity) {
@@ -502,53 +658,101 @@ struct dpt_server_ctx {
         return hipSuccess;
     }
 
+    // Enqueues the retirement of every finished request: one grouped launch for
+    // their eigenvalues (into the staging buffer) and stats, one copy of the
+    // staging buffer to its pinned mirror, and the optional eigenvector exports.
+    // Their arena space and slots are free at once (stream order protects them);
+    // the results are handed out after the stream's next synchronisation.  The
+    // stream is idle when this is called.
     hipError_t retire() {
         std::vector<Request *> out;
         for (Request *r : active)
             if (finished(r)) out.push_back(r);
         if (out.empty()) return hipSuccess;
+        size_t need = 0;
+        for (Request *r : out) need += (size_t)r->n;
         hipError_t e = hipSuccess;
+        if (need > e_stage_cap) {  // grow (nothing is in flight on the staging buffers)
+            if (e_stage_d) (void)hipFree(e_stage_d);
+            if (e_stage_h) (void)hipHostFree(e_stage_h);
+            e_stage_d = e_stage_h = nullptr;
+            e_stage_cap = 0;
+            const size_t cap = std::max<size_t>(need, (size_t)1 << 16);
+            e = hipMalloc((void **)&e_stage_d, cap * 8);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&e_stage_h, cap * 8, 0);
+            if (e != hipSuccess) return e;
+            e_stage_cap = cap;
+        }
+        RetireTable &t = *retire_h;
+        t.prefix[0] = 0;
+        size_t eoff = 0;
+        for (size_t k = 0; k < out.size(); ++k) {
+            Request *r = out[k];
+            RetireReq &q = t.reqs[k];
+            q.W = r->W[r->cur];
+            q.D = r->D;
+            q.theta = r->theta_d;
+            q.E = e_stage_d + eoff;
+            q.stat = stats_d + 2 * r->slot;
+            q.n = r->n;
+            q.ld = r->ld;
+            q.lambda = r->lambda;
+            t.prefix[k + 1] = t.prefix[k] + (int32_t)r->n;
+            retiring.emplace_back(r, eoff);
+            eoff += (size_t)r->n;
+        }
+        t.count = (int32_t)out.size();
+        e = hipMemcpyAsync(retire_d, retire_h, offsetof(RetireTable, reqs) + out.size() * sizeof(RetireReq),
+                           hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = launch_group_retire(retire_d, grid, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(e_stage_h, e_stage_d, eoff * 8, hipMemcpyDeviceToHost, stream);
         for (Request *r : out) {
-            StepArgs a;
-            a.n = r->n;
-            a.ld = r->ld;
-            a.lambda = r->lambda;
-            a.theta = r->theta_d;
-            a.d = r->d_d;
-            a.stat = nullptr;
-            r->E.resize((size_t)r->n);
-            if (e == hipSuccess) e = launch_prepass_f32_f32(r->W[r->cur], r->D, a, r->d_d, r->e_d, nullptr, stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(r->E.data(), r->e_d, (size_t)r->n * 8, hipMemcpyDeviceToHost, stream);
-            if (r->want_z) {
+            if (r->want_z && e == hipSuccess) {
                 r->Z.resize((size_t)(r->n * r->n));
                 float *staging = r->W[r->cur ^ 1];
-                if (e == hipSuccess) e = launch_export_f32(r->W[r->cur], r->n, r->ld, staging, 0, stream);
+                e = launch_export_f32(r->W[r->cur], r->n, r->ld, staging, 0, stream);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(r->Z.data(), staging, r->Z.size() * 4, hipMemcpyDeviceToHost, stream);
             }
-        }
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e == hipSuccess) idle_since_staged = true;
-        const double t_now = now_s(t0);
-        for (Request *r : out) {
             arena.release(r->off, r->bytes);
             arena_used -= r->bytes;
             free_slots.push_back(r->slot);
             r->slot = -1;
-            r->t_finish = t_now;
             r->status = r->ctl.status;
-            std::vector<float>().swap(r->delta);
             active.erase(std::find(active.begin(), active.end(), r));
         }
         {
             std::lock_guard<std::mutex> lk(mu);
-            for (Request *r : out) done[r->id] = r;
-            st.completed += (int64_t)out.size();
             st.active = (int64_t)active.size();
         }
-        cv_done.notify_all();
         return e;
+    }
+
+    // After a synchronisation of the stream: the retirements enqueued before it
+    // are complete; copy their eigenvalues out and hand them to the pollers.
+    void hand_out(double t_now) {
+        if (retiring.empty()) return;
+        for (auto &rp : retiring) {
+            Request *r = rp.first;
+            r->E.assign(e_stage_h + rp.second, e_stage_h + rp.second + r->n);
+            r->t_finish = t_now;
+            std::vector<float>().swap(r->delta);
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto &rp : retiring) done[rp.first->id] = rp.first;
+            st.completed += (int64_t)retiring.size();
+        }
+        retiring.clear();
+        cv_done.notify_all();
+    }
+
+    hipError_t finish_retiring() {
+        const hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        idle_since_staged = true;
+        hand_out(now_s(t0));
+        return hipSuccess;
     }
 
     // The uploads of the requests admitted so far have completed once the stream
@@ -577,6 +781,11 @@ struct dpt_server_ctx {
             done[r->id] = r;
         }
         active.clear();
+        for (auto &rp : retiring) {
+            rp.first->status = code;
+            done[rp.first->id] = rp.first;
+        }
+        retiring.clear();
         for (Request *r : pending) {
             r->status = code;
             done[r->id] = r;
@@ -590,7 +799,7 @@ struct dpt_server_ctx {
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(mu);
-                if (active.empty() && pending.empty()) {
+                if (active.empty() && pending.empty() && retiring.empty()) {
                     if (stop) break;
                     cv_work.wait_for(lk, std::chrono::milliseconds(2));
                     continue;
@@ -598,7 +807,9 @@ struct dpt_server_ctx {
             }
             const auto t_begin = std::chrono::steady_clock::now();
             hipError_t e = admit();
-            if (e == hipSuccess && !active.empty()) e = step();
+            const bool any_step = std::any_of(active.begin(), active.end(), [&](Request *r) { return !finished(r); });
+            if (e == hipSuccess && any_step) e = step();  // synchronises and hands out earlier retirements
+            else if (e == hipSuccess) e = finish_retiring();
             if (e == hipSuccess) e = retire();
             if (e == hipSuccess && !staged.empty()) e = release_staged();
             {
@@ -614,27 +825,6 @@ struct dpt_server_ctx {
     }
 };
 
-namespace {
-// dst = (float) src (n x n), written in order (dst is pinned staging memory:
-// write-combined, slow to read and to write out of order), and whether the FP32
-// values are exactly symmetric, tested on the caller's cached array over 64 x 64
-// blocks with their mirrors (stops at the first mismatch).
-template <typename T>
-bool stage_and_test(const T *src, int64_t n, float *dst) {
-    const size_t nn = (size_t)(n * n);
-    for (size_t i = 0; i < nn; ++i) dst[i] = (float)src[i];
-    for (int64_t bi = 0; bi < n; bi += 64) {
-        const int64_t ie = std::min(bi + 64, n);
-        for (int64_t bj = bi; bj < n; bj += 64) {
-            const int64_t je = std::min(bj + 64, n);
-            for (int64_t i = bi; i < ie; ++i)
-                for (int64_t j = std::max(bj, i + 1); j < je; ++j)
-                    if ((float)src[i * n + j] != (float)src[j * n + i]) return false;
-        }
-    }
-    return true;
-}
-}  // namespace
 
 extern "C" {
 
@@ -660,7 +850,12 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     }
     if (e == hipSuccess) e = hipMalloc((void **)&c->arena_base, (size_t)cfg->budget_bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&c->table_d, sizeof(GroupTable));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->admit_d, sizeof(AdmitTable));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->retire_d, sizeof(RetireTable));
     if (e == hipSuccess) e = hipMalloc((void **)&c->stats_d, 16 * (size_t)cfg->max_slots);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->submit_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->admit_h, sizeof(AdmitTable), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->retire_h, sizeof(RetireTable), 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->table_h, sizeof(GroupTable), 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->stats_h, 16 * (size_t)cfg->max_slots, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->ring.base, dpt_server_ctx::kRingBytes, 0);
@@ -669,6 +864,10 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
         std::memset(c->table_h, 0, sizeof(GroupTable));
         e = hipMemcpy(c->table_d, c->table_h, sizeof(GroupTable), hipMemcpyHostToDevice);
     }
+    // every slot's stats start at zero (the admission launch publishes into them;
+    // retirement clears them again)
+    if (e == hipSuccess) e = launch_zero_u64(c->stats_d, 2 * (int64_t)cfg->max_slots, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess && cfg->autotune) e = c->autotune();  // fixes the launches the graph holds
     if (e == hipSuccess && cfg->use_graph) {
         e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
@@ -688,6 +887,7 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     c->st.tile128_min_ld[1] = c->min_ld_128[1] == INT64_MAX ? -1 : c->min_ld_128[1];
     c->arena.init((size_t)cfg->budget_bytes);
     for (int i = cfg->max_slots - 1; i >= 0; --i) c->free_slots.push_back(i);
+    c->stage_pool.start(dpt_server_ctx::kStageThreads);
     c->worker = std::thread([c] { c->run(); });
     *srv = c;
     return DPT_OK;
@@ -698,7 +898,9 @@ int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o,
                      int64_t *ticket) {
     if (!srv || !ticket) return DPT_EINVAL;
     if (dpt_validate(p, o) != DPT_OK) return DPT_EINVAL;
-    if (p->format != DPT_DENSE || p->mem != DPT_MEM_HOST) return DPT_EINVAL;
+    if (p->format != DPT_DENSE) return DPT_EINVAL;
+    const bool dev = p->mem == DPT_MEM_DEVICE;
+    if (dev && !inputs_on_device(p)) return DPT_EINVAL;
     dpt_options opt;
     if (o) {
         opt = *o;
@@ -722,53 +924,101 @@ int dpt_serve_submit(dpt_server srv, const dpt_problem *p, const dpt_options *o,
         delete r;
         return DPT_ENOMEM;
     }
-    // Delta goes to the pinned ring (waiting for space while earlier submissions
-    // are uploaded) unless it takes more than half of it
-    float *dst = nullptr;
-    if (nn * 4 <= srv->ring.cap / 2) {
-        std::unique_lock<std::mutex> lk(srv->ring_mu);
-        size_t off = 0;
-        srv->cv_ring.wait(lk, [&] { return srv->closing.load() || srv->ring.alloc(nn * 4, &off); });
-        if (srv->closing.load()) {
-            delete r;
-            return DPT_ESTATE;
-        }
-        dst = (float *)(srv->ring.base + off);
-        r->delta_pinned = dst;
-        r->ring_off = off;
-    }
-    // an early return from here on gives the ring space back
-    auto drop = [&](int code) {
-        if (r->delta_pinned) {
-            {
-                std::lock_guard<std::mutex> lk(srv->ring_mu);
-                srv->ring.release(r->ring_off);
+    if (dev) {
+        // Device arrays are read by the worker at admission (the caller keeps them
+        // unchanged until the result is polled); theta is checked here.  The
+        // transpose is always stored (symmetry is not tested on the device).
+        std::vector<double> th((size_t)p->n);
+        {
+            std::lock_guard<std::mutex> lk(srv->submit_mu);
+            if (hipMemcpyAsync(th.data(), p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost,
+                               srv->submit_stream) != hipSuccess ||
+                hipStreamSynchronize(srv->submit_stream) != hipSuccess) {
+                delete r;
+                return DPT_EDEVICE;
             }
-            srv->cv_ring.notify_all();
         }
-        delete r;
-        return code;
-    };
-    try {
-        r->theta.assign((size_t)r->ld, 0.0);
-        if (!dst) r->delta.resize(nn);
-    } catch (...) {
-        return drop(DPT_ENOMEM);
+        if (!host_theta_ok(th.data(), p->n)) {
+            delete r;
+            return DPT_EINVAL;
+        }
+        r->dev_theta = (const double *)p->theta;
+        r->dev_delta = p->delta;
+        r->dev_f64 = p->dtype == DPT_DTYPE_F64;
+        r->symmetric = false;
+        if (request_bytes(r->ld, r->bf16, false) > (size_t)srv->cfg.budget_bytes) {
+            delete r;
+            return DPT_ENOMEM;
+        }
+    } else {
+        // theta (padded) and the FP32 Delta go to the pinned ring as one block
+        // (waiting for space while earlier submissions are uploaded) unless the
+        // block takes more than half of it
+        const size_t tb = theta_bytes(r->ld), block = tb + nn * 4;
+        unsigned char *blk = nullptr;
+        if (block <= srv->ring.cap / 2) {
+            std::unique_lock<std::mutex> lk(srv->ring_mu);
+            size_t off = 0;
+            srv->cv_ring.wait(lk, [&] { return srv->closing.load() || srv->ring.alloc(block, &off); });
+            if (srv->closing.load()) {
+                delete r;
+                return DPT_ESTATE;
+            }
+            blk = srv->ring.base + off;
+            r->staged = blk;
+            r->ring_off = off;
+        }
+        // an early return from here on gives the ring space back
+        auto drop = [&](int code) {
+            if (r->staged) {
+                {
+                    std::lock_guard<std::mutex> lk(srv->ring_mu);
+                    srv->ring.release(r->ring_off);
+                }
+                srv->cv_ring.notify_all();
+            }
+            delete r;
+            return code;
+        };
+        double *th = nullptr;
+        float *dst = nullptr;
+        if (blk) {
+            th = (double *)blk;
+            dst = (float *)(blk + tb);
+        } else {
+            try {
+                r->theta.assign((size_t)r->ld, 0.0);
+                r->delta.resize(nn);
+            } catch (...) {
+                return drop(DPT_ENOMEM);
+            }
+            th = r->theta.data();
+            dst = r->delta.data();
+        }
+        std::memcpy(th, p->theta, sizeof(double) * (size_t)p->n);
+        for (int64_t i = p->n; i < r->ld; ++i) th[i] = 0.0;
+        // FP32 copy into the staging block; symmetry of the FP32 values tested on
+        // the caller's array (not on the pinned copy).
+        const bool sym = p->dtype == DPT_DTYPE_F64
+                             ? stage_and_test<double>((const double *)p->delta, p->n, dst, &srv->stage_pool)
+                             : stage_and_test<float>((const float *)p->delta, p->n, dst, &srv->stage_pool);
+        r->symmetric = sym;
+        if (request_bytes(r->ld, r->bf16, r->symmetric) > (size_t)srv->cfg.budget_bytes) return drop(DPT_ENOMEM);
     }
-    if (!dst) dst = r->delta.data();
-    std::memcpy(r->theta.data(), p->theta, sizeof(double) * (size_t)p->n);
-    // FP32 copy into the staging ring; symmetry of the FP32 values tested on the
-    // caller's array (not on the pinned copy).
-    const bool sym = p->dtype == DPT_DTYPE_F64 ? stage_and_test<double>((const double *)p->delta, p->n, dst)
-                                               : stage_and_test<float>((const float *)p->delta, p->n, dst);
-    r->symmetric = sym;
-    if (request_bytes(r->ld, r->bf16, r->symmetric) > (size_t)srv->cfg.budget_bytes) return drop(DPT_ENOMEM);
     {
         std::unique_lock<std::mutex> lk(srv->mu);
         if (srv->stop || srv->error != DPT_OK) {
             const int code = srv->error != DPT_OK ? srv->error : DPT_ESTATE;
             lk.unlock();
-            return drop(code);
+            if (r->staged) {
+                {
+                    std::lock_guard<std::mutex> lr(srv->ring_mu);
+                    srv->ring.release(r->ring_off);
+                }
+                srv->cv_ring.notify_all();
+            }
+            delete r;
+            return code;
         }
         r->id = srv->next_id++;
         r->t_submit = now_s(srv->t0);

@@ -524,19 +524,22 @@ def dpt_serve_open(budget_bytes, max_slots=256, use_graph=True, grid_blocks=0, a
 
 def dpt_serve_submit(srv: Server, problem: ProblemSpec, opts: Options = None,
                      want_eigenvectors: bool = False) -> int:
+    """Host (numpy) or device (torch cuda, finished) theta/Delta.  Device arrays
+    are read when the request is admitted: the ticket keeps the spec (and so its
+    tensors) alive until the result is polled."""
     t = ctypes.c_int64()
     rc = load_library().dpt_serve_submit(srv.ptr, ctypes.byref(problem.struct),
                                          ctypes.byref(opts) if opts is not None else None,
                                          int(bool(want_eigenvectors)), ctypes.byref(t))
     if rc != DPT_OK:
         raise DptError(rc, "dpt_serve_submit")
-    srv.tickets[t.value] = (int(problem.struct.n), bool(want_eigenvectors))
+    srv.tickets[t.value] = (int(problem.struct.n), bool(want_eigenvectors), problem)
     return t.value
 
 
 def dpt_serve_poll(srv: Server, ticket: int, wait_ms: int = 0):
     """None while pending; else dict(status, iters..., E, Z (or None), times)."""
-    n, want_z = srv.tickets[ticket]
+    n, want_z, _ = srv.tickets[ticket]
     e = np.empty(n, np.float64)
     z = np.empty((n, n), np.float64) if want_z else None
     r = Result()

@@ -84,7 +84,7 @@ def test_matches_single_problem_solver():
 
 def test_budget_limits_concurrency_and_everything_completes():
     probs = [request(256, True, 20 + i) for i in range(6)]
-    one = 3 * 256 * 8 + 2 * 256 * 256 * 4 + 256 * 256 * 4 + 3 * 256 * 256 * 2   # BF16, symmetric
+    one = 2 * 256 * 8 + 2 * 256 * 256 * 4 + 256 * 256 * 4 + 3 * 256 * 256 * 2   # BF16, symmetric: d, theta, W, D, BF16
     srv = dpt.dpt_serve_open(2 * one + 4096, max_slots=64)
     res = run_all(srv, probs, want_z=False)
     st = dpt.dpt_serve_stats_read(srv)
@@ -104,7 +104,7 @@ def test_submissions_beyond_the_staging_ring_wait_and_complete():
     th, de = request(n, True, 40)
     probs = [(th, de)] * count
     o = dict(tol=1e-5, max_iter=100, precision=1)
-    one = 3 * n * 8 + 3 * n * n * 4           # FP32, symmetric: theta, d, E, W[0..1], D
+    one = 2 * n * 8 + 3 * n * n * 4           # FP32, symmetric: d, theta, W[0..1], D
     srv = dpt.dpt_serve_open(one + (1 << 20), max_slots=8)
     res = run_all(srv, probs, want_z=False, opts=o)
     st = dpt.dpt_serve_stats_read(srv)
@@ -192,6 +192,46 @@ def test_large_problems_and_tile_autotuner(autotune):
         ref = oracle.iterate(th, de.astype(np.float64), 1.0, rows=rows, max_iter=200, tol=1e-14)
         assert rel_eig_error(res["E"][rows], ref["e"], th) <= 1e-5
         assert np.max(np.abs(res["Z"][rows] - ref["z"])) <= 1e-5 * np.max(np.abs(ref["z"] - np.eye(n)[rows]))
+
+
+def test_device_inputs_match_host_inputs():
+    """Problems submitted as device arrays (FP64 and FP32) give bitwise the
+    results of the same problems submitted from host memory (the transpose is
+    stored for every device problem: same values as the symmetric alias)."""
+    import torch
+    probs = [request(*m) for m in MIX]
+    srv = dpt.dpt_serve_open(1 << 30, max_slots=16)
+    host = run_all(srv, probs)
+    o = dpt.options(**OPTS)
+    for dtype in (torch.float64, torch.float32):
+        dev = [(torch.from_numpy(th).cuda(), torch.from_numpy(de).to(dtype).cuda()) for th, de in probs]
+        torch.cuda.synchronize()
+        tickets = [dpt.dpt_serve_submit(srv, dpt.ProblemSpec(th, de, 1.0), o, True) for th, de in dev]
+        res = [dpt.dpt_serve_poll(srv, t, wait_ms=-1) for t in tickets]
+        for (th, de), x, y in zip(probs, res, host):
+            # host submissions round the FP64 Delta to FP32 as torch does (to nearest even)
+            assert x["status"] == dpt.DPT_OK and x["iters"] == y["iters"], (len(th), x["status"])
+            assert np.array_equal(x["E"], y["E"]) and np.array_equal(x["Z"], y["Z"])
+    dpt.dpt_serve_close(srv)
+
+
+def test_device_submit_rejections():
+    import torch
+    th, de = request(50, True, 60)
+    srv = dpt.dpt_serve_open(1 << 28, max_slots=4)
+    bad_theta = torch.from_numpy(th).cuda()
+    bad_theta[3] = bad_theta[4]                       # duplicate unperturbed level
+    torch.cuda.synchronize()
+    with pytest.raises(dpt.DptError) as ei:
+        dpt.dpt_serve_submit(srv, dpt.ProblemSpec(bad_theta, torch.from_numpy(de).cuda(), 1.0), dpt.options(**OPTS))
+    assert ei.value.code == dpt.DPT_EINVAL
+    # theta on the device, Delta on the host: inconsistent memory kinds
+    with pytest.raises((dpt.DptError, ValueError, TypeError)):
+        dpt.dpt_serve_submit(srv, dpt.ProblemSpec(torch.from_numpy(th).cuda(), de, 1.0), dpt.options(**OPTS))
+    t = dpt.dpt_serve_submit(srv, dpt.ProblemSpec(torch.from_numpy(th).cuda(), torch.from_numpy(de).cuda(), 1.0),
+                             dpt.options(**OPTS))
+    assert dpt.dpt_serve_poll(srv, t, wait_ms=-1)["status"] == dpt.DPT_OK
+    dpt.dpt_serve_close(srv)
 
 
 def test_server_on_the_callers_stream():
