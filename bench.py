@@ -160,7 +160,7 @@ def serving_bench(args):
                 "converged": int(sum(r["status"] == dpt.DPT_OK for r in res)),
                 "steps": st["steps"], "peak_active": st["peak_active"],
                 "peak_arena_gib": round(st["peak_bytes"] / 2 ** 30, 3),
-                "tile128_min_ld_bf16_fp32": st["tile128_min_ld"]}
+                "tile_shape_bf16_fp32": st["tile_shape"]}
 
     def base_at(rate_mult):
         arr = arrivals / rate_mult

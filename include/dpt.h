@@ -325,7 +325,7 @@ int dpt_profile_read(dpt_handle h, dpt_profile *out);
  * its own stopping rule and is retired individually (freeing its memory for
  * the next admissions).  Results do not depend on which other problems share
  * a step: every problem is computed with tiles chosen from its own padded
- * order and phase (64x64, or 128x128 from a threshold fixed when the server
+ * order and phase (a shape per padded-order class, fixed when the server
  * opens) and with its own statistics. */
 typedef struct dpt_server_ctx *dpt_server;
 
@@ -334,9 +334,11 @@ typedef struct dpt_serve_config {
     int32_t max_slots;      /* concurrent problems, 1 .. 1024                         */
     int32_t use_graph;      /* 1: replay the grouped step as a HIP graph              */
     int32_t grid_blocks;    /* persistent grid of the grouped kernels; 0 = 1024       */
-    int32_t autotune;       /* 1: time 64x64 against 128x128 fused-step tiles per     *
-                             * phase and size at open and keep the faster; 0: 128x128 *
-                             * tiles from padded order 1024 up                       */
+    int32_t autotune;       /* 1: time the fused-step tile shapes (64x64, 128x64,     *
+                             * 128x128) per phase and padded-order class at open and  *
+                             * keep the fastest; 0: 128x128 above padded order 512;   *
+                             * -1, -2, -3: shape 64x64, 128x64 or 128x128 for every   *
+                             * class (orders that are not multiples of 128: 64x64)    */
     void *stream;           /* hipStream_t for all of the server's device work (the   *
                              * caller keeps ownership and enqueues nothing on it      *
                              * while the server is open), or NULL: an own stream      */
@@ -352,8 +354,11 @@ typedef struct dpt_serve_stats {
     int64_t peak_active, peak_bytes;       /* largest concurrent set and arena use  */
     int64_t active, pending;               /* current counts                        */
     double busy_s;                         /* wall time spent inside engine steps   */
-    int64_t tile128_min_ld[2];             /* smallest padded order run with 128x128 *
-                                            * tiles in the BF16 / FP32 phase; -1: none */
+    int32_t tile_shape[2][4];              /* fused-step tile per phase (BF16, FP32) *
+                                            * and padded-order class (ld <= 256,     *
+                                            * <= 512, <= 1024, larger): 0 = 64x64,   *
+                                            * 1 = 128x64, 2 = 128x128 (orders that   *
+                                            * are not multiples of 128 use 64x64)    */
 } dpt_serve_stats;
 
 /* Start a server on the current device (on cfg->stream, or a stream of its own,

@@ -184,12 +184,17 @@ struct GroupReq {
 constexpr int kServeMaxSlots = 1024;
 
 // Work lists of one serving step, rewritten by the host before every step.
-// The fused-step work is split into kGroupLists lists by (phase, tile edge):
-// list 2 * (phase == PH_FP32) + (tile == 128).  counts[0] = requests,
+// Output tile shapes of the grouped fused step (rows x columns): shape 0 is
+// 64 x 64, 1 is 128 x 64, 2 is 128 x 128 (shapes 1 and 2 need ld % 128 == 0).
+// The fused-step work is split into kGroupLists lists by (phase, shape): list
+// kGroupShapes * (phase == PH_FP32) + shape.  counts[0] = requests,
 // counts[1 + L] = requests in list L; prefix arrays hold running sums of rows
 // (pre-pass) and of output tiles (step kernels).
-constexpr int kGroupLists = 4;
-inline int group_list(int phase, int tile) { return 2 * (phase == PH_FP32 ? 1 : 0) + (tile == 128 ? 1 : 0); }
+constexpr int kGroupShapes = 3;
+constexpr int group_shape_rows(int shape) { return shape == 0 ? 64 : 128; }
+constexpr int group_shape_cols(int shape) { return shape == 2 ? 128 : 64; }
+constexpr int kGroupLists = 2 * kGroupShapes;
+inline int group_list(int phase, int shape) { return kGroupShapes * (phase == PH_FP32 ? 1 : 0) + shape; }
 
 struct GroupTable {
     int32_t counts[1 + kGroupLists];
@@ -250,9 +255,8 @@ hipError_t launch_group_retire(const RetireTable *t, int grid, hipStream_t s);
 
 // Persistent grouped launches with a fixed grid (graph-capturable): the
 // pre-pass (also clears each request's stats) and the fused step for the
-// requests of one phase (PH_BF16 or PH_FP32) with one tile edge (64 or 128;
-// 128 needs ld % 128 == 0).
+// requests of one phase (PH_BF16 or PH_FP32) with one tile shape.
 hipError_t launch_group_prepass(const GroupTable *t, int grid, hipStream_t s);
-hipError_t launch_group_step(const GroupTable *t, int phase, int tile, int grid, hipStream_t s);
+hipError_t launch_group_step(const GroupTable *t, int phase, int shape, int grid, hipStream_t s);
 
 }  // namespace dpt

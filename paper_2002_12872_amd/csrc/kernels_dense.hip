@@ -693,11 +693,12 @@ __global__ __launch_bounds__(256) void k_group_prepass(const GroupTable *__restr
     }
 }
 
-// One TILE x TILE output tile of one request per work item; blocks stride over
-// the items of every request in the list (persistent grid, fixed size).
-template <int PHASE, int TILE>
+// One output tile (shape SHAPE) of one request per work item; blocks stride
+// over the items of every request in the list (persistent grid, fixed size).
+template <int PHASE, int SHAPE>
 __global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict__ t) {
-    constexpr int L = 2 * (PHASE == PH_FP32 ? 1 : 0) + (TILE == 128 ? 1 : 0);
+    constexpr int BM = group_shape_rows(SHAPE), BN = group_shape_cols(SHAPE);
+    constexpr int L = kGroupShapes * (PHASE == PH_FP32 ? 1 : 0) + SHAPE;
     const int cnt = t->counts[1 + L];
     const int32_t *idx = t->idx[L];
     const int32_t *prefix = t->prefix[L];
@@ -705,7 +706,7 @@ __global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int j = find_segment(prefix, cnt, item);
         const GroupReq &q = t->reqs[idx[j]];
-        const int tpr = (int)(q.ld / TILE);
+        const int tpr = (int)(q.ld / BN);
         const int local = item - prefix[j];
         const int tm = local / tpr, tn = local - tm * tpr;
         StepArgs a;
@@ -716,9 +717,9 @@ __global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict
         a.d = q.d;
         a.stat = q.stat;
         if (PHASE == PH_BF16)
-            step_tile<PolBF16, TILE, TILE, 32, 2, 2, float>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
+            step_tile<PolBF16, BM, BN, 32, 2, 2, float>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
         else
-            step_tile<PolF32, TILE, TILE, 16, 2, 2, float>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a, tm, tn);
+            step_tile<PolF32, BM, BN, 16, 2, 2, float>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a, tm, tn);
     }
 }
 
@@ -1140,18 +1141,24 @@ hipError_t launch_group_prepass(const GroupTable *t, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_group_step(const GroupTable *t, int phase, int tile, int grid, hipStream_t s) {
-    if (tile != 64 && tile != 128) return hipErrorInvalidValue;
-    if (phase == PH_BF16 && tile == 64)
-        hipLaunchKernelGGL((k_group_step<PH_BF16, 64>), dim3((unsigned int)grid), dim3(256), 0, s, t);
-    else if (phase == PH_BF16)
-        hipLaunchKernelGGL((k_group_step<PH_BF16, 128>), dim3((unsigned int)grid), dim3(256), 0, s, t);
-    else if (phase == PH_FP32 && tile == 64)
-        hipLaunchKernelGGL((k_group_step<PH_FP32, 64>), dim3((unsigned int)grid), dim3(256), 0, s, t);
-    else if (phase == PH_FP32)
-        hipLaunchKernelGGL((k_group_step<PH_FP32, 128>), dim3((unsigned int)grid), dim3(256), 0, s, t);
+hipError_t launch_group_step(const GroupTable *t, int phase, int shape, int grid, hipStream_t s) {
+    const dim3 g((unsigned int)grid), b(256);
+#define DPT_GROUP_STEP(PH, SH) hipLaunchKernelGGL((k_group_step<PH, SH>), g, b, 0, s, t)
+    if (phase == PH_BF16 && shape == 0)
+        DPT_GROUP_STEP(PH_BF16, 0);
+    else if (phase == PH_BF16 && shape == 1)
+        DPT_GROUP_STEP(PH_BF16, 1);
+    else if (phase == PH_BF16 && shape == 2)
+        DPT_GROUP_STEP(PH_BF16, 2);
+    else if (phase == PH_FP32 && shape == 0)
+        DPT_GROUP_STEP(PH_FP32, 0);
+    else if (phase == PH_FP32 && shape == 1)
+        DPT_GROUP_STEP(PH_FP32, 1);
+    else if (phase == PH_FP32 && shape == 2)
+        DPT_GROUP_STEP(PH_FP32, 2);
     else
         return hipErrorInvalidValue;
+#undef DPT_GROUP_STEP
     return hipGetLastError();
 }
 

@@ -323,9 +323,11 @@ struct dpt_server_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::chrono::steady_clock::time_point t0;
-    // smallest padded order that uses 128 x 128 tiles, per phase (BF16, FP32);
-    // set by the autotuner at open, else the defaults below
-    int64_t min_ld_128[2] = {1024, 1024};
+    // fused-step tile shape (index into the grouped shapes) per phase (BF16,
+    // FP32) and padded-order class (ld <= 256, <= 512, <= 1024, larger); set by
+    // the autotuner at open, else the defaults below (128 x 128 above 512)
+    static constexpr int kOrderClasses = 4;
+    int shape_of[2][kOrderClasses] = {{0, 0, 2, 2}, {0, 0, 2, 2}};
 
     // pinned staging ring (guarded by ring_mu; cv_ring wakes waiting submits)
     static constexpr size_t kRingBytes = (size_t)256 << 20;
@@ -376,14 +378,16 @@ struct dpt_server_ctx {
 
     // ------------------------------------------------------------ worker
     // The launches of one engine step: the pre-pass and the fused step for every
-    // (phase, tile) list; lists without work exit at once.
-    // (128x128 launches are left out for a phase that never uses them.)
+    // (phase, shape) list; lists without work exit at once.  Shapes a phase
+    // never uses are left out (64 x 64, the fallback, always stays).
     hipError_t launch_all(hipStream_t s) const {
         hipError_t e = launch_group_prepass(table_d, grid, s);
-        for (int ph : {PH_BF16, PH_FP32})
-            for (int tile : {64, 128})
-                if (e == hipSuccess && (tile == 64 || min_ld_128[ph == PH_BF16 ? 0 : 1] != INT64_MAX))
-                    e = launch_group_step(table_d, ph, tile, grid, s);
+        for (int pi = 0; pi < 2; ++pi)
+            for (int sh = 0; sh < kGroupShapes; ++sh) {
+                bool used = sh == 0;
+                for (int k = 0; k < kOrderClasses; ++k) used |= shape_of[pi][k] == sh;
+                if (e == hipSuccess && used) e = launch_group_step(table_d, pi == 0 ? PH_BF16 : PH_FP32, sh, grid, s);
+            }
         return e;
     }
 
@@ -392,22 +396,27 @@ struct dpt_server_ctx {
         return launch_all(stream);
     }
 
-    int tile_for(int64_t ld, int phase) const {
-        return (ld % 128 == 0 && ld >= min_ld_128[phase == PH_BF16 ? 0 : 1]) ? 128 : 64;
+    static int order_class(int64_t ld) { return ld <= 256 ? 0 : ld <= 512 ? 1 : ld <= 1024 ? 2 : 3; }
+
+    // The shape chosen for the order class of ld, or 64 x 64 when ld is not a
+    // multiple of its tile edges.
+    int shape_for(int64_t ld, int phase) const {
+        const int sh = shape_of[phase == PH_BF16 ? 0 : 1][order_class(ld)];
+        return (ld % group_shape_rows(sh) == 0 && ld % group_shape_cols(sh) == 0) ? sh : 0;
     }
 
-    // Tile-shape autotuner.  For padded orders 256 .. 2048 and each phase, time
-    // the grouped fused step over a batch of synthetic problems (about four
-    // grid-fulls of 64x64 tiles, distinct buffers, zero state, theta_i = i) with
-    // 64x64 and with 128x128 tiles; 128x128 is used from the smallest order
-    // from which it is at least 3 % faster at every larger order measured.
+    // Tile-shape autotuner.  For padded orders 256, 512, 1024, 2048 (the largest
+    // of each order class) and each phase, time the grouped fused step over a
+    // batch of synthetic problems (about four grid-fulls of 64x64 tiles,
+    // distinct buffers, zero state, theta_i = i) with each tile shape; a larger
+    // shape replaces the best so far only when at least 3 % faster.
     hipError_t autotune() {
         const int64_t orders[] = {256, 512, 1024, 2048};
         constexpr int kOrders = 4, kReps = 3;
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         hipError_t e = hipEventCreate(&ev0);
         if (e == hipSuccess) e = hipEventCreate(&ev1);
-        bool wins[2][kOrders] = {};
+        int best[2][kOrders] = {};
         for (int oi = 0; oi < kOrders && e == hipSuccess; ++oi) {
             const int64_t ld = orders[oi], l2 = ld * ld;
             const int batch = (int)std::min<int64_t>(64, std::max<int64_t>(1, 4 * (int64_t)grid * 4096 / l2));
@@ -442,27 +451,30 @@ struct dpt_server_ctx {
             }
             for (int pi = 0; pi < 2 && e == hipSuccess; ++pi) {
                 const int phase = pi == 0 ? PH_BF16 : PH_FP32;
-                float ms[2] = {0.0f, 0.0f};
-                for (int ti = 0; ti < 2 && e == hipSuccess; ++ti) {
-                    const int tile = ti == 0 ? 64 : 128, L = group_list(phase, tile);
+                float ms[kGroupShapes] = {};
+                for (int sh = 0; sh < kGroupShapes && e == hipSuccess; ++sh) {
+                    const int L = group_list(phase, sh);
                     std::memset(t.counts, 0, sizeof(t.counts));
                     t.counts[0] = batch;
                     t.counts[1 + L] = batch;
-                    const int32_t tiles = (int32_t)((ld / tile) * (ld / tile));
+                    const int32_t tiles = (int32_t)((ld / group_shape_rows(sh)) * (ld / group_shape_cols(sh)));
                     for (int b = 0; b <= batch; ++b) {
                         t.prefix[L][b] = b * tiles;
                         if (b < batch) t.idx[L][b] = b;
                     }
                     e = hipMemcpyAsync(table_d, table_h, sizeof(GroupTable), hipMemcpyHostToDevice, stream);
-                    if (e == hipSuccess) e = launch_group_step(table_d, phase, tile, grid, stream);  // warm-up
+                    if (e == hipSuccess) e = launch_group_step(table_d, phase, sh, grid, stream);  // warm-up
                     if (e == hipSuccess) e = hipEventRecord(ev0, stream);
                     for (int r = 0; r < kReps && e == hipSuccess; ++r)
-                        e = launch_group_step(table_d, phase, tile, grid, stream);
+                        e = launch_group_step(table_d, phase, sh, grid, stream);
                     if (e == hipSuccess) e = hipEventRecord(ev1, stream);
                     if (e == hipSuccess) e = hipEventSynchronize(ev1);
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms[ti], ev0, ev1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms[sh], ev0, ev1);
                 }
-                wins[pi][oi] = ms[1] < 0.97f * ms[0];
+                int b = 0;
+                for (int sh = 1; sh < kGroupShapes; ++sh)
+                    if (ms[sh] < 0.97f * ms[b]) b = sh;
+                best[pi][oi] = b;
             }
             (void)hipStreamSynchronize(stream);
             (void)hipFree(buf);
@@ -473,11 +485,8 @@ struct dpt_server_ctx {
         if (e == hipSuccess) e = hipMemcpyAsync(table_d, table_h, sizeof(GroupTable), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e == hipSuccess)
-            for (int pi = 0; pi < 2; ++pi) {
-                int64_t m = INT64_MAX;
-                for (int oi = kOrders - 1; oi >= 0 && wins[pi][oi]; --oi) m = orders[oi];
-                min_ld_128[pi] = m;
-            }
+            for (int pi = 0; pi < 2; ++pi)
+                for (int oi = 0; oi < kOrders; ++oi) shape_of[pi][oi] = best[pi][oi];
         return e;
     }
 
@@ -613,11 +622,11 @@ struct dpt_server_ctx {
             g.lambda = r->lambda;
             t.pre_prefix[nreq] = rows;
             rows += (int32_t)r->n;
-            const int phase = bf ? PH_BF16 : PH_FP32, tile = tile_for(r->ld, phase);
-            const int L = group_list(phase, tile);
+            const int phase = bf ? PH_BF16 : PH_FP32, sh = shape_for(r->ld, phase);
+            const int L = group_list(phase, sh);
             t.idx[L][cnt[L]] = nreq;
             t.prefix[L][cnt[L]++] = tiles_sum[L];
-            tiles_sum[L] += (int32_t)((r->ld / tile) * (r->ld / tile));
+            tiles_sum[L] += (int32_t)((r->ld / group_shape_rows(sh)) * (r->ld / group_shape_cols(sh)));
             ++nreq;
         }
         t.pre_prefix[nreq] = rows;
@@ -830,7 +839,7 @@ extern "C" {
 
 int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     if (!srv || !cfg || cfg->budget_bytes <= 0 || cfg->max_slots < 1 || cfg->max_slots > kServeMaxSlots ||
-        cfg->grid_blocks < 0 || (cfg->autotune != 0 && cfg->autotune != 1))
+        cfg->grid_blocks < 0 || cfg->autotune < -kGroupShapes || cfg->autotune > 1)
         return DPT_EINVAL;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return DPT_EDEVICE;
@@ -864,11 +873,10 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
         std::memset(c->table_h, 0, sizeof(GroupTable));
         e = hipMemcpy(c->table_d, c->table_h, sizeof(GroupTable), hipMemcpyHostToDevice);
     }
-    // every slot's stats start at zero (the admission launch publishes into them;
-    // retirement clears them again)
-    if (e == hipSuccess) e = launch_zero_u64(c->stats_d, 2 * (int64_t)cfg->max_slots, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess && cfg->autotune) e = c->autotune();  // fixes the launches the graph holds
+    if (cfg->autotune < 0)  // one shape for every order class
+        for (auto &row : c->shape_of)
+            for (int &sh : row) sh = -cfg->autotune - 1;
+    if (e == hipSuccess && cfg->autotune == 1) e = c->autotune();  // fixes the launches the graph holds
     if (e == hipSuccess && cfg->use_graph) {
         e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
@@ -878,13 +886,17 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
     }
+    // every slot's stats start at zero (the autotuner's timing runs publish into
+    // slot 0; the admission launch publishes into them; retirement clears them)
+    if (e == hipSuccess) e = launch_zero_u64(c->stats_d, 2 * (int64_t)cfg->max_slots, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         const int code = (e == hipErrorOutOfMemory) ? DPT_ENOMEM : DPT_EDEVICE;
         delete c;
         return code;
     }
-    c->st.tile128_min_ld[0] = c->min_ld_128[0] == INT64_MAX ? -1 : c->min_ld_128[0];
-    c->st.tile128_min_ld[1] = c->min_ld_128[1] == INT64_MAX ? -1 : c->min_ld_128[1];
+    for (int pi = 0; pi < 2; ++pi)
+        for (int k = 0; k < dpt_server_ctx::kOrderClasses; ++k) c->st.tile_shape[pi][k] = c->shape_of[pi][k];
     c->arena.init((size_t)cfg->budget_bytes);
     for (int i = cfg->max_slots - 1; i >= 0; --i) c->free_slots.push_back(i);
     c->stage_pool.start(dpt_server_ctx::kStageThreads);

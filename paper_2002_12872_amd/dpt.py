@@ -102,7 +102,7 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("peak_active", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
                 ("active", ctypes.c_int64), ("pending", ctypes.c_int64), ("busy_s", ctypes.c_double),
-                ("tile128_min_ld", ctypes.c_int64 * 2)]
+                ("tile_shape", (ctypes.c_int32 * 4) * 2)]
 
 
 _FUNCS = {
@@ -511,10 +511,12 @@ class Server:
 
 
 def dpt_serve_open(budget_bytes, max_slots=256, use_graph=True, grid_blocks=0, autotune=False,
-                   stream=None) -> Server:
-    """stream: a hipStream_t (e.g. torch.cuda.Stream().cuda_stream) for the server's work, or None."""
-    cfg = ServeConfig(int(budget_bytes), int(max_slots), int(bool(use_graph)), int(grid_blocks), int(bool(autotune)),
-                      stream)
+                   stream=None, tile_shape=None) -> Server:
+    """stream: a hipStream_t (e.g. torch.cuda.Stream().cuda_stream) for the server's work, or None.
+    tile_shape: 0, 1 or 2 (64x64, 128x64, 128x128) for every order class instead of the defaults
+    or the autotuner."""
+    mode = int(bool(autotune)) if tile_shape is None else -int(tile_shape) - 1
+    cfg = ServeConfig(int(budget_bytes), int(max_slots), int(bool(use_graph)), int(grid_blocks), mode, stream)
     h = ctypes.c_void_p()
     rc = load_library().dpt_serve_open(ctypes.byref(h), ctypes.byref(cfg))
     if rc != DPT_OK:
@@ -564,7 +566,7 @@ def dpt_serve_stats_read(srv: Server) -> dict:
     if rc != DPT_OK:
         raise DptError(rc, "dpt_serve_stats_read")
     out = {k: getattr(st, k) for k, _ in ServeStats._fields_}
-    out["tile128_min_ld"] = list(st.tile128_min_ld)
+    out["tile_shape"] = [list(row) for row in st.tile_shape]
     return out
 
 

@@ -1,8 +1,8 @@
 """Serving engine: continuous batching of uneven-size problems (C ABI through the binding).
 
 Every problem is computed with tiles chosen from its own padded order and
-phase (64x64, or 128x128 from a threshold fixed when the server opens) and
-with its own statistics, so a problem's result must not depend on the batch it
+phase (a tile shape per order class, fixed when the server opens) and with its
+own statistics, so a problem's result must not depend on the batch it
 shares: alone and in a mix the results are bitwise equal.  Each result is also
 checked against the FP64 oracle at the FP32 target (1e-5).
 """
@@ -171,16 +171,15 @@ def test_zero_iterations_retire_without_a_step():
 
 @pytest.mark.parametrize("autotune", [False, True])
 def test_large_problems_and_tile_autotuner(autotune):
-    """Padded orders >= 1024 run with 128x128 tiles by default; the autotuner
-    picks the threshold per phase by timing at open.  Either way results are
-    batch invariant and reach the FP32 target."""
+    """Padded orders above 512 run with 128x128 tiles by default; the autotuner
+    picks one of three shapes per phase and order class by timing at open.
+    Either way results are batch invariant and reach the FP32 target."""
     probs = [request(1100, True, 30), request(1030, False, 31), request(300, True, 32), request(64, False, 33)]
     srv = dpt.dpt_serve_open(8 << 30, max_slots=16, autotune=autotune)
     st = dpt.dpt_serve_stats_read(srv)
-    for m in st["tile128_min_ld"]:
-        assert m in (-1, 256, 512, 1024, 2048)
+    assert all(sh in (0, 1, 2) for row in st["tile_shape"] for sh in row)
     if not autotune:
-        assert st["tile128_min_ld"] == [1024, 1024]
+        assert st["tile_shape"] == [[0, 0, 2, 2], [0, 0, 2, 2]]
     alone = run_all(srv, [probs[0]], opts=OPTS_ACC)[0]
     mixed = run_all(srv, probs, opts=OPTS_ACC)
     dpt.dpt_serve_close(srv)
@@ -192,6 +191,29 @@ def test_large_problems_and_tile_autotuner(autotune):
         ref = oracle.iterate(th, de.astype(np.float64), 1.0, rows=rows, max_iter=200, tol=1e-14)
         assert rel_eig_error(res["E"][rows], ref["e"], th) <= 1e-5
         assert np.max(np.abs(res["Z"][rows] - ref["z"])) <= 1e-5 * np.max(np.abs(ref["z"] - np.eye(n)[rows]))
+
+
+def test_every_tile_shape_is_batch_invariant_and_matches_oracle():
+    """Each of the three fused-step tile shapes, forced for every order class:
+    alone and in a mix bitwise equal, and at the FP32 bar against the oracle
+    (orders 250 / 500 / 1000 pad to multiples of 128, 300 to 320: 64x64)."""
+    probs = [request(250, True, 70), request(500, False, 71), request(1000, True, 72), request(300, False, 73)]
+    refs = []
+    for th, de in probs:
+        rows = workloads.sample_rows(th.shape[0], 16)
+        refs.append((rows, oracle.iterate(th, de.astype(np.float64), 1.0, rows=rows, max_iter=200, tol=1e-14)))
+    for shape in (0, 1, 2):
+        srv = dpt.dpt_serve_open(4 << 30, max_slots=16, tile_shape=shape)
+        assert dpt.dpt_serve_stats_read(srv)["tile_shape"] == [[shape] * 4] * 2
+        alone = run_all(srv, [probs[1]], opts=OPTS_ACC)[0]
+        mixed = run_all(srv, probs, opts=OPTS_ACC)
+        dpt.dpt_serve_close(srv)
+        assert np.array_equal(alone["E"], mixed[1]["E"]) and np.array_equal(alone["Z"], mixed[1]["Z"])
+        for (th, de), res, (rows, ref) in zip(probs, mixed, refs):
+            assert res["status"] == dpt.DPT_OK, (shape, th.shape[0])
+            assert rel_eig_error(res["E"][rows], ref["e"], th) <= 1e-5
+            n = th.shape[0]
+            assert np.max(np.abs(res["Z"][rows] - ref["z"])) <= 1e-5 * np.max(np.abs(ref["z"] - np.eye(n)[rows]))
 
 
 def test_device_inputs_match_host_inputs():
