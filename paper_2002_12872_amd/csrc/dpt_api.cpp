@@ -647,13 +647,16 @@ int small_batch(dpt_ctx *c, Controller &ctl, dpt_result *r, int64_t consumed, in
     const size_t l2 = (size_t)(c->ld * c->ld), esz = f64 ? 8 : 4;
     if (!c->small_hist) DPT_TRY(dalloc((unsigned char **)&c->small_hist, (size_t)kSmallBatch * l2 * 8));
     const StepArgs a = step_args(c, nullptr);
+    // the first delta below the phase's target ends the batch on the device: the
+    // controller's decision (delta or estimate rule) comes at that step or earlier
+    const double target = (c->phase == PH_FP64 && c->opt.precision != DPT_FP64) ? c->opt.fp64_final_tol : c->opt.tol;
     hipError_t e;
     if (f64)
         e = launch_small_steps_f64(c->W64[c->cur], (double *)c->small_hist, c->d64, c->dT64, a, c->stats, c->k, m,
-                                   c->at_identity ? 1 : 0, c->dvec, c->stream);
+                                   c->at_identity ? 1 : 0, c->dvec, target, c->opt.blowup, c->stream);
     else
         e = launch_small_steps_f32(c->W32[c->cur], (float *)c->small_hist, c->d32, c->dT32, a, c->stats, c->k, m,
-                                   c->at_identity ? 1 : 0, c->dvec, c->stream);
+                                   c->at_identity ? 1 : 0, c->dvec, target, c->opt.blowup, c->stream);
     DPT_TRY(e);
     int rc = fetch_stats(c, c->k, c->k + m);
     if (rc != DPT_OK) return rc;

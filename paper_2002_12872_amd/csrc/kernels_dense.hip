@@ -576,30 +576,190 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm_nt_f64(const double *__res
 }
 
 // --------------------------------------------------- small problems (ld 64)
+// One application of F to a 64 x 64 state held in LDS (row pitch PW elements),
+// by the 4 waves of the block: the product and update of
+// step_tile<P, 64, 64, 16, 2, 2, S> (wave grid 2 x 2, 32 x 32 wave tiles) with
+// the same MFMAs on the same operands in the same order and the same
+// per-element arithmetic, so the result is bitwise the same; the operands are
+// read from LDS directly (no staging) and each lane's epilogue loads are issued
+// before its stores.  FP64: 16x16x4 MFMAs, lane group g = lane / 16 holds K
+// values 4g .. 4g + 3 of each K-tile of 16, MFMA s takes K = 4g + s.  FP32:
+// 32x32x2 MFMAs, g = lane / 32 holds K values 8g .. 8g + 7, MFMA s takes
+// K = 8g + s.  Wold, Dl, d, th and stat are in LDS; dT (pitch dtp) may be global.
+template <typename S, int PW>
+__device__ __forceinline__ void small_step_tile(const S *Wold, const S *Dl, const S *dT, int dtp, S *Wnew,
+                                                const double *d, const double *th, int64_t N, double lambda,
+                                                unsigned long long *stat) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wr = wave >> 1, wc = wave & 1;
+    const S lam = (S)lambda;
+    double dmax = 0.0, wmax = 0.0;
+    bool bad = false;
+    if constexpr (sizeof(S) == 8) {
+        const int grp = lane >> 4, rr = lane & 15;
+        doublex4_t acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+        const S *a0 = Wold + (wr * 32 + rr) * PW, *b0 = Dl + (wc * 32 + rr) * PW;
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int k = kt * 16 + grp * 4 + 2 * v;
+                const double2 A0 = *reinterpret_cast<const double2 *>(a0 + k);
+                const double2 A1 = *reinterpret_cast<const double2 *>(a0 + 16 * PW + k);
+                const double2 B0 = *reinterpret_cast<const double2 *>(b0 + k);
+                const double2 B1 = *reinterpret_cast<const double2 *>(b0 + 16 * PW + k);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const double x0 = e ? A0.y : A0.x, x1 = e ? A1.y : A1.x;
+                    const double y0 = e ? B0.y : B0.x, y1 = e ? B1.y : B1.x;
+                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
+                }
+            }
+        }
+        // register r of lane l in block (i, j): row 16 i + 4 r + (l >> 4), column 16 j + (l & 15)
+        S dt[2][2][4], wo[2][2][4];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n = wr * 32 + 16 * i + 4 * r + (lane >> 4), m = wc * 32 + 16 * j + (lane & 15);
+                    dt[i][j][r] = dT[n * dtp + m];
+                    wo[i][j][r] = Wold[n * PW + m];
+                }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int m = wc * 32 + 16 * j + (lane & 15);
+            const double th_m = th[m];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n = wr * 32 + 16 * i + 4 * r + (lane >> 4);
+                    const S c = (S)acc[i][j][r] + dt[i][j][r];
+                    const S o = wo[i][j][r];
+                    S w = (S)0;
+                    if (n < N && m < N && n != m) {
+                        const S num = c - (S)d[n] * o;
+                        const S gap = (S)(th[n] - th_m);
+                        w = lam * num / gap;
+                    }
+                    Wnew[n * PW + m] = w;
+                    const double dv = fabs((double)w - (double)o), av = fabs((double)w);
+                    dmax = fmax(dmax, dv);
+                    wmax = fmax(wmax, av);
+                    bad |= !(dv <= DBL_MAX) || !(av <= DBL_MAX);
+                }
+        }
+    } else {
+        const int grp = lane >> 5, rr = lane & 31;
+        floatx16_t acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+        const S *a0 = Wold + (wr * 32 + rr) * PW, *b0 = Dl + (wc * 32 + rr) * PW;
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int k = kt * 16 + grp * 8 + 4 * v;
+                const float4 A = *reinterpret_cast<const float4 *>(a0 + k);
+                const float4 B = *reinterpret_cast<const float4 *>(b0 + k);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A.x, B.x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A.y, B.y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A.z, B.z, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A.w, B.w, acc, 0, 0, 0);
+            }
+        }
+        // register r of lane l: row (r & 3) + 4 (l >> 5) + 8 (r >> 2), column l & 31
+        const int m = wc * 32 + (lane & 31);
+        S dt[16], wo[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int n = wr * 32 + (r & 3) + ((lane >> 5) << 2) + ((r >> 2) << 3);
+            dt[r] = dT[n * dtp + m];
+            wo[r] = Wold[n * PW + m];
+        }
+        const double th_m = th[m];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int n = wr * 32 + (r & 3) + ((lane >> 5) << 2) + ((r >> 2) << 3);
+            const S c = (S)acc[r] + dt[r];
+            const S o = wo[r];
+            S w = (S)0;
+            if (n < N && m < N && n != m) {
+                const S num = c - (S)d[n] * o;
+                const S gap = (S)(th[n] - th_m);
+                w = lam * num / gap;
+            }
+            Wnew[n * PW + m] = w;
+            const double dv = fabs((double)w - (double)o), av = fabs((double)w);
+            dmax = fmax(dmax, dv);
+            wmax = fmax(wmax, av);
+            bad |= !(dv <= DBL_MAX) || !(av <= DBL_MAX);
+        }
+    }
+    publish_stats(stat, dmax, wmax, bad);
+}
+
 // Up to nsteps applications of F in one workgroup for ld = 64 (one 64x64 tile),
 // bitwise equal to the separate first-iterate / pre-pass / step launches: the
 // same per-element arithmetic and the same reduction order, with the 64 rows
 // spread over the block (16 lanes per row, 4 columns per lane) instead of one
-// block per row.  Iterate s + 1 goes to hist + s ld^2 and its statistics to
-// ring slot (k0 + s) mod kStatRing; the host picks the iterate its stopping rule
-// ends on (the later ones are discarded).
-template <class P, typename S>
+// block per row.  Delta (and Delta^T when it is not Delta itself, in FP32), theta,
+// d, the step statistics and the two latest iterates stay in LDS for the whole
+// batch (rows padded to PW elements against bank conflicts), so a step's
+// operands never leave the CU; iterate s + 1 is also written to hist + s ld^2,
+// d to the given array and the statistics to ring slot (k0 + s) mod kStatRing.
+// The host picks the iterate its stopping rule ends on (the later ones are
+// discarded); the batch ends early after a step whose delta is below stop_below
+// or not finite, or whose max|W| exceeds blowup: the host's rule ends there or
+// earlier.
+template <typename S>
 __global__ __launch_bounds__(256) void k_small_steps(const S *__restrict__ Wcur, S *__restrict__ hist,
                                                      const S *__restrict__ D, const S *__restrict__ DT, StepArgs a,
                                                      unsigned long long *__restrict__ stats, int64_t k0, int nsteps,
-                                                     int at_identity, double *__restrict__ d) {
-    constexpr int64_t LD = 64;
-    const int64_t l2 = LD * LD;
+                                                     int at_identity, double *__restrict__ d, double stop_below,
+                                                     double blowup) {
+    constexpr int LD = 64, PW = sizeof(S) == 8 ? 66 : 68, L2P = LD * PW;
+    constexpr int VPC = 16 / (int)sizeof(S), CPR = LD / VPC;  // values per 16-byte chunk, chunks per row
+    __shared__ __attribute__((aligned(16))) S sW[2][L2P];
+    __shared__ __attribute__((aligned(16))) S sD[L2P];
+    __shared__ __attribute__((aligned(16))) S sDT[(sizeof(S) == 4) ? L2P : 1];  // FP32 only (FP64: LDS budget)
+    __shared__ double sTh[64], sd[64];
+    __shared__ unsigned long long sStat[2];
+    __shared__ int s_stop;
     const int t = threadIdx.x, c4 = 4 * (t & 15), r0 = t >> 4;
+    const bool dt_is_d = DT == D;
+    if (t < 64) sTh[t] = a.theta[t];
+    for (int i = t; i < LD * CPR; i += 256) {
+        const int row = i / CPR, col = (i % CPR) * VPC;
+        *reinterpret_cast<u32x4_t *>(&sD[row * PW + col]) = *reinterpret_cast<const u32x4_t *>(&D[row * LD + col]);
+        *reinterpret_cast<u32x4_t *>(&sW[0][row * PW + col]) =
+            *reinterpret_cast<const u32x4_t *>(&Wcur[row * LD + col]);
+        if (sizeof(S) == 4 && !dt_is_d)
+            *reinterpret_cast<u32x4_t *>(&sDT[row * PW + col]) =
+                *reinterpret_cast<const u32x4_t *>(&DT[row * LD + col]);
+    }
+    __syncthreads();
+    // Delta^T for the epilogue and the first iterate: LDS, except an FP64
+    // unsymmetric Delta^T, read from global memory (cached)
+    const S *dT = dt_is_d ? (const S *)sD : (sizeof(S) == 4 ? (const S *)sDT : DT);
+    const int dtp = (dt_is_d || sizeof(S) == 4) ? PW : LD;
     for (int s = 0; s < nsteps; ++s) {
-        const S *Wold = s == 0 ? Wcur : hist + (int64_t)(s - 1) * l2;
-        S *Wnew = hist + (int64_t)s * l2;
-        StepArgs as = a;
-        as.stat = stats + 2 * ((k0 + s) % kStatRing);
-        as.d = d;
+        const S *Wold = sW[s & 1];
+        S *Wnew = sW[(s + 1) & 1];
         if (t == 0) {
-            as.stat[0] = 0ull;
-            as.stat[1] = 0ull;
+            sStat[0] = 0ull;
+            sStat[1] = 0ull;
         }
         __syncthreads();
         if (s == 0 && at_identity) {
@@ -608,47 +768,66 @@ __global__ __launch_bounds__(256) void k_small_steps(const S *__restrict__ Wcur,
             bool bad = false;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t n = r0 + 16 * q, idx = n * LD + c4;
-                const double th_n = a.theta[n];
+                const int n = r0 + 16 * q;
+                const double th_n = sTh[n];
                 const bool row_ok = n < a.n;
                 S dv[4], w[4];
-                load4v(DT + idx, dv);
+                load4v(dT + n * dtp + c4, dv);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int64_t m = c4 + e;
+                    const int m = c4 + e;
                     w[e] = (S)0;
-                    if (row_ok && m < a.n && m != n) w[e] = gap_quotient<S>(a.lambda * (double)dv[e], th_n, a.theta[m]);
+                    if (row_ok && m < a.n && m != n) w[e] = gap_quotient<S>(a.lambda * (double)dv[e], th_n, sTh[m]);
                     const double v = fabs((double)w[e]);
                     dmax = fmax(dmax, v);
                     bad |= !(v <= DBL_MAX);
                 }
-                store4v(Wnew + idx, w);
+                store4v(Wnew + n * PW + c4, w);
             }
-            publish_stats_block(as.stat, dmax, dmax, bad);
+            publish_stats_block(sStat, dmax, dmax, bad);
         } else {
             // k_prepass: in a 64-wide block reduction only lanes 0..15 of wave 0
             // hold values for ld = 64; their xor-32 and xor-16 partners hold
             // zeros, so those two butterfly levels are additions of +0.0
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t n = r0 + 16 * q;
+                const int n = r0 + 16 * q;
                 double sum = 0.0;
                 {
                     double wv[4], dv[4];
-                    load4(Wold + n * LD + c4, wv);
-                    load4(D + n * LD + c4, dv);
+                    load4(Wold + n * PW + c4, wv);
+                    load4(sD + n * PW + c4, dv);
                     sum += wv[0] * dv[0] + wv[1] * dv[1] + wv[2] * dv[2] + wv[3] * dv[3];
                 }
                 sum = sum + 0.0;
                 sum = sum + 0.0;
 #pragma unroll
                 for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-                if ((t & 15) == 0 && n < a.n) d[n] = (double)D[n * LD + n] + ((sum + 0.0) + (0.0 + 0.0));
+                if ((t & 15) == 0 && n < a.n) {
+                    const double dn = (double)sD[n * PW + n] + ((sum + 0.0) + (0.0 + 0.0));
+                    sd[n] = dn;
+                    d[n] = dn;
+                }
             }
             __syncthreads();  // d complete before the step reads it
-            step_tile<P, 64, 64, 16, 2, 2, S>(Wold, D, DT, Wold, Wnew, (__bf16 *)nullptr, as, 0, 0);
+            small_step_tile<S, PW>(Wold, sD, dT, dtp, Wnew, sd, sTh, a.n, a.lambda, sStat);
         }
-        __syncthreads();  // iterate s + 1 complete before the next step reads it
+        __syncthreads();  // iterate s + 1 and its statistics complete before they are stored and read
+        S *out = hist + (int64_t)s * LD * LD;
+        for (int i = t; i < LD * CPR; i += 256) {
+            const int row = i / CPR, col = (i % CPR) * VPC;
+            *reinterpret_cast<u32x4_t *>(&out[row * LD + col]) = *reinterpret_cast<const u32x4_t *>(&Wnew[row * PW + col]);
+        }
+        if (t == 0) {
+            unsigned long long *slot = stats + 2 * ((k0 + s) % kStatRing);
+            slot[0] = sStat[0];
+            slot[1] = sStat[1];
+            const double dl = __longlong_as_double((long long)sStat[0]);
+            const double wm = __longlong_as_double((long long)sStat[1]);
+            s_stop = !(dl <= DBL_MAX) || dl < stop_below || !(wm <= blowup);
+        }
+        __syncthreads();
+        if (s_stop) break;
     }
 }
 
@@ -1100,19 +1279,19 @@ hipError_t launch_gemm_nt_f64(const double *A, const double *B, double *C, int64
 
 hipError_t launch_small_steps_f32(const float *Wcur, float *hist, const float *D, const float *DT, const StepArgs &a,
                                   unsigned long long *stats, int64_t k0, int nsteps, int at_identity, double *d,
-                                  hipStream_t s) {
+                                  double stop_below, double blowup, hipStream_t s) {
     if (a.ld != 64 || nsteps < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_small_steps<PolF32, float>), dim3(1), dim3(256), 0, s, Wcur, hist, D, DT, a, stats, k0,
-                       nsteps, at_identity, d);
+    hipLaunchKernelGGL((k_small_steps<float>), dim3(1), dim3(256), 0, s, Wcur, hist, D, DT, a, stats, k0,
+                       nsteps, at_identity, d, stop_below, blowup);
     return hipGetLastError();
 }
 
 hipError_t launch_small_steps_f64(const double *Wcur, double *hist, const double *D, const double *DT,
                                   const StepArgs &a, unsigned long long *stats, int64_t k0, int nsteps,
-                                  int at_identity, double *d, hipStream_t s) {
+                                  int at_identity, double *d, double stop_below, double blowup, hipStream_t s) {
     if (a.ld != 64 || nsteps < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_small_steps<PolF64, double>), dim3(1), dim3(256), 0, s, Wcur, hist, D, DT, a, stats, k0,
-                       nsteps, at_identity, d);
+    hipLaunchKernelGGL((k_small_steps<double>), dim3(1), dim3(256), 0, s, Wcur, hist, D, DT, a, stats, k0,
+                       nsteps, at_identity, d, stop_below, blowup);
     return hipGetLastError();
 }
 

@@ -309,6 +309,8 @@ def test_unaligned_device_delta_is_copied_and_matches():
     (dpt.DPT_FP64, 33, False, 2.0, 1e-300, 37),  # slow contraction: the cap, over three batches
     (dpt.DPT_FP32, 50, False, 1.0, 1e-6, 200),
     (dpt.DPT_FP32, 64, True, 4.0, 1e-300, 20),   # the cap, over two batches
+    (dpt.DPT_FP64, 40, True, 6.0, 1e-12, 200),   # diverges inside the first batch (the batch ends there)
+    (dpt.DPT_FP32, 40, True, 6.0, 1e-6, 200),
 ])
 def test_small_problem_batches_equal_single_steps(precision, n, sym, lam, tol, max_iter):
     """Problems with padded order 64 run several steps per launch in dpt_solve;
@@ -317,6 +319,8 @@ def test_small_problem_batches_equal_single_steps(precision, n, sym, lam, tol, m
     theta, delta = small_problem(n, 14, symmetric=sym)
     d = delta if precision == dpt.DPT_FP64 else delta.astype(np.float32)
     _, res, e1, z1 = gpu_run(theta, d, lam, precision, tol=tol, max_iter=max_iter)
+    if lam == 6.0:
+        assert res["status"] == dpt.DPT_DIVERGED
     steps = res["iters"]
     assert (steps < 16) if tol > 1e-100 else (steps == max_iter)
     spec = dpt.ProblemSpec(theta, d, lam, stream=0)
