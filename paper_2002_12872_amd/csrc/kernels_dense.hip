@@ -1199,7 +1199,7 @@ hipError_t launch_prepass_f64_f64(const double *W, const double *D, const StepAr
 // everything else the 64x64 tiles.
 hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                             const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
-    if (Wbn && step_large_preferred(a.ld)) return launch_step_bf16_large(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
+    if (Wbn && step_large_preferred(a.ld, true)) return launch_step_bf16_large(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
     if (a.ld % 256 == 0 && a.ld >= 1024)
         return launch_gemm<PolBF16, 256, 128, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
     return launch_gemm<PolBF16, 64, 64, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
@@ -1214,16 +1214,17 @@ hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta
             return launch_gemm<PolF32, 128, 128, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
         return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
     }
-    if (!Wbn && step_large_preferred(a.ld)) return launch_step_f32_large(a, W, Delta, deltaT, Wn, s);
+    if (!Wbn && step_large_preferred(a.ld, false)) return launch_step_f32_large(a, W, Delta, deltaT, Wn, s);
     if (a.ld % 256 == 0 && a.ld >= 1024)
         return launch_gemm<PolF32, 128, 128, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
     return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
 }
 
-// FP64: from order 4096 on, 128 x 128 tiles of 8 waves (32 x 64 each, two
-// waves per SIMD) and K-tiles of 32 take 139 ms per step at N = 16384 against
-// 154 ms for the 64 x 64 tiles (4 waves, three workgroups per CU); below,
-// 128-wide tiles leave CUs idle.
+// FP64: from order 4096 on (a multiple of 128) the large-tile kernel of
+// kernels_gemm_f64.hip; with a row map, or at such orders that are not multiples
+// of 128, the general 128 x 128 tiles of 8 waves (32 x 64 each, two waves per
+// SIMD, K-tiles of 32: 139 ms per step at N = 16384 against 154 ms for 64 x 64
+// tiles); below 4096, 64 x 64 tiles (128-wide tiles leave CUs idle).
 hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT, double *Wn,
                            hipStream_t s) {
     if (!a.rowmap && step_f64_large_supported(a.ld)) return launch_step_f64_large(a, W, Delta, deltaT, Wn, s);

@@ -97,9 +97,11 @@ def _state_after(theta, delta32, lam, precision, k):
     return zk, zk1, ek1
 
 
-@pytest.mark.parametrize("n", [31, 64, 257, 1000, 1100, 4100])
+@pytest.mark.parametrize("n", [31, 64, 257, 1000, 1100, 4096, 4100])
 @pytest.mark.parametrize("sym", [False, True])
 def test_fp32_step_within_rounding_bound(n, sym):
+    """4096 runs the 256 x 256-tile FP32 step, 4100 (padded to 4352, a third of
+    a wave of those tiles) the general 128 x 128 one."""
     theta, delta = small_problem(n, 2, symmetric=sym)
     delta32 = delta.astype(np.float32)
     d64 = delta32.astype(np.float64)
@@ -112,9 +114,10 @@ def test_fp32_step_within_rounding_bound(n, sym):
         assert np.all(err <= bound), (k, float(np.max(err / bound)))
 
 
-@pytest.mark.parametrize("n", [31, 64, 257, 1000, 1100, 4100])
+@pytest.mark.parametrize("n", [31, 64, 257, 1000, 1100, 2048, 4100])
 @pytest.mark.parametrize("sym", [False, True])
 def test_bf16_step_within_rounding_bound(n, sym):
+    """2048 and 4100 (padded to 4352) run the 256 x 256-tile BF16 step."""
     theta, delta = small_problem(n, 3, symmetric=sym)
     delta32 = delta.astype(np.float32)
     d64 = delta32.astype(np.float64)
