@@ -125,9 +125,8 @@ hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *D
 // global->LDS ring.  Require ld % 256 == 0 and ld >= 1024; the BF16 one also
 // writes the BF16 shadow (Wbn != NULL).
 bool step_large_supported(int64_t ld);
-// Whether the BF16 (bf16 = true) / FP32 step uses them at this order (measured
-// against the general kernels).
-bool step_large_preferred(int64_t ld, bool bf16);
+// Whether the 256 x 256 tiles fill the chip at this order (ld >= 4096).
+bool step_large_preferred(int64_t ld);
 hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                                   const float *W, float *Wn, __bf16 *Wbn, hipStream_t s);
 // Split BF16 form (DPT_BF16_X3): operands ld x 2ld, A = [Wh | Wl], B = [Dh | Dl],

@@ -1195,11 +1195,25 @@ hipError_t launch_prepass_f64_f64(const double *W, const double *D, const StepAr
     return hipGetLastError();
 }
 
+// Whether a step uses the 256 x 256-tile kernels of kernels_gemm_large.hip
+// ((ld / 256)^2 workgroups, one per CU at a time over 256 CUs).  Measured
+// against the general 128 x 128 kernels on MI355X: the BF16 step is faster from
+// ld 2048 on (3072: 2.1x; the general BF16 tiles reach 12-15 % of the BF16
+// peak); the FP32 step is slower up to ld 3072, and above it wherever the last
+// wave of tiles is mostly empty (6144, 7168: 10-13 % slower; 4096, 5120, 10240:
+// as fast or faster), so FP32 takes it from ld 4096 when the waves of tiles are
+// at least 78 % full on average.
+static bool use_large_step(int64_t ld, bool bf16) {
+    if (bf16) return step_large_supported(ld) && ld >= 2048;
+    const int64_t tiles = (ld / 256) * (ld / 256), waves = (tiles + 255) / 256;
+    return step_large_preferred(ld) && tiles * 100 >= 78 * 256 * waves;
+}
+
 // Tile configurations: large problems (ld a multiple of 256) use the big tiles,
 // everything else the 64x64 tiles.
 hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                             const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
-    if (Wbn && step_large_preferred(a.ld, true)) return launch_step_bf16_large(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
+    if (Wbn && use_large_step(a.ld, true)) return launch_step_bf16_large(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
     if (a.ld % 256 == 0 && a.ld >= 1024)
         return launch_gemm<PolBF16, 256, 128, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
     return launch_gemm<PolBF16, 64, 64, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
@@ -1214,7 +1228,7 @@ hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta
             return launch_gemm<PolF32, 128, 128, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
         return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
     }
-    if (!Wbn && step_large_preferred(a.ld, false)) return launch_step_f32_large(a, W, Delta, deltaT, Wn, s);
+    if (!Wbn && use_large_step(a.ld, false)) return launch_step_f32_large(a, W, Delta, deltaT, Wn, s);
     if (a.ld % 256 == 0 && a.ld >= 1024)
         return launch_gemm<PolF32, 128, 128, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
     return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);

@@ -640,19 +640,10 @@ __global__ __launch_bounds__(256) void k_quant_fp8(const float *__restrict__ src
 
 bool step_large_supported(int64_t ld) { return ld % BM == 0 && ld % BN == 0 && ld >= 1024; }
 
-// The 256 x 256 tiles give (ld / 256)^2 workgroups, one per CU at a time
-// (256 CUs).  Measured against the general 128 x 128 kernels on MI355X: the
-// BF16 step is faster from ld 2048 on (3072: 2.1x; the general BF16 tiles reach
-// 12-15 % of the BF16 peak); the FP32 step is slower up to ld 3072, and above
-// it wherever the last wave of tiles is mostly empty (6144, 7168: 10-13 %
-// slower; 4096, 5120, 10240: as fast or faster), so FP32 takes it from ld 4096
-// when the waves of tiles are at least 78 % full on average.
-bool step_large_preferred(int64_t ld, bool bf16) {
-    if (!step_large_supported(ld)) return false;
-    if (bf16) return ld >= 2048;
-    const int64_t tiles = (ld / BM) * (ld / BN), waves = (tiles + 255) / 256;
-    return ld >= 4096 && tiles * 100 >= 78 * 256 * waves;
-}
+// The 256 x 256 tiles give (ld / 256)^2 workgroups, one per CU at a time: below
+// one full wave over the 256 CUs (ld < 4096) the 128-wide tiles of the
+// general kernels keep more of the chip busy.
+bool step_large_preferred(int64_t ld) { return step_large_supported(ld) && ld >= 4096; }
 
 hipError_t launch_step_bf16_large(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                                   const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
