@@ -845,8 +845,27 @@ __device__ __forceinline__ int find_segment(const int32_t *prefix, int cnt, int 
     return lo;
 }
 
+// sum_k w[k] dl[k] over a zero-padded row of ld (a multiple of 64) FP32 values,
+// in FP64, by one wave: lane l takes the 16-byte chunks l, l + 64, ... (four
+// products each, added in order), then a fixed butterfly.
+__device__ __forceinline__ double group_row_dot(const float *w, const float *dl, int64_t ld, int lane) {
+    const float4 *w4 = reinterpret_cast<const float4 *>(w);
+    const float4 *d4 = reinterpret_cast<const float4 *>(dl);
+    double sum = 0.0;
+    for (int64_t k = lane; k < ld / 4; k += 64) {
+        const float4 a = w4[k], b = d4[k];
+        sum += (double)a.x * (double)b.x;
+        sum += (double)a.y * (double)b.y;
+        sum += (double)a.z * (double)b.z;
+        sum += (double)a.w * (double)b.w;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    return sum;
+}
+
 // One wave per (request, row): d_n = Delta[n][n] + sum_k W[n][k] Delta[n][k] in
-// FP64 (fixed butterfly order); row 0 of every request clears its stats.
+// FP64 (group_row_dot); row 0 of every request clears its stats.
 __global__ __launch_bounds__(256) void k_group_prepass(const GroupTable *__restrict__ t) {
     const int nreq = t->counts[0];
     const int total = nreq > 0 ? t->pre_prefix[nreq] : 0;
@@ -858,10 +877,7 @@ __global__ __launch_bounds__(256) void k_group_prepass(const GroupTable *__restr
         const int64_t row = item - t->pre_prefix[r];
         const float *w = q.W + row * q.ld;
         const float *dl = q.D + row * q.ld;
-        double sum = 0.0;
-        for (int64_t k = lane; k < q.n; k += 64) sum += (double)w[k] * (double)dl[k];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+        const double sum = group_row_dot(w, dl, q.ld, lane);
         if (lane == 0) {
             q.d[row] = (double)dl[row] + sum;
             if (row == 0) {
@@ -896,7 +912,7 @@ __global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict
         a.d = q.d;
         a.stat = q.stat;
         if (PHASE == PH_BF16)
-            step_tile<PolBF16, BM, BN, 32, 2, 2, float>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
+            step_tile<PolBF16, BM, BN, 64, 2, 2, float>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
         else
             step_tile<PolF32, BM, BN, 16, 2, 2, float>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a, tm, tn);
     }
@@ -964,9 +980,9 @@ __global__ __launch_bounds__(256) void k_group_admit(const AdmitTable *__restric
     }
 }
 
-// Retirement: one wave per (request, row), the pre-pass sum in FP64 with the
-// fixed butterfly of k_group_prepass, then E_n = theta_n + lambda d_n; row 0
-// clears the request's stats.
+// Retirement: one wave per (request, row), the pre-pass sum of k_group_prepass
+// (group_row_dot), then E_n = theta_n + lambda d_n; row 0 clears the request's
+// stats.
 __global__ __launch_bounds__(256) void k_group_retire(const RetireTable *__restrict__ t) {
     const int nreq = t->count;
     const int total = nreq > 0 ? t->prefix[nreq] : 0;
@@ -976,14 +992,9 @@ __global__ __launch_bounds__(256) void k_group_retire(const RetireTable *__restr
         const int r = find_segment(t->prefix, nreq, item);
         const RetireReq &q = t->reqs[r];
         const int64_t row = item - t->prefix[r];
-        const float *w = q.W + row * q.ld;
-        const float *dl = q.D + row * q.ld;
-        double sum = 0.0;
-        for (int64_t k = lane; k < q.n; k += 64) sum += (double)w[k] * (double)dl[k];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+        const double sum = group_row_dot(q.W + row * q.ld, q.D + row * q.ld, q.ld, lane);
         if (lane == 0) {
-            q.E[row] = q.theta[row] + q.lambda * ((double)dl[row] + sum);
+            q.E[row] = q.theta[row] + q.lambda * ((double)q.D[row * q.ld + row] + sum);
             if (row == 0) {
                 q.stat[0] = 0ull;
                 q.stat[1] = 0ull;
@@ -1214,9 +1225,7 @@ static bool use_large_step(int64_t ld, bool bf16) {
 hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *Deltab, const float *deltaT,
                             const float *W, float *Wn, __bf16 *Wbn, hipStream_t s) {
     if (Wbn && use_large_step(a.ld, true)) return launch_step_bf16_large(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
-    if (a.ld % 256 == 0 && a.ld >= 1024)
-        return launch_gemm<PolBF16, 256, 128, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
-    return launch_gemm<PolBF16, 64, 64, 32, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
+    return launch_gemm<PolBF16, 64, 64, 64, 2, 2, float>(a, Wb, Deltab, deltaT, W, Wn, Wbn, s);
 }
 
 hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta, const float *deltaT, float *Wn,
