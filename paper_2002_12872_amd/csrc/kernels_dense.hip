@@ -914,7 +914,7 @@ __global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict
         if (PHASE == PH_BF16)
             step_tile<PolBF16, BM, BN, 64, 2, 2, float>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
         else
-            step_tile<PolF32, BM, BN, 16, 2, 2, float>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a, tm, tn);
+            step_tile<PolF32, BM, BN, 32, 2, 2, float>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a, tm, tn);
     }
 }
 
