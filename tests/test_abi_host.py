@@ -172,3 +172,17 @@ def test_missing_library_fails_loudly():
             "    print('raised', e)\n")
     p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
     assert p.returncode == 0 and p.stdout.startswith("raised"), p.stdout + p.stderr
+
+
+@pytest.mark.parametrize("kw", [dict(budget_bytes=0), dict(max_slots=0), dict(max_slots=1025),
+                                dict(grid_blocks=-1), dict(autotune=2), dict(autotune=-4)])
+def test_serve_open_rejects_bad_config_before_touching_device(kw):
+    """Config checks come before any runtime call (autotune: 1 tunes, 0 takes the
+    defaults, -1 / -2 / -3 force one tile shape; nothing else)."""
+    args = dict(budget_bytes=1 << 20, max_slots=4, use_graph=1, grid_blocks=0, autotune=0)
+    args.update(kw)
+    cfg = dpt.ServeConfig(args["budget_bytes"], args["max_slots"], args["use_graph"], args["grid_blocks"],
+                          args["autotune"], None)
+    h = ctypes.c_void_p()
+    assert dpt.load_library().dpt_serve_open(ctypes.byref(h), ctypes.byref(cfg)) == dpt.DPT_EINVAL
+    assert h.value is None
