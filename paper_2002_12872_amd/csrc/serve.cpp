@@ -2,16 +2,16 @@
 //
 // A worker thread owns one stream, a device arena of the configured budget
 // and a slot table.  Each engine step:
-//   1. admits waiting problems in FIFO order while the arena and the slots have
-//      room: one upload per host-submitted problem (theta and Delta staged
-//      together in a pinned ring), none for device-resident ones, then one
-//      grouped launch for all of them (padded FP32/BF16 copies, transpose, and
-//      the closed-form first iterate of eq. (dyn) of Kenmoe, Smerlak, Zadorin,
-//      arXiv:2002.12872, Sec. II.B);
-//   2. applies the map once to every other admitted problem: one persistent
+//   1. applies the map of eq. (dyn) (Kenmoe, Smerlak, Zadorin, arXiv:2002.12872,
+//      Sec. II.B) once to every problem admitted earlier: one persistent
 //      grouped pre-pass and one persistent grouped fused step per precision
 //      phase and tile shape over a device work table (a HIP graph replayed
 //      every step);
+//   2. meanwhile admits waiting problems in FIFO order while the arena and the
+//      slots have room: one upload per host-submitted problem (theta and Delta
+//      staged together in a pinned ring), none for device-resident ones, then
+//      one grouped launch for all of them (padded FP32/BF16 copies, transpose,
+//      and the closed-form first iterate);
 //   3. reads every problem's (delta, max|W|) back and runs its own controller
 //      (the same stopping rule as dpt_solve);
 //   4. retires finished problems with one grouped launch (eigenvalues into a
@@ -594,16 +594,17 @@ struct dpt_server_ctx {
         return r->ctl.status != DPT_NOT_CONVERGED || r->ctl.capped();
     }
 
-    hipError_t step() {
+    // Enqueues one application of the map to every admitted request past its
+    // first iterate: the work table's upload and the grouped launches.  The
+    // admissions of the same engine step are enqueued after it (their host
+    // work overlaps the grouped step) and finish_step reads both back.
+    hipError_t launch_step() {
         GroupTable &t = *table_h;
         int nreq = 0;
         int cnt[kGroupLists] = {};
         int32_t rows = 0, tiles_sum[kGroupLists] = {};
-        std::vector<Request *> stepping;
         for (Request *r : active) {
-            if (finished(r)) continue;  // e.g. max_iter = 0: retired without a step
-            stepping.push_back(r);
-            if (r->at_identity) continue;
+            if (finished(r) || r->at_identity) continue;  // finished: e.g. max_iter = 0, retired without a step
             const int nx = r->cur ^ 1;
             const bool bf = r->ctl.phase == PH_BF16;
             GroupReq &g = t.reqs[nreq];
@@ -635,15 +636,24 @@ struct dpt_server_ctx {
             t.prefix[L][cnt[L]] = tiles_sum[L];
             t.counts[1 + L] = cnt[L];
         }
-        // requests at the identity took their first iterate in the admission launch
         hipError_t e = hipSuccess;
         if (nreq > 0) {
             e = hipMemcpyAsync(table_d, table_h, offsetof(GroupTable, reqs) + (size_t)nreq * sizeof(GroupReq),
                                hipMemcpyHostToDevice, stream);
             if (e == hipSuccess) e = launch_grouped();
         }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(stats_h, stats_d, 16 * (size_t)cfg.max_slots, hipMemcpyDeviceToHost, stream);
+        return e;
+    }
+
+    // After launch_step and the admissions: the statistics of every request
+    // stepped or admitted (first iterate) in this engine step are read back with
+    // one copy and one synchronisation; the retirements enqueued before are
+    // handed out; each request's controller takes its step.
+    hipError_t finish_step() {
+        std::vector<Request *> stepping;  // the table's requests and the ones just admitted
+        for (Request *r : active)
+            if (!finished(r)) stepping.push_back(r);
+        hipError_t e = hipMemcpyAsync(stats_h, stats_d, 16 * (size_t)cfg.max_slots, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e == hipSuccess) idle_since_staged = true;
         if (e != hipSuccess) return e;
@@ -815,9 +825,10 @@ struct dpt_server_ctx {
                 }
             }
             const auto t_begin = std::chrono::steady_clock::now();
-            hipError_t e = admit();
+            hipError_t e = launch_step();
+            if (e == hipSuccess) e = admit();
             const bool any_step = std::any_of(active.begin(), active.end(), [&](Request *r) { return !finished(r); });
-            if (e == hipSuccess && any_step) e = step();  // synchronises and hands out earlier retirements
+            if (e == hipSuccess && any_step) e = finish_step();  // synchronises and hands out earlier retirements
             else if (e == hipSuccess) e = finish_retiring();
             if (e == hipSuccess) e = retire();
             if (e == hipSuccess && !staged.empty()) e = release_staged();
