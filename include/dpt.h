@@ -326,7 +326,11 @@ int dpt_profile_read(dpt_handle h, dpt_profile *out);
  * the next admissions).  Results do not depend on which other problems share
  * a step: every problem is computed with tiles chosen from its own padded
  * order and phase (a shape per padded-order class, fixed when the server
- * opens) and with its own statistics. */
+ * opens) and with its own statistics.  Besides the worker, a server keeps four
+ * host threads that stage large host submissions with the submitting thread.
+ * dpt_serve_submit, dpt_serve_poll and dpt_serve_stats_read may be called from
+ * several threads at once; dpt_serve_close must not overlap any other call on
+ * the same server. */
 typedef struct dpt_server_ctx *dpt_server;
 
 typedef struct dpt_serve_config {
