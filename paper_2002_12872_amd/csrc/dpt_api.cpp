@@ -198,6 +198,43 @@ SmallPool &small_pool() {
 
 void dfree(void *p) { small_pool().release(p); }
 
+// Pinned host blocks of kPinBlock bytes for the uploads of small host problems:
+// a copy from pinned memory is an asynchronous DMA, where one from pageable
+// memory is staged by the runtime and waits for it.  A handle takes a block at
+// dpt_init and gives it back once the stream has drained (the end of
+// dpt_init); blocks are kept until the process exits.
+constexpr size_t kPinBlock = (size_t)1 << 20;
+
+class PinPool {
+  public:
+    void *take() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (!free_.empty()) {
+                void *p = free_.back();
+                free_.pop_back();
+                return p;
+            }
+        }
+        void *p = nullptr;
+        return hipHostMalloc(&p, kPinBlock, 0) == hipSuccess ? p : nullptr;
+    }
+    void give(void *p) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.push_back(p);
+    }
+
+  private:
+    std::mutex mu_;
+    std::vector<void *> free_;
+};
+
+PinPool &pin_pool() {
+    static PinPool *pool = new PinPool();  // never destroyed, like the device pool
+    return *pool;
+}
+
 template <typename T>
 hipError_t dalloc(T **p, size_t count) {
     *p = nullptr;
@@ -321,6 +358,17 @@ struct dpt_ctx {
     SparseState *sp = nullptr;
     Profiler prof;
     void *small_hist = nullptr;  // iterates of one fused small-problem batch (ld = 64)
+    // pinned staging of a small host problem's uploads during dpt_init
+    unsigned char *pin = nullptr;
+    size_t pin_used = 0;
+    // kPinBlock bytes of pinned staging at pin + pin_used, or null
+    void *pin_space(size_t bytes) {
+        bytes = (bytes + 255) / 256 * 256;
+        if (!pin || pin_used + bytes > kPinBlock) return nullptr;
+        void *q = pin + pin_used;
+        pin_used += bytes;
+        return q;
+    }
 
     ~dpt_ctx() {
         if (sp) sparse_destroy(sp);
@@ -333,6 +381,7 @@ struct dpt_ctx {
         if (d32 && d32_own) dfree(d32);
         if (d64 && d64_own) dfree(d64);
         delete[] stats_host;
+        pin_pool().give(pin);  // the stream has drained: the destructor runs after a synchronisation
     }
 };
 
@@ -354,15 +403,22 @@ hipError_t stage_dense(dpt_ctx *c, const dpt_problem *p, T **dst, bool *own) {
     hipError_t e = dalloc(dst, (size_t)(ld * ld));
     if (e != hipSuccess) return e;
     *own = true;
-    // small host inputs: converted and padded on the host, one upload
+    // small host inputs: converted and padded on the host, one upload (from the
+    // handle's pinned block when it has room: no wait; dpt_init drains the
+    // stream before it returns)
     if (p->mem == DPT_MEM_HOST && (size_t)(ld * ld) * sizeof(T) <= ((size_t)16 << 20)) {
-        std::vector<T> hostpad((size_t)(ld * ld), (T)0);
+        const size_t count = (size_t)(ld * ld);
+        T *pinned = (T *)c->pin_space(count * sizeof(T));
+        std::vector<T> hostpad;
+        if (!pinned) hostpad.assign(count, (T)0);
+        T *hp = pinned ? pinned : hostpad.data();
+        if (pinned) std::memset(hp, 0, count * sizeof(T));
         for (int64_t i = 0; i < n; ++i)
             for (int64_t j = 0; j < n; ++j)
-                hostpad[(size_t)(i * ld + j)] = p->dtype == DPT_DTYPE_F64 ? (T)((const double *)p->delta)[i * n + j]
-                                                                         : (T)((const float *)p->delta)[i * n + j];
-        e = hipMemcpyAsync(*dst, hostpad.data(), hostpad.size() * sizeof(T), hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // hostpad is freed on return
+                hp[(size_t)(i * ld + j)] = p->dtype == DPT_DTYPE_F64 ? (T)((const double *)p->delta)[i * n + j]
+                                                                    : (T)((const float *)p->delta)[i * n + j];
+        e = hipMemcpyAsync(*dst, hp, count * sizeof(T), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && !pinned) e = hipStreamSynchronize(c->stream);  // hostpad is freed on return
         return e;
     }
     const void *src = p->delta;
@@ -1024,14 +1080,18 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
         return fail(DPT_ENOMEM);
     c->stats_host = new (std::nothrow) unsigned long long[2 * kStatRing];
     if (!c->stats_host) return fail(DPT_ENOMEM);
+    // small dense host problems upload theta and Delta from a pinned block
+    if (p->mem == DPT_MEM_HOST && p->format == DPT_DENSE && c->ld <= 256) c->pin = (unsigned char *)pin_pool().take();
     {
         const bool dev = p->mem == DPT_MEM_DEVICE;
+        double *thp = dev ? nullptr : (double *)c->pin_space(sizeof(double) * (size_t)c->ld);
+        if (thp) std::memcpy(thp, th.data(), sizeof(double) * (size_t)c->ld);
         void *zp[4] = {c->dvec, c->evec, c->stats, c->theta + c->n};
         const size_t zb[4] = {sizeof(double) * (size_t)c->ld, sizeof(double) * (size_t)c->ld,
                               sizeof(unsigned long long) * 2 * kStatRing, sizeof(double) * (size_t)(c->ld - c->n)};
         const int nz = dev && c->ld > c->n ? 4 : 3;  // the padding of a device-copied theta
         if (launch_zero_many(zp, zb, nz, c->stream) != hipSuccess ||
-            hipMemcpyAsync(c->theta, dev ? p->theta : (const void *)th.data(),
+            hipMemcpyAsync(c->theta, dev ? p->theta : thp ? (const void *)thp : (const void *)th.data(),
                            sizeof(double) * (size_t)(dev ? c->n : c->ld),
                            dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream) != hipSuccess)
             return fail(DPT_EDEVICE);
@@ -1047,6 +1107,9 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
     }
     if (rc != DPT_OK) return fail(rc);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(DPT_EDEVICE);
+    pin_pool().give(c->pin);  // its uploads are complete
+    c->pin = nullptr;
+    c->pin_used = 0;
     *h = c;
     return DPT_OK;
 }
@@ -1159,9 +1222,16 @@ int dpt_eigenvalues(dpt_handle h, double *E, int mem) {
     if (mem == DPT_MEM_DEVICE && !is_device_ptr(E)) return DPT_EINVAL;
     int rc = compute_eigenvalues(h);
     if (rc != DPT_OK) return rc;
-    DPT_TRY(hipMemcpyAsync(E, h->evec, sizeof(double) * (size_t)h->n,
-                           mem == DPT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
-    DPT_TRY(hipStreamSynchronize(h->stream));
+    const size_t bytes = sizeof(double) * (size_t)h->n;
+    // host output: through a pinned block when it fits (a pageable destination
+    // would make the runtime stage the copy)
+    void *bounce = mem == DPT_MEM_HOST && bytes <= kPinBlock ? pin_pool().take() : nullptr;
+    hipError_t e = hipMemcpyAsync(bounce ? bounce : (void *)E, h->evec, bytes,
+                                  mem == DPT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess && bounce) std::memcpy(E, bounce, bytes);
+    if (e == hipSuccess) pin_pool().give(bounce);  // drained; after a device error the block is not reused
+    DPT_TRY(e);
     return DPT_OK;
 }
 
