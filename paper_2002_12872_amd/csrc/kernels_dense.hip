@@ -1206,6 +1206,10 @@ hipError_t launch_prepass_f64_f64(const double *W, const double *D, const StepAr
     return hipGetLastError();
 }
 
+// A row-mapped step whose 128 x 128 tiles would not give each of the 256 CUs
+// one (few rows still running): the 64 x 64 tiles give four times as many.
+static bool few_row_tiles(const StepArgs &a) { return (a.rows / 128) * (a.ld / 128) < 256; }
+
 // Whether a step uses the 256 x 256-tile kernels of kernels_gemm_large.hip
 // ((ld / 256)^2 workgroups, one per CU at a time over 256 CUs).  Measured
 // against the general 128 x 128 kernels on MI355X: the BF16 step is faster from
@@ -1231,9 +1235,10 @@ hipError_t launch_step_bf16(const StepArgs &a, const __bf16 *Wb, const __bf16 *D
 hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta, const float *deltaT, float *Wn,
                            __bf16 *Wbn, hipStream_t s) {
     // a row map runs on the general kernel's 128-row tiles (the large kernel's
-    // direct-to-LDS loads assume contiguous tile rows)
+    // direct-to-LDS loads assume contiguous tile rows), or its 64-row tiles when
+    // 128-row ones would not give every CU a tile
     if (a.rowmap) {
-        if (row_tile(a.ld) == 128)
+        if (row_tile(a.ld) == 128 && !few_row_tiles(a))
             return launch_gemm<PolF32, 128, 128, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
         return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
     }
@@ -1244,13 +1249,16 @@ hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta
 }
 
 // FP64: from order 4096 on (a multiple of 128) the large-tile kernel of
-// kernels_gemm_f64.hip; with a row map, or at such orders that are not multiples
-// of 128, the general 128 x 128 tiles of 8 waves (32 x 64 each, two waves per
-// SIMD, K-tiles of 32: 139 ms per step at N = 16384 against 154 ms for 64 x 64
-// tiles); below 4096, 64 x 64 tiles (128-wide tiles leave CUs idle).
+// kernels_gemm_f64.hip, with or without a row map; at such orders that are not
+// multiples of 128 the general 128 x 128 tiles of 8 waves (32 x 64 each, two
+// waves per SIMD, K-tiles of 32: 139 ms per step at N = 16384 against 154 ms for
+// 64 x 64 tiles), or their row-mapped form; below 4096, 64 x 64 tiles (128-wide
+// tiles leave CUs idle).
 hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT, double *Wn,
                            hipStream_t s) {
-    if (!a.rowmap && step_f64_large_supported(a.ld)) return launch_step_f64_large(a, W, Delta, deltaT, Wn, s);
+    if (a.rowmap && few_row_tiles(a))  // the last running rows: 64-row tiles, four times as many workgroups
+        return launch_gemm<PolF64, 64, 64, 16, 2, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
+    if (step_f64_large_supported(a.ld)) return launch_step_f64_large(a, W, Delta, deltaT, Wn, s);
     if ((a.ld >= 4096 || a.rowmap) && row_tile(a.ld) == 128)
         return launch_gemm<PolF64, 128, 128, 32, 4, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
     return launch_gemm<PolF64, 64, 64, 16, 2, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);

@@ -65,21 +65,29 @@ __device__ __forceinline__ void barrier_keep_loads() { asm volatile("s_barrier" 
 // rows [32w, 32w + 32), 8 rows per instruction; lane L lands at byte 16 L of
 // the instruction's 1 KiB: row 8i + (L >> 3) of the instruction's rows,
 // physical slot L & 7, so it reads logical chunk (L & 7) ^ key8(row), and
-// key8(32w + 8i + lr) = lr ^ ((4w + i) & 7).
+// key8(32w + 8i + lr) = lr ^ ((4w + i) & 7).  Each lane keeps the source of
+// its A rows, so with a row map tile row r reads W row rowmap[row0 + r] (a
+// padding entry, -1, reads row 0, whose products are not stored).
 struct Loader {
-    const unsigned char *ga, *gb;
+    const unsigned char *pa[A_LOADS];
+    const unsigned char *gb;
     int64_t ldb;
     int lane_off;
     int wave;
 
-    __device__ void init(const double *A, const double *B, int64_t row0, int64_t col0, int64_t ld_bytes, int w,
-                         int lane) {
+    __device__ void init(const double *A, const double *B, const int32_t *rowmap, int64_t row0, int64_t col0,
+                         int64_t ld_bytes, int w, int lane) {
         ldb = ld_bytes;
         wave = w;
-        ga = (const unsigned char *)A + (row0 + 32 * w) * ldb;
         gb = (const unsigned char *)B + (col0 + 32 * w) * ldb;
         const int lr = lane >> 3;
         lane_off = lr * (int)ldb + (((lane & 7) ^ lr) << 4);
+#pragma unroll
+        for (int i = 0; i < A_LOADS; ++i) {
+            int64_t r = row0 + 32 * w + 8 * i + lr;
+            if (rowmap) r = max(rowmap[r], 0);
+            pa[i] = (const unsigned char *)A + r * ldb + ((((lane & 7) ^ lr) ^ ((4 * w + i) & 7)) << 4);
+        }
     }
     __device__ __forceinline__ void issue(unsigned char *smem, int kt, int slot) const {
         unsigned char *sa = smem + slot * STAGE + 32 * wave * ROW;
@@ -87,9 +95,7 @@ struct Loader {
         const int64_t ko = (int64_t)kt * ROW;
 #pragma unroll
         for (int i = 0; i < A_LOADS; ++i)
-            __builtin_amdgcn_global_load_lds(
-                (gbl_void *)(ga + ko + 8 * i * ldb + (lane_off ^ (((4 * wave + i) & 7) << 4))),
-                (lds_void *)(sa + i * 8 * ROW), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((gbl_void *)(pa[i] + ko), (lds_void *)(sa + i * 8 * ROW), 16, 0, 0);
 #pragma unroll
         for (int i = 0; i < B_LOADS; ++i)
             __builtin_amdgcn_global_load_lds(
@@ -111,7 +117,7 @@ __global__ __launch_bounds__(NT, 2) void k_step_f64_large(const double *__restri
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave / WN, wc = wave % WN;
     Loader ld;
-    ld.init(A, B, row0, col0, a.ld * 8, wave, lane);
+    ld.init(A, B, a.rowmap, row0, col0, a.ld * 8, wave, lane);
 
     doublex4_t acc[TM][TN];
 #pragma unroll
@@ -208,7 +214,12 @@ __global__ __launch_bounds__(NT, 2) void k_step_f64_large(const double *__restri
 #pragma unroll 4
         for (int k = 0; k < 16; ++k) {
             const int row = wave + 4 * k;
-            const int64_t n = row0 + 64 * p + row, idx = n * ldd + m0;
+            int64_t n = row0 + 64 * p + row;
+            if (a.rowmap) {
+                n = a.rowmap[n];
+                if (n < 0) continue;  // padding of the row list
+            }
+            const int64_t idx = n * ldd + m0;
             const f64x2 dt = *reinterpret_cast<const f64x2 *>(&deltaT[idx]);
             const f64x2 wo = *reinterpret_cast<const f64x2 *>(&Wold[idx]);
             const f64x2 cv = *reinterpret_cast<const f64x2 *>(&tile[row * TP + c2]);
@@ -234,10 +245,13 @@ __global__ __launch_bounds__(NT, 2) void k_step_f64_large(const double *__restri
 
 bool step_f64_large_supported(int64_t ld) { return ld % BM == 0 && ld % BN == 0 && ld >= 4096; }
 
+// With a row map (a.rows entries, a multiple of BM) the tile rows run over the
+// listed W rows only.
 hipError_t launch_step_f64_large(const StepArgs &a, const double *W, const double *Delta, const double *deltaT,
                                  double *Wn, hipStream_t s) {
-    if (!step_f64_large_supported(a.ld) || a.rowmap) return hipErrorInvalidValue;
-    const int tiles_m = (int)(a.ld / BM), tiles_n = (int)(a.ld / BN);
+    if (!step_f64_large_supported(a.ld) || (a.rowmap && (a.rows < BM || a.rows % BM != 0 || a.rows > a.ld)))
+        return hipErrorInvalidValue;
+    const int tiles_m = (int)((a.rowmap ? a.rows : a.ld) / BM), tiles_n = (int)(a.ld / BN);
     hipLaunchKernelGGL(k_step_f64_large, dim3((unsigned int)(tiles_m * tiles_n)), dim3(NT), 0, s, W, Delta, deltaT,
                        W, Wn, a, tiles_m, tiles_n);
     return hipGetLastError();

@@ -44,6 +44,23 @@ def test_fp64_rows_freeze_on_the_oracle_step(n):
         assert rows_mult < ld * (res["iters"] - 1)      # products skipped frozen rows
 
 
+def test_fp64_rows_on_the_large_tile_kernel():
+    """Order 4100 (padded to 4352) runs the row-mapped steps on the large-tile
+    FP64 kernel: sampled rows freeze on the oracle's step and equal its rows."""
+    n = 4100
+    theta, delta = workloads.delta_potential(n)
+    h, res = row_solve(theta, delta, 1.0, dpt.DPT_FP64, 1e-12)
+    assert res["status"] == dpt.DPT_OK
+    rows = workloads.sample_rows(n, 40)
+    ref = oracle.iterate(theta, delta, 1.0, rows=rows, max_iter=200, tol=1e-12, per_row=True)
+    at, rows_mult = dpt.dpt_row_status(h)
+    assert np.array_equal(at[rows], ref["row_iters"])
+    assert len(set(at.tolist())) > 2 and rows_mult < 4352 * (res["iters"] - 1)
+    z = dpt.dpt_eigenvectors(h)[rows]
+    assert np.max(np.abs(z - ref["z"])) <= 1e-12 * max(1.0, np.abs(ref["z"]).max())
+    assert rel_eig_error(dpt.dpt_eigenvalues(h)[rows], ref["e"], theta) <= 1e-12
+
+
 def test_frozen_rows_stay_bitwise_and_running_rows_continue():
     n = 1100
     theta, delta = workloads.delta_potential(n)
