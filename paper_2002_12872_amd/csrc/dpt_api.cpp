@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <atomic>
 #include <cstdint>
 #include <cmath>
@@ -207,6 +208,7 @@ constexpr size_t kPinBlock = (size_t)1 << 20;
 
 class PinPool {
   public:
+    explicit PinPool(size_t block) : block_(block) {}
     void *take() {
         {
             std::lock_guard<std::mutex> lk(mu_);
@@ -217,7 +219,7 @@ class PinPool {
             }
         }
         void *p = nullptr;
-        return hipHostMalloc(&p, kPinBlock, 0) == hipSuccess ? p : nullptr;
+        return hipHostMalloc(&p, block_, 0) == hipSuccess ? p : nullptr;
     }
     void give(void *p) {
         if (!p) return;
@@ -226,12 +228,21 @@ class PinPool {
     }
 
   private:
+    size_t block_;
     std::mutex mu_;
     std::vector<void *> free_;
 };
 
 PinPool &pin_pool() {
-    static PinPool *pool = new PinPool();  // never destroyed, like the device pool
+    static PinPool *pool = new PinPool(kPinBlock);  // never destroyed, like the device pool
+    return *pool;
+}
+
+// The pinned host mirrors of the handles' statistics rings (one block per live
+// handle: read-backs into pinned memory are plain DMAs).
+constexpr size_t kStatMirrorBytes = sizeof(unsigned long long) * 2 * kStatRing;
+PinPool &stat_mirror_pool() {
+    static PinPool *pool = new PinPool(kStatMirrorBytes);
     return *pool;
 }
 
@@ -380,7 +391,7 @@ struct dpt_ctx {
         if (dT64 && dT64 != d64) dfree(dT64);
         if (d32 && d32_own) dfree(d32);
         if (d64 && d64_own) dfree(d64);
-        delete[] stats_host;
+        stat_mirror_pool().give(stats_host);  // the stream has drained (see below)
         pin_pool().give(pin);  // the stream has drained: the destructor runs after a synchronisation
     }
 };
@@ -716,6 +727,17 @@ int small_batch(dpt_ctx *c, Controller &ctl, dpt_result *r, int64_t consumed, in
     DPT_TRY(e);
     int rc = fetch_stats(c, c->k, c->k + m);
     if (rc != DPT_OK) return rc;
+    // the steps the kernel computed: it ends after the first step meeting its
+    // exit test (same values, same test)
+    int computed = m;
+    for (int s = 0; s < m; ++s) {
+        double dl, wm;
+        stat_of(c, c->k + s, &dl, &wm);
+        if (!(dl <= DBL_MAX) || dl < target || !(wm <= c->opt.blowup)) {
+            computed = s + 1;
+            break;
+        }
+    }
     int j = 0;
     Controller::Action last = Controller::CONTINUE;
     while (j < m) {
@@ -727,10 +749,13 @@ int small_batch(dpt_ctx *c, Controller &ctl, dpt_result *r, int64_t consumed, in
         last = ctl.update(dl, wm);
         if (last != Controller::CONTINUE || ctl.capped()) break;
     }
-    // the state becomes iterate j of the batch
-    void *dst = f64 ? (void *)c->W64[c->cur] : (void *)c->W32[c->cur];
-    DPT_TRY(hipMemcpyAsync(dst, (const unsigned char *)c->small_hist + (size_t)(j - 1) * l2 * esz, l2 * esz,
-                           hipMemcpyDeviceToDevice, c->stream));
+    // the state becomes iterate j of the batch (the kernel left the last one it
+    // computed there)
+    if (j != computed) {
+        void *dst = f64 ? (void *)c->W64[c->cur] : (void *)c->W32[c->cur];
+        DPT_TRY(hipMemcpyAsync(dst, (const unsigned char *)c->small_hist + (size_t)(j - 1) * l2 * esz, l2 * esz,
+                               hipMemcpyDeviceToDevice, c->stream));
+    }
     c->k += j;
     c->at_identity = false;
     *taken = j;
@@ -1078,7 +1103,7 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
     if (dalloc(&c->theta, (size_t)c->ld) != hipSuccess || dalloc(&c->dvec, (size_t)c->ld) != hipSuccess ||
         dalloc(&c->evec, (size_t)c->ld) != hipSuccess || dalloc(&c->stats, (size_t)2 * kStatRing) != hipSuccess)
         return fail(DPT_ENOMEM);
-    c->stats_host = new (std::nothrow) unsigned long long[2 * kStatRing];
+    c->stats_host = (unsigned long long *)stat_mirror_pool().take();
     if (!c->stats_host) return fail(DPT_ENOMEM);
     // small dense host problems upload theta and Delta from a pinned block
     if (p->mem == DPT_MEM_HOST && p->format == DPT_DENSE && c->ld <= 256) c->pin = (unsigned char *)pin_pool().take();

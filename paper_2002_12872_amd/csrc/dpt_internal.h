@@ -95,11 +95,12 @@ hipError_t launch_symmetry_check_f64(const double *src, int64_t ld, unsigned int
 // Up to nsteps steps of a dense problem with ld = 64 in one workgroup: iterate
 // s + 1 into hist + s * 64 * 64, its statistics into ring slot (k0 + s) mod
 // kStatRing (first step in closed form when at_identity).  The batch ends after
-// a step with delta < stop_below, a non-finite delta or max|W| > blowup.
-hipError_t launch_small_steps_f32(const float *Wcur, float *hist, const float *D, const float *DT, const StepArgs &a,
+// a step with delta < stop_below, a non-finite delta or max|W| > blowup; the
+// last iterate computed is also written over Wcur.
+hipError_t launch_small_steps_f32(float *Wcur, float *hist, const float *D, const float *DT, const StepArgs &a,
                                   unsigned long long *stats, int64_t k0, int nsteps, int at_identity, double *d,
                                   double stop_below, double blowup, hipStream_t s);
-hipError_t launch_small_steps_f64(const double *Wcur, double *hist, const double *D, const double *DT,
+hipError_t launch_small_steps_f64(double *Wcur, double *hist, const double *D, const double *DT,
                                   const StepArgs &a, unsigned long long *stats, int64_t k0, int nsteps,
                                   int at_identity, double *d, double stop_below, double blowup, hipStream_t s);
 hipError_t launch_first_iterate_f32(const StepArgs &a, const float *deltaT, float *W, __bf16 *Wb, hipStream_t s);

@@ -722,9 +722,10 @@ __device__ __forceinline__ void small_step_tile(const S *Wold, const S *Dl, cons
 // The host picks the iterate its stopping rule ends on (the later ones are
 // discarded); the batch ends early after a step whose delta is below stop_below
 // or not finite, or whose max|W| exceeds blowup: the host's rule ends there or
-// earlier.
+// earlier.  The last iterate computed also replaces the state in Wcur (the host
+// copies an earlier one from hist when its rule ends before).
 template <typename S>
-__global__ __launch_bounds__(256) void k_small_steps(const S *__restrict__ Wcur, S *__restrict__ hist,
+__global__ __launch_bounds__(256) void k_small_steps(S *__restrict__ Wcur, S *__restrict__ hist,
                                                      const S *__restrict__ D, const S *__restrict__ DT, StepArgs a,
                                                      unsigned long long *__restrict__ stats, int64_t k0, int nsteps,
                                                      int at_identity, double *__restrict__ d, double stop_below,
@@ -754,6 +755,7 @@ __global__ __launch_bounds__(256) void k_small_steps(const S *__restrict__ Wcur,
     // unsymmetric Delta^T, read from global memory (cached)
     const S *dT = dt_is_d ? (const S *)sD : (sizeof(S) == 4 ? (const S *)sDT : DT);
     const int dtp = (dt_is_d || sizeof(S) == 4) ? PW : LD;
+    int done = 0;
     for (int s = 0; s < nsteps; ++s) {
         const S *Wold = sW[s & 1];
         S *Wnew = sW[(s + 1) & 1];
@@ -827,7 +829,13 @@ __global__ __launch_bounds__(256) void k_small_steps(const S *__restrict__ Wcur,
             s_stop = !(dl <= DBL_MAX) || dl < stop_below || !(wm <= blowup);
         }
         __syncthreads();
+        done = s + 1;
         if (s_stop) break;
+    }
+    const S *last = sW[done & 1];
+    for (int i = t; i < LD * CPR; i += 256) {
+        const int row = i / CPR, col = (i % CPR) * VPC;
+        *reinterpret_cast<u32x4_t *>(&Wcur[row * LD + col]) = *reinterpret_cast<const u32x4_t *>(&last[row * PW + col]);
     }
 }
 
@@ -1309,7 +1317,7 @@ hipError_t launch_gemm_nt_f64(const double *A, const double *B, double *C, int64
     return hipGetLastError();
 }
 
-hipError_t launch_small_steps_f32(const float *Wcur, float *hist, const float *D, const float *DT, const StepArgs &a,
+hipError_t launch_small_steps_f32(float *Wcur, float *hist, const float *D, const float *DT, const StepArgs &a,
                                   unsigned long long *stats, int64_t k0, int nsteps, int at_identity, double *d,
                                   double stop_below, double blowup, hipStream_t s) {
     if (a.ld != 64 || nsteps < 1) return hipErrorInvalidValue;
@@ -1318,7 +1326,7 @@ hipError_t launch_small_steps_f32(const float *Wcur, float *hist, const float *D
     return hipGetLastError();
 }
 
-hipError_t launch_small_steps_f64(const double *Wcur, double *hist, const double *D, const double *DT,
+hipError_t launch_small_steps_f64(double *Wcur, double *hist, const double *D, const double *DT,
                                   const StepArgs &a, unsigned long long *stats, int64_t k0, int nsteps,
                                   int at_identity, double *d, double stop_below, double blowup, hipStream_t s) {
     if (a.ld != 64 || nsteps < 1) return hipErrorInvalidValue;
