@@ -1014,6 +1014,8 @@ int compute_eigenvalues(dpt_ctx *c) {
 // ============================================================== C ABI
 namespace dpt {
 bool host_theta_ok(const double *theta, int64_t n) { return theta_ok(theta, n); }
+void *pinned_block_take() { return stat_mirror_pool().take(); }
+void pinned_block_give(void *p) { stat_mirror_pool().give(p); }
 bool inputs_on_device(const dpt_problem *p) { return p->mem == DPT_MEM_DEVICE && device_inputs_ok(p, nullptr); }
 }  // namespace dpt
 
@@ -1343,12 +1345,7 @@ int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, doub
     }
     // the single-line map divides only by theta_index - theta_m: theta_index must
     // be simple, other values may coincide (Sec. II.H)
-    if (p->mem == DPT_MEM_DEVICE) {
-        double th_index = 0.0;
-        rc = dominant_theta_check_device(p->theta, p->n, &index, &th_index, (hipStream_t)p->stream);
-        if (rc != DPT_OK) return rc;
-        return dominant_solve(p, &opt, nullptr, th_index, index, eigval, eigvec, r);
-    }
+    if (p->mem == DPT_MEM_DEVICE) return dominant_solve_device(p, &opt, index, eigval, eigvec, r);
     const double *th = p->theta;
     for (int64_t m = 0; m < p->n; ++m)
         if (!std::isfinite(th[m])) return DPT_EINVAL;

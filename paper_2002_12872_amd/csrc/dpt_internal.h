@@ -252,6 +252,12 @@ hipError_t launch_group_admit(const AdmitTable *t, int grid, hipStream_t s);
 // finite and pairwise distinct (host array); theta and Delta of a DPT_MEM_DEVICE
 // dense problem are device allocations.
 bool host_theta_ok(const double *theta, int64_t n);
+// Pinned host blocks of at least 64 KiB, recycled across calls (dpt_api.cpp):
+// read-back destinations that make device-to-host copies plain DMAs.  take()
+// returns null when none can be allocated; give back only after the stream
+// that used the block has drained.
+void *pinned_block_take();
+void pinned_block_give(void *p);
 bool inputs_on_device(const dpt_problem *p);
 hipError_t launch_group_retire(const RetireTable *t, int grid, hipStream_t s);
 

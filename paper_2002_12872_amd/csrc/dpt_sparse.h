@@ -64,11 +64,12 @@ constexpr size_t kNoallocVectorBytes = (size_t)64 << 20;
 int dominant_solve_noalloc(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval, void *eigvec,
                            dpt_result *r);
 
-// Checks of a device-resident theta for the dominant mode without copying it to
-// the host: all values finite and theta[*index] occurring once; *index < 0 is
-// replaced by the first index of the largest value.  *theta_index receives the
-// value.  Returns DPT_OK, DPT_EINVAL or a device error.
-int dominant_theta_check_device(const double *theta, int64_t n, int64_t *index, double *theta_index,
-                                hipStream_t s);
+// The dominant mode for device-resident inputs: theta is checked on the device
+// (all values finite, theta[index] occurring once; index < 0 selects the first
+// index of the largest value) together with the CSR structure, read back with
+// one synchronisation, then the solve as dominant_solve.  Returns what
+// dominant_solve returns, or DPT_EINVAL for a bad theta or structure.
+int dominant_solve_device(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval, void *eigvec,
+                          dpt_result *r);
 
 }  // namespace dpt

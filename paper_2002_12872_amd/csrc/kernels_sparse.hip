@@ -615,7 +615,7 @@ int validate_device_csr(const dpt_problem *p, unsigned int *flag, hipStream_t s)
 // Returns DPT_OK, DPT_EINVAL (bad structure) or a device error code; on
 // failure nothing stays allocated.
 template <typename T>
-int stage_csr(const dpt_problem *p, DevCsr<T> *c, hipStream_t s) {
+int stage_csr(const dpt_problem *p, DevCsr<T> *c, hipStream_t s, bool validated = false) {
     const int64_t n = p->n, nnz = p->nnz;
     const bool vals64 = p->dtype == DPT_DTYPE_F64;
     const size_t in_b = (size_t)std::max<int64_t>(1, nnz) * (vals64 ? 8 : 4);
@@ -636,12 +636,14 @@ int stage_csr(const dpt_problem *p, DevCsr<T> *c, hipStream_t s) {
     } else {
         c->rowptr = p->indptr;
         c->col = p->indices;
-        unsigned int *flag = nullptr;
-        e = hipMalloc((void **)&flag, sizeof(unsigned int));
-        if (e == hipSuccess) {
-            const int rc = validate_device_csr(p, flag, s);
-            (void)hipFree(flag);
-            if (rc != DPT_OK) return rc;
+        if (!validated) {
+            unsigned int *flag = nullptr;
+            e = hipMalloc((void **)&flag, sizeof(unsigned int));
+            if (e == hipSuccess) {
+                const int rc = validate_device_csr(p, flag, s);
+                (void)hipFree(flag);
+                if (rc != DPT_OK) return rc;
+            }
         }
         if (e == hipSuccess && vals64 == (sizeof(T) == 8)) {
             c->val = (const T *)p->delta;  // borrowed
@@ -909,15 +911,27 @@ struct DomOutcome {
 // caller provides (allocates nothing).  `val` holds the CSR values, or the
 // n x n row-major matrix when rowptr is NULL.  The eigenvector goes to the
 // device array dst (dtype out64 ? double : float); *eigval gets
-// theta_star + lambda (Delta z)[nstar] of the returned iterate.
+// theta_star + lambda (Delta z)[nstar] of the returned iterate.  Each iteration
+// ends with (Delta z)[nstar] of its new iterate (the next iteration's scalar, and
+// the eigenvalue if the iteration is the last), read back with its statistics
+// in one synchronisation; host_words (three words, pinned) receives them, or a
+// local array when it is null.
 template <typename T>
 hipError_t dominant_iterate(const dpt_problem *p, const dpt_options *o, const int64_t *rowptr, const int *col,
                             const T *val, const double *theta, double theta_star, int64_t nstar,
                             const DomBuffers<T> &b, int cap, void *dst, bool out64, double *eigval,
-                            DomOutcome *out, dpt_result *r, hipStream_t s) {
+                            DomOutcome *out, dpt_result *r, hipStream_t s,
+                            unsigned long long *host_words = nullptr) {
     const int64_t n = p->n;
     const bool csr = rowptr != nullptr;
-    unsigned long long hs[2] = {0ull, 0ull};
+    unsigned long long local[3] = {0ull, 0ull, 0ull};
+    unsigned long long *hs = host_words ? host_words : local;
+    auto row_dot = [&](const T *z) {
+        if (csr)
+            hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, rowptr, col, val, nstar, z, b.s);
+        else
+            hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, val, n, nstar, z, b.s);
+    };
     hipLaunchKernelGGL((k_zero<unsigned long long>), dim3(blocks_for(2 * (int64_t)cap, 256)), dim3(256), 0, s,
                        b.stats, (int64_t)2 * cap);
     hipLaunchKernelGGL((k_zero<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, b.z[0], n);
@@ -946,19 +960,17 @@ hipError_t dominant_iterate(const dpt_problem *p, const dpt_options *o, const in
                 hipLaunchKernelGGL((k_dom_first<T, false>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
                                    (const int64_t *)nullptr, (const int *)nullptr, val, n, nstar, lam, theta,
                                    b.z[cur ^ 1], st);
-        } else if (csr) {
-            hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, rowptr, col, val, nstar,
-                               (const T *)b.z[cur], b.s);
+        } else if (csr) {  // b.s = (Delta z)[nstar] of z[cur], from the end of the previous iteration
             hipLaunchKernelGGL((k_dom_csr<T>), dim3(blocks_for(n, 32, kDomGrid)), dim3(256), 0, s, rowptr, col, val,
                                n, nstar, lam, theta, (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
         } else {
-            hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, val, n, nstar, (const T *)b.z[cur],
-                               b.s);
             hipLaunchKernelGGL((k_dom_dense<T>), dim3(blocks_for(n, 4)), dim3(256), 0, s, val, n, nstar, lam, theta,
                                (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
         }
+        row_dot((const T *)b.z[cur ^ 1]);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(hs, st, 16, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hs + 2, b.s, 8, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
         cur ^= 1;
@@ -975,18 +987,16 @@ hipError_t dominant_iterate(const dpt_problem *p, const dpt_options *o, const in
             break;
         }
     }
-    // eigenvalue readout from the returned iterate
-    if (csr)
-        hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, rowptr, col, val, nstar, (const T *)b.z[cur],
-                           b.s);
-    else
-        hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, val, n, nstar, (const T *)b.z[cur], b.s);
-    double sv = 0.0;
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&sv, b.s, sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    *eigval = theta_star + p->lambda * sv;
+    // eigenvalue readout from the returned iterate: read back with the last
+    // iteration, or (no iteration) from e_nstar
+    if (out->iters == 0) {
+        row_dot((const T *)b.z[cur]);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(hs + 2, b.s, 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+    }
+    *eigval = theta_star + p->lambda * bits_to_double(hs[2]);
     if (out64)
         hipLaunchKernelGGL((k_convert<T, double>), dim3(blocks_for(n, 256)), dim3(256), 0, s, (const T *)b.z[cur],
                            (double *)dst, n);
@@ -1008,7 +1018,7 @@ void fill_dom_result(dpt_result *r, const DomOutcome &out, bool fp64) {
 
 template <typename T>
 int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_host, double theta_star,
-               int64_t nstar, double *eigval, void *eigvec, dpt_result *r) {
+               int64_t nstar, double *eigval, void *eigvec, dpt_result *r, bool csr_validated = false) {
     const int64_t n = p->n;
     hipStream_t s = (hipStream_t)p->stream;
     int rc = DPT_OK;
@@ -1020,10 +1030,11 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
     void *out_tmp = nullptr;
     const int cap = std::max(1, o->max_iter);
     DomOutcome out;
+    unsigned long long *words = (unsigned long long *)pinned_block_take();  // read-backs (null: pageable)
     auto run = [&]() -> hipError_t {
         hipError_t e;
         if (p->format == DPT_CSR) {
-            rc = stage_csr(p, &csr, s);
+            rc = stage_csr(p, &csr, s, csr_validated);
             if (rc != DPT_OK) return hipSuccess;
         } else {
             const size_t nn = (size_t)(n * n);
@@ -1078,13 +1089,14 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
         const bool is_csr = p->format == DPT_CSR;
         e = dominant_iterate<T>(p, o, is_csr ? csr.rowptr : nullptr, is_csr ? csr.col : nullptr,
                                 is_csr ? csr.val : (const T *)dense, theta, theta_star, nstar, b, cap, dst, out64,
-                                eigval, &out, r, s);
+                                eigval, &out, r, s, words);
         if (e == hipSuccess && out_tmp) e = hipMemcpyAsync(eigvec, out_tmp, ob, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         return e;
     };
     hipError_t e = run();
-    (void)hipStreamSynchronize(s);
+    const hipError_t es = hipStreamSynchronize(s);
+    if (es == hipSuccess) pinned_block_give(words);  // drained; after a device error the block is not reused
     csr.release();
     if (val) (void)hipFree(val);
     for (int i = 0; i < 2; ++i)
@@ -1099,23 +1111,33 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
     return out.status;
 }
 
-// Device-side theta checks into the caller's ThetaScan (allocates nothing).
-int theta_check_into(const double *theta, int64_t n, int64_t *index, double *theta_index, ThetaScan *sc,
-                     hipStream_t s) {
-    ThetaScan h{};
+// Device-side theta checks into the caller's ThetaScan: the launches, then the
+// verdict on the scan read back.
+void theta_check_enqueue(const double *theta, int64_t n, int64_t index, ThetaScan *sc, hipStream_t s) {
     const unsigned int g = blocks_for(n, 256, 1024);
-    hipLaunchKernelGGL(k_theta_scan_init, dim3(1), dim3(64), 0, s, sc, n, *index);
+    hipLaunchKernelGGL(k_theta_scan_init, dim3(1), dim3(64), 0, s, sc, n, index);
     hipLaunchKernelGGL(k_theta_max, dim3(g), dim3(256), 0, s, theta, n, sc);
-    hipLaunchKernelGGL(k_theta_argmax, dim3(g), dim3(256), 0, s, theta, n, sc, *index);
+    hipLaunchKernelGGL(k_theta_argmax, dim3(g), dim3(256), 0, s, theta, n, sc, index);
     hipLaunchKernelGGL(k_theta_count, dim3(g), dim3(256), 0, s, theta, n, sc);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, sc, sizeof(h), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return err_code(e);
+}
+
+int theta_check_verdict(const ThetaScan &h, int64_t n, int64_t *index, double *theta_index) {
     if (h.bad || h.index >= (unsigned long long)n || h.count != 1) return DPT_EINVAL;
     *index = (int64_t)h.index;
     *theta_index = bits_to_double(h.value_bits);
     return DPT_OK;
+}
+
+// The checks with their own synchronisation (allocates nothing).
+int theta_check_into(const double *theta, int64_t n, int64_t *index, double *theta_index, ThetaScan *sc,
+                     hipStream_t s) {
+    ThetaScan h{};
+    theta_check_enqueue(theta, n, *index, sc, s);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, sc, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return err_code(e);
+    return theta_check_verdict(h, n, index, theta_index);
 }
 
 }  // namespace
@@ -1126,13 +1148,47 @@ int dominant_solve(const dpt_problem *p, const dpt_options *o, const double *the
     return dominant_t<float>(p, o, theta_host, theta_index, index, eigval, eigvec, r);
 }
 
-int dominant_theta_check_device(const double *theta, int64_t n, int64_t *index, double *theta_index, hipStream_t s) {
-    ThetaScan *sc = nullptr;
-    hipError_t e = hipMalloc((void **)&sc, sizeof(ThetaScan));
+// Device inputs: the theta checks and (CSR) the structure check run together
+// and are read back with one synchronisation, then the solve.
+int dominant_solve_device(const dpt_problem *p, const dpt_options *o, int64_t index, double *eigval, void *eigvec,
+                          dpt_result *r) {
+    hipStream_t s = (hipStream_t)p->stream;
+    unsigned char *dev = nullptr;  // ThetaScan at 0, the CSR flag at 256
+    hipError_t e = hipMalloc((void **)&dev, 512);
     if (e != hipSuccess) return err_code(e);
-    const int rc = theta_check_into(theta, n, index, theta_index, sc, s);
-    (void)hipFree(sc);
-    return rc;
+    ThetaScan *sc = (ThetaScan *)dev;
+    unsigned int *flag = (unsigned int *)(dev + 256);
+    const bool csr = p->format == DPT_CSR;
+    theta_check_enqueue(p->theta, p->n, index, sc, s);
+    if (csr) {
+        hipLaunchKernelGGL((k_zero<unsigned int>), dim3(1), dim3(64), 0, s, flag, (int64_t)1);
+        hipLaunchKernelGGL(k_csr_validate, dim3(blocks_for(p->n, 32)), dim3(256), 0, s, p->indptr, p->indices, p->n,
+                           p->nnz, flag);
+    }
+    unsigned char *hw = (unsigned char *)pinned_block_take();
+    unsigned char local[sizeof(ThetaScan) + sizeof(unsigned int)];
+    unsigned char *hb = hw ? hw : local;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(hb, sc, sizeof(ThetaScan), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && csr)
+        e = hipMemcpyAsync(hb + sizeof(ThetaScan), flag, sizeof(unsigned int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    ThetaScan h{};
+    unsigned int hflag = 0;
+    if (e == hipSuccess) {
+        std::memcpy(&h, hb, sizeof(ThetaScan));
+        if (csr) std::memcpy(&hflag, hb + sizeof(ThetaScan), sizeof(unsigned int));
+        pinned_block_give(hw);
+    }
+    (void)hipFree(dev);
+    if (e != hipSuccess) return err_code(e);
+    double theta_index = 0.0;
+    int rc = theta_check_verdict(h, p->n, &index, &theta_index);
+    if (rc != DPT_OK) return rc;
+    if (hflag) return DPT_EINVAL;
+    if (o->precision == DPT_FP64)
+        return dominant_t<double>(p, o, nullptr, theta_index, index, eigval, eigvec, r, csr);
+    return dominant_t<float>(p, o, nullptr, theta_index, index, eigval, eigvec, r, csr);
 }
 
 // ------------------------------------------------- dominant mode, no allocation
