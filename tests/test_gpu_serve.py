@@ -237,6 +237,31 @@ def test_device_inputs_match_host_inputs():
     dpt.dpt_serve_close(srv)
 
 
+def test_orders_one_to_three_alone_and_in_a_mix():
+    """The smallest orders (one partly filled 64 x 64 tile each), from host and
+    device arrays: N = 1 gives E = theta_0 + lambda Delta_00 and Z = [1]; the
+    others match the oracle at the FP32 bar, alone and in a mix."""
+    import torch
+    probs = [(np.array([0.5]), np.array([[0.25]])), request(2, True, 80), request(3, False, 81)]
+    srv = dpt.dpt_serve_open(1 << 28, max_slots=8)
+    mixed = run_all(srv, probs + [request(100, True, 82)], opts=OPTS_ACC)
+    alone = [run_all(srv, [pr], opts=OPTS_ACC)[0] for pr in probs]
+    o = dpt.options(**OPTS_ACC)
+    dev = [(torch.from_numpy(th).cuda(), torch.from_numpy(de).cuda()) for th, de in probs]
+    torch.cuda.synchronize()
+    tickets = [dpt.dpt_serve_submit(srv, dpt.ProblemSpec(th, de, 1.0), o, True) for th, de in dev]
+    from_dev = [dpt.dpt_serve_poll(srv, t, wait_ms=-1) for t in tickets]
+    dpt.dpt_serve_close(srv)
+    assert mixed[0]["status"] == dpt.DPT_OK and np.allclose(mixed[0]["E"], [0.75], rtol=0, atol=1e-7)
+    assert np.array_equal(mixed[0]["Z"], np.ones((1, 1)))
+    for (th, de), x, a, d in zip(probs, mixed, alone, from_dev):
+        assert x["status"] == dpt.DPT_OK
+        assert np.array_equal(x["E"], a["E"]) and np.array_equal(x["Z"], a["Z"])
+        assert np.array_equal(x["E"], d["E"]) and np.array_equal(x["Z"], d["Z"])
+        ref = oracle.iterate(th, de.astype(np.float64), 1.0, max_iter=200, tol=1e-14)
+        assert rel_eig_error(x["E"], ref["e"], th) <= 1e-5
+
+
 def test_device_submit_rejections():
     import torch
     th, de = request(50, True, 60)
