@@ -79,8 +79,10 @@ hipError_t launch_copy_rows_f64(double *dst, const double *src, const int32_t *r
 // Tile height of the products when a row map is in use: the row list is
 // padded to a multiple of it (at most ld).
 inline int64_t row_tile(int64_t ld) { return ld % 128 == 0 ? 128 : 64; }
-// Large-tile FP64 step (kernels_gemm_f64.hip): ld a multiple of 128, ld >= 4096.
+// Large-tile FP64 step (kernels_gemm_f64.hip): ld a multiple of 128, ld >= 2048;
+// preferred: where it is measured faster than the general kernels.
 bool step_f64_large_supported(int64_t ld);
+bool step_f64_large_preferred(int64_t ld);
 hipError_t launch_step_f64_large(const StepArgs &a, const double *W, const double *Delta, const double *deltaT,
                                  double *Wn, hipStream_t s);
 // C[i][j] = sum_k A[i][k] B[j][k] for ld x ld FP64 operands (ld a multiple of 64).

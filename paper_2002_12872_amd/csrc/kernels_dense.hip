@@ -1256,17 +1256,17 @@ hipError_t launch_step_f32(const StepArgs &a, const float *W, const float *Delta
     return launch_gemm<PolF32, 64, 64, 16, 2, 2, float>(a, W, Delta, deltaT, W, Wn, Wbn, s);
 }
 
-// FP64: from order 4096 on (a multiple of 128) the large-tile kernel of
-// kernels_gemm_f64.hip, with or without a row map; at such orders that are not
-// multiples of 128 the general 128 x 128 tiles of 8 waves (32 x 64 each, two
-// waves per SIMD, K-tiles of 32: 139 ms per step at N = 16384 against 154 ms for
-// 64 x 64 tiles), or their row-mapped form; below 4096, 64 x 64 tiles (128-wide
-// tiles leave CUs idle).
+// FP64: the large-tile kernel of kernels_gemm_f64.hip where it is preferred
+// (from order 4096 on, a multiple of 128, and at 2048), with or without a row
+// map; at orders from 4096 that are not multiples of 128 the general 128 x 128
+// tiles of 8 waves (32 x 64 each, two waves per SIMD, K-tiles of 32: 139 ms per
+// step at N = 16384 against 154 ms for 64 x 64 tiles), or their row-mapped form;
+// below, 64 x 64 tiles (128-wide tiles leave CUs idle).
 hipError_t launch_step_f64(const StepArgs &a, const double *W, const double *Delta, const double *deltaT, double *Wn,
                            hipStream_t s) {
     if (a.rowmap && few_row_tiles(a))  // the last running rows: 64-row tiles, four times as many workgroups
         return launch_gemm<PolF64, 64, 64, 16, 2, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
-    if (step_f64_large_supported(a.ld)) return launch_step_f64_large(a, W, Delta, deltaT, Wn, s);
+    if (step_f64_large_preferred(a.ld)) return launch_step_f64_large(a, W, Delta, deltaT, Wn, s);
     if ((a.ld >= 4096 || a.rowmap) && row_tile(a.ld) == 128)
         return launch_gemm<PolF64, 128, 128, 32, 4, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);
     return launch_gemm<PolF64, 64, 64, 16, 2, 2, double>(a, W, Delta, deltaT, W, Wn, (__bf16 *)nullptr, s);

@@ -1,6 +1,6 @@
 // Fused FP64 D-PT step for large dense problems on gfx950 (ld a multiple of
-// 128, ld >= 4096): the optional FP64 sweeps, the stage solves of the homotopy
-// continuation and FP64 solves of large problems.
+// 128, ld >= 2048; chosen where measured faster): the optional FP64 sweeps, the
+// stage solves of the homotopy continuation and FP64 solves of large problems.
 //
 // One application of eq. (dyn) of Kenmoe, Smerlak, Zadorin (arXiv:2002.12872)
 // on the padded state W = A - I, all in FP64:
@@ -243,7 +243,16 @@ __global__ __launch_bounds__(NT, 2) void k_step_f64_large(const double *__restri
 
 }  // namespace
 
-bool step_f64_large_supported(int64_t ld) { return ld % BM == 0 && ld % BN == 0 && ld >= 4096; }
+bool step_f64_large_supported(int64_t ld) { return ld % BM == 0 && ld % BN == 0 && ld >= 2048; }
+
+// Measured against the general kernels: faster from ld 4096 on (N = 16384:
+// 128 ms against 140), and below where its tiles make whole waves at one
+// workgroup per CU (ld 2048: 0.33 ms against 0.38); slower or level at
+// 1024-1536 and at 3072-3584, whose last wave is mostly empty.
+bool step_f64_large_preferred(int64_t ld) {
+    if (!step_f64_large_supported(ld)) return false;
+    return ld >= 4096 || ((ld / BM) * (ld / BN)) % 256 == 0;
+}
 
 // With a row map (a.rows entries, a multiple of BM) the tile rows run over the
 // listed W rows only.

@@ -63,12 +63,12 @@ def test_fp64_solve_small_symmetric_matches_oracle_and_jacobi(seed):
     assert np.max(r / (norm_ub * np.linalg.norm(z, axis=1))) <= 1e-10
 
 
-@pytest.mark.parametrize("n", SIZES + [4100, 6000])
+@pytest.mark.parametrize("n", SIZES + [2048, 4100, 6000])
 @pytest.mark.parametrize("sym", [False, True])
 def test_fp64_steps_match_oracle(n, sym):
-    """N = 4100 and 6000 (padded to 4352 and 6144) run the large-tile FP64 step
-    (128 x 128 tiles, two workgroups per CU, direct-to-LDS loads); the smaller
-    orders the general one."""
+    """N = 2048, 4100 and 6000 (padded to 2048, 4352 and 6144) run the
+    large-tile FP64 step (128 x 128 tiles, two workgroups per CU, direct-to-LDS
+    loads); the smaller orders the general one."""
     theta, delta = small_problem(n, 1, symmetric=sym)
     lam = -0.8 if sym else 1.0
     rows = workloads.sample_rows(n, 48)
