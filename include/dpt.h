@@ -339,8 +339,10 @@ typedef struct dpt_serve_config {
     int32_t use_graph;      /* 1: replay the grouped step as a HIP graph              */
     int32_t grid_blocks;    /* persistent grid of the grouped kernels; 0 = 1024       */
     int32_t autotune;       /* 1: time the fused-step tile shapes (64x64, 128x64,     *
-                             * 128x128) per phase and padded-order class at open and  *
-                             * keep the fastest; 0: 128x128 above padded order 512;   *
+                             * 128x128) per phase and padded-order class at open, on  *
+                             * a full batch and on a lone problem, and keep the one   *
+                             * fastest alone among those within 3 % of the fastest on *
+                             * the full batch; 0: 128x128 above padded order 512;     *
                              * -1, -2, -3: shape 64x64, 128x64 or 128x128 for every   *
                              * class (orders that are not multiples of 128: 64x64)    */
     void *stream;           /* hipStream_t for all of the server's device work (the   *

@@ -353,8 +353,9 @@ struct PolF64 {
 // One output tile (tm, tn) of one fused step; called by the single-problem
 // kernel below and by the grouped serving kernel (one tile per work item).
 // PLAIN: the same product without the update, Wnew = A B^T (a plain NT GEMM of
-// two ld x ld operands; deltaT and Wold are not read, no statistics).
-template <class P, int BM, int BN, int BK, int WM, int WN, typename S, bool PLAIN = false>
+// two ld x ld operands; deltaT and Wold are not read, no statistics).  EG: the
+// elements of an accumulator block whose epilogue loads are issued together.
+template <class P, int BM, int BN, int BK, int WM, int WN, typename S, bool PLAIN = false, int EG = 4>
 __device__ __forceinline__ void step_tile(const typename P::in_t *__restrict__ A, const typename P::in_t *__restrict__ B,
                                           const S *__restrict__ deltaT, const S *__restrict__ Wold,
                                           S *__restrict__ Wnew, __bf16 *__restrict__ Wbnew, const StepArgs &a, int tm,
@@ -485,41 +486,91 @@ __device__ __forceinline__ void step_tile(const typename P::in_t *__restrict__ A
         return;
     }
     // Epilogue: C = Delta^T (exact, state precision) + acc; update of eq. (dyn).
+    // The quotient is formed for every element and selected (0 on the diagonal
+    // and outside n, m < N).  Without a row map, the elements of an accumulator
+    // block go in groups of EG: the loads of a group (Delta^T, W, theta_n, d_n)
+    // are issued together, then its results computed and stored (each BF16
+    // shadow value beside its FP32 one).  With a branch per element the loads
+    // of an element waited for the stores of the one before (half of a 64 x 64
+    // BF16 step at orders up to 1024).  The persistent grouped step takes groups
+    // of 2: loading more at once takes registers from its four resident waves
+    // per SIMD (a whole block of 16 raised its 64 x 64 form from 108 to 184).  For an FP32 state max|W'| and the finiteness test
+    // run in FP32 (the same values: |W' - W| of two floats cannot overflow in
+    // FP64, so it is infinite or NaN exactly when W' or W is).
     const S lam = (S)a.lambda;
-    double dmax = 0.0, wmax = 0.0;
+    double dmax = 0.0;
+    S wmax = (S)0;
     bool bad = false;
+    auto update = [&](S c, S wo, double th_n, double th_m, S dn, bool ok) -> S {
+        const S num = c - dn * wo;
+        const S gap = (S)(th_n - th_m);
+        const S q = lam * num / gap;
+        const S w = ok ? q : (S)0;
+        const double dv = fabs((double)w - (double)wo);
+        dmax = fmax(dmax, dv);
+        wmax = fmax(wmax, fabs(w));
+        if constexpr (sizeof(S) == 4)
+            bad |= !(fabsf(w) <= FLT_MAX) || !(fabsf(wo) <= FLT_MAX);
+        else
+            bad |= !(dv <= DBL_MAX) || !(fabs(w) <= DBL_MAX);
+        return w;
+    };
+    if (a.rowmap) {  // per-row retirement: the listed rows only (-1: padding)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-        const int64_t m = col0 + wc * WTN + j * P::MI + P::acc_col(lane);
-        const double th_m = a.theta[m];
+        for (int j = 0; j < TN; ++j) {
+            const int64_t m = col0 + wc * WTN + j * P::MI + P::acc_col(lane);
+            const double th_m = a.theta[m];
+            const bool col_ok = m < a.n;
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
+            for (int i = 0; i < TM; ++i) {
 #pragma unroll
-            for (int r = 0; r < P::NACC; ++r) {
-                int64_t n = row0 + wr * WTM + i * P::MI + P::acc_row(r, lane);
-                if (a.rowmap) {
-                    n = a.rowmap[n];
-                    if (n < 0) continue;  // padding of the row list
+                for (int r = 0; r < P::NACC; ++r) {
+                    const int64_t n = a.rowmap[row0 + wr * WTM + i * P::MI + P::acc_row(r, lane)];
+                    if (n < 0) continue;
+                    const int64_t idx = n * ld + m;
+                    const S w = update((S)acc[i][j][r] + deltaT[idx], Wold[idx], a.theta[n], th_m, (S)a.d[n],
+                                       n < a.n && col_ok && n != m);
+                    Wnew[idx] = w;
+                    if (Wbnew) Wbnew[idx] = (__bf16)(float)w;
                 }
-                const int64_t idx = n * ld + m;
-                const S c = (S)acc[i][j][r] + deltaT[idx];
-                const S wo = Wold[idx];
-                S w = (S)0;
-                if (n < a.n && m < a.n && n != m) {
-                    const S num = c - (S)a.d[n] * wo;
-                    const S gap = (S)(a.theta[n] - th_m);
-                    w = lam * num / gap;
+            }
+        }
+    } else {
+        const bool shadow = Wbnew != nullptr;
+        constexpr int EB = P::NACC < EG ? P::NACC : EG;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t m = col0 + wc * WTN + j * P::MI + P::acc_col(lane);
+            const double th_m = a.theta[m];
+            const bool col_ok = m < a.n;
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int64_t nb = row0 + wr * WTM + i * P::MI;
+#pragma unroll
+                for (int r0 = 0; r0 < P::NACC; r0 += EB) {
+                    S dtv[EB], wov[EB];
+                    double thv[EB], dv[EB];
+#pragma unroll
+                    for (int u = 0; u < EB; ++u) {
+                        const int64_t n = nb + P::acc_row(r0 + u, lane), idx = n * ld + m;
+                        dtv[u] = deltaT[idx];
+                        wov[u] = Wold[idx];
+                        thv[u] = a.theta[n];
+                        dv[u] = a.d[n];
+                    }
+#pragma unroll
+                    for (int u = 0; u < EB; ++u) {
+                        const int64_t n = nb + P::acc_row(r0 + u, lane), idx = n * ld + m;
+                        const S w = update((S)acc[i][j][r0 + u] + dtv[u], wov[u], thv[u], th_m, (S)dv[u],
+                                           n < a.n && col_ok && n != m);
+                        Wnew[idx] = w;
+                        if (shadow) Wbnew[idx] = (__bf16)(float)w;
+                    }
                 }
-                Wnew[idx] = w;
-                if (Wbnew) Wbnew[idx] = (__bf16)(float)w;
-                const double dv = fabs((double)w - (double)wo), av = fabs((double)w);
-                dmax = fmax(dmax, dv);
-                wmax = fmax(wmax, av);
-                bad |= !(dv <= DBL_MAX) || !(av <= DBL_MAX);
             }
         }
     }
-    publish_stats(a.stat, dmax, wmax, bad);
+    publish_stats(a.stat, dmax, (double)wmax, bad);
 }
 
 template <class P, int BM, int BN, int BK, int WM, int WN, typename S>
@@ -920,9 +971,10 @@ __global__ __launch_bounds__(256) void k_group_step(const GroupTable *__restrict
         a.d = q.d;
         a.stat = q.stat;
         if (PHASE == PH_BF16)
-            step_tile<PolBF16, BM, BN, 64, 2, 2, float>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
+            step_tile<PolBF16, BM, BN, 64, 2, 2, float, false, 2>(q.Wb, q.Db, q.DT, q.W, q.Wn, q.Wbn, a, tm, tn);
         else
-            step_tile<PolF32, BM, BN, 32, 2, 2, float>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a, tm, tn);
+            step_tile<PolF32, BM, BN, 32, 2, 2, float, false, 2>(q.W, q.D, q.DT, q.W, q.Wn, (__bf16 *)nullptr, a,
+                                                                 tm, tn);
     }
 }
 

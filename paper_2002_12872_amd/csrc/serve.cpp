@@ -406,13 +406,18 @@ struct dpt_server_ctx {
     }
 
     // Tile-shape autotuner.  For padded orders 256, 512, 1024, 2048 (the largest
-    // of each order class) and each phase, time the grouped fused step over a
-    // batch of synthetic problems (about four grid-fulls of 64x64 tiles,
-    // distinct buffers, zero state, theta_i = i) with each tile shape; a larger
-    // shape replaces the best so far only when at least 3 % faster.
+    // of each order class) and each phase, time the grouped fused step with each
+    // tile shape on synthetic problems (distinct buffers, zero state,
+    // theta_i = i): a full batch (about four grid-fulls of 64x64 tiles: the
+    // throughput under load) and a lone problem (the step time when few requests
+    // are in flight).  Among the shapes within 3 % of the best full-batch time,
+    // the one with the fastest lone-problem step is kept; a larger shape replaces
+    // a smaller one only when at least 3 % faster there.  (Timed on full batches
+    // alone, larger tiles won by a few per cent at no gain in the burst rate but
+    // at 20 % longer latencies at the service rate.)
     hipError_t autotune() {
         const int64_t orders[] = {256, 512, 1024, 2048};
-        constexpr int kOrders = 4, kReps = 3;
+        constexpr int kOrders = 4, kReps = 3, kRepsLone = 20;
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         hipError_t e = hipEventCreate(&ev0);
         if (e == hipSuccess) e = hipEventCreate(&ev1);
@@ -449,31 +454,38 @@ struct dpt_server_ctx {
                 g.lambda = 1.0;
                 e = hipMemcpyAsync(theta_b, th.data(), (size_t)ld * 8, hipMemcpyHostToDevice, stream);
             }
+            // time of one grouped step of shape sh over the first `count` problems
+            auto time_step = [&](int phase, int sh, int count, int reps, float *ms) {
+                const int L = group_list(phase, sh);
+                std::memset(t.counts, 0, sizeof(t.counts));
+                t.counts[0] = count;
+                t.counts[1 + L] = count;
+                const int32_t tiles = (int32_t)((ld / group_shape_rows(sh)) * (ld / group_shape_cols(sh)));
+                for (int b = 0; b <= count; ++b) {
+                    t.prefix[L][b] = b * tiles;
+                    if (b < count) t.idx[L][b] = b;
+                }
+                hipError_t x = hipMemcpyAsync(table_d, table_h, sizeof(GroupTable), hipMemcpyHostToDevice, stream);
+                if (x == hipSuccess) x = launch_group_step(table_d, phase, sh, grid, stream);  // warm-up
+                if (x == hipSuccess) x = hipEventRecord(ev0, stream);
+                for (int r = 0; r < reps && x == hipSuccess; ++r) x = launch_group_step(table_d, phase, sh, grid, stream);
+                if (x == hipSuccess) x = hipEventRecord(ev1, stream);
+                if (x == hipSuccess) x = hipEventSynchronize(ev1);
+                if (x == hipSuccess) x = hipEventElapsedTime(ms, ev0, ev1);
+                return x;
+            };
             for (int pi = 0; pi < 2 && e == hipSuccess; ++pi) {
                 const int phase = pi == 0 ? PH_BF16 : PH_FP32;
-                float ms[kGroupShapes] = {};
+                float full[kGroupShapes] = {}, lone[kGroupShapes] = {};
                 for (int sh = 0; sh < kGroupShapes && e == hipSuccess; ++sh) {
-                    const int L = group_list(phase, sh);
-                    std::memset(t.counts, 0, sizeof(t.counts));
-                    t.counts[0] = batch;
-                    t.counts[1 + L] = batch;
-                    const int32_t tiles = (int32_t)((ld / group_shape_rows(sh)) * (ld / group_shape_cols(sh)));
-                    for (int b = 0; b <= batch; ++b) {
-                        t.prefix[L][b] = b * tiles;
-                        if (b < batch) t.idx[L][b] = b;
-                    }
-                    e = hipMemcpyAsync(table_d, table_h, sizeof(GroupTable), hipMemcpyHostToDevice, stream);
-                    if (e == hipSuccess) e = launch_group_step(table_d, phase, sh, grid, stream);  // warm-up
-                    if (e == hipSuccess) e = hipEventRecord(ev0, stream);
-                    for (int r = 0; r < kReps && e == hipSuccess; ++r)
-                        e = launch_group_step(table_d, phase, sh, grid, stream);
-                    if (e == hipSuccess) e = hipEventRecord(ev1, stream);
-                    if (e == hipSuccess) e = hipEventSynchronize(ev1);
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms[sh], ev0, ev1);
+                    e = time_step(phase, sh, batch, kReps, &full[sh]);
+                    if (e == hipSuccess) e = time_step(phase, sh, 1, kRepsLone, &lone[sh]);
                 }
-                int b = 0;
-                for (int sh = 1; sh < kGroupShapes; ++sh)
-                    if (ms[sh] < 0.97f * ms[b]) b = sh;
+                float best_full = full[0];
+                for (int sh = 1; sh < kGroupShapes; ++sh) best_full = std::min(best_full, full[sh]);
+                int b = -1;
+                for (int sh = 0; sh < kGroupShapes; ++sh)
+                    if (full[sh] <= 1.03f * best_full && (b < 0 || lone[sh] < 0.97f * lone[b])) b = sh;
                 best[pi][oi] = b;
             }
             (void)hipStreamSynchronize(stream);
