@@ -15,19 +15,47 @@ constexpr unsigned long long kNanBits = 0x7ff8000000000000ull;
 
 __device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 
+// x of another lane by a DPP lane move (both 32-bit halves with the same
+// control): lanes that the row mask leaves out, or whose source lane does not
+// exist, get `old`.  CTRL: 0x00-0xff quad permutation, 0x121-0x12f rotation
+// right by 1-15 lanes within a row of 16, 0x140 row mirror, 0x141 half-row
+// mirror, 0x142 / 0x143 broadcast of lane 15 / 31 of a row to the next rows.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double x, double old) {
+    const long long xb = __double_as_longlong(x), ob = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)ob, (int)xb, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(ob >> 32), (int)(xb >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Max over the 64 lanes of a wave of values that are never NaN, in every lane.
+// DPP moves within quads, half-rows and rows, then the row ends broadcast
+// forward (lane 63 ends with the maximum), instead of six dependent
+// cross-lane shuffles through the LDS crossbar (≈ 2000 cycles for two values
+// in the small-problem kernel).  Max is exact in any order.
+__device__ __forceinline__ double wave_max(double x) {
+    x = fmax(x, dpp_f64<0xb1>(x, x));       // lanes 1 0 3 2 of each quad
+    x = fmax(x, dpp_f64<0x4e>(x, x));       // lanes 2 3 0 1 of each quad
+    x = fmax(x, dpp_f64<0x141>(x, x));      // half-row mirror
+    x = fmax(x, dpp_f64<0x140>(x, x));      // row mirror: every lane holds its row's max
+    x = fmax(x, dpp_f64<0x142, 0xa>(x, x));  // rows 1, 3 take lane 15 / 47
+    x = fmax(x, dpp_f64<0x143, 0xc>(x, x));  // rows 2, 3 take lane 31
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Wave-wide max of (delta, |w|) plus a non-finite flag; lane 0 of every wave
 // publishes with one atomicMax per value (max is order-independent, so the
-// result is deterministic).  The current value is read first (device scope,
-// past the non-coherent L1) and the atomic skipped when it cannot raise it:
-// the slot only grows during a launch, so a skipped update is never lost, and
-// kernels with 10^5-10^6 waves do not serialise on two addresses.  Must be
-// reached by all 64 lanes of the wave.
+// result is deterministic).  delta and |w| are non-negative and never NaN
+// (they come from fmax, which drops NaN operands; NaNs set `bad`).  The
+// current value is read first (device scope, past the non-coherent L1) and the
+// atomic skipped when it cannot raise it: the slot only grows during a launch,
+// so a skipped update is never lost, and kernels with 10^5-10^6 waves do not
+// serialise on two addresses.  Must be reached by all 64 lanes of the wave.
 __device__ __forceinline__ void publish_stats(unsigned long long *stat, double dmax, double wmax, bool bad) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        dmax = fmax(dmax, __shfl_xor(dmax, o));
-        wmax = fmax(wmax, __shfl_xor(wmax, o));
-    }
+    dmax = wave_max(dmax);
+    wmax = wave_max(wmax);
     const bool any_bad = __any(bad ? 1 : 0);
     if ((threadIdx.x & 63) == 0) {
         const unsigned long long vd = any_bad ? kNanBits : dbits(dmax), vw = any_bad ? kNanBits : dbits(wmax);
@@ -45,11 +73,8 @@ __device__ __forceinline__ void publish_stats(unsigned long long *stat, double d
 __device__ __forceinline__ void publish_stats_block(unsigned long long *stat, double dmax, double wmax, bool bad) {
     __shared__ double s_d[16], s_w[16];
     __shared__ int s_b[16];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        dmax = fmax(dmax, __shfl_xor(dmax, o));
-        wmax = fmax(wmax, __shfl_xor(wmax, o));
-    }
+    dmax = wave_max(dmax);
+    wmax = wave_max(wmax);
     const bool any_bad = __any(bad ? 1 : 0);
     const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     if ((threadIdx.x & 63) == 0) {
