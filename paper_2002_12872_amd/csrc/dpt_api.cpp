@@ -777,7 +777,9 @@ bool host_symmetric(const dpt_problem *p) {
     return true;
 }
 
-// Symmetry test of the staged copy on the device (flag read back).
+// Symmetry test of the staged copy on the device (flag read back, into the
+// handle's pinned block when it has one; the wait also completes every
+// read-back enqueued before it).
 template <typename T>
 int device_symmetric(dpt_ctx *c, const T *src, __bf16 *bf, bool *sym) {
     unsigned int *flag = nullptr;
@@ -789,12 +791,14 @@ int device_symmetric(dpt_ctx *c, const T *src, __bf16 *bf, bool *sym) {
         else
             e = launch_symmetry_check_f32((const float *)src, c->ld, flag, bf, c->stream);
     }
-    unsigned int h = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, c->stream);
+    unsigned int h_local = 0;
+    unsigned int *h = (unsigned int *)c->pin_space(sizeof(unsigned int));
+    if (!h) h = &h_local;
+    if (e == hipSuccess) e = hipMemcpyAsync(h, flag, 4, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     dfree(flag);
     DPT_TRY(e);
-    *sym = (h == 0);
+    *sym = (*h == 0);
     return DPT_OK;
 }
 
@@ -1091,14 +1095,28 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
 
     // theta: validated on the host (device inputs are read back on the handle's
     // stream), then placed on the device padded with zeros: a device-to-device
-    // copy for device inputs, one upload for host inputs
+    // copy for device inputs, one upload for host inputs.  A dense device
+    // problem reads theta back into a pinned block and checks it after the
+    // symmetry test's wait, so both take one round trip (nothing computes with
+    // theta before then; a bad theta fails the call there).
     std::vector<double> th((size_t)c->ld, 0.0);
+    const double *th_deferred = nullptr;
     if (p->mem == DPT_MEM_DEVICE) {
-        if (hipMemcpyAsync(th.data(), p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost, c->stream) !=
-                hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess)
-            return fail(DPT_EDEVICE);
-        if (!theta_ok(th.data(), p->n)) return fail(DPT_EINVAL);
+        if (p->format == DPT_DENSE && sizeof(double) * (size_t)p->n + 512 <= kPinBlock) {
+            c->pin = (unsigned char *)pin_pool().take();
+            th_deferred = (const double *)c->pin_space(sizeof(double) * (size_t)p->n);
+        }
+        if (th_deferred) {
+            if (hipMemcpyAsync((void *)th_deferred, p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost,
+                               c->stream) != hipSuccess)
+                return fail(DPT_EDEVICE);
+        } else {
+            if (hipMemcpyAsync(th.data(), p->theta, sizeof(double) * (size_t)p->n, hipMemcpyDeviceToHost,
+                               c->stream) != hipSuccess ||
+                hipStreamSynchronize(c->stream) != hipSuccess)
+                return fail(DPT_EDEVICE);
+            if (!theta_ok(th.data(), p->n)) return fail(DPT_EINVAL);
+        }
     } else {
         std::memcpy(th.data(), p->theta, sizeof(double) * (size_t)p->n);
     }
@@ -1130,9 +1148,10 @@ int dpt_init(dpt_handle *h, const dpt_problem *p, const dpt_options *o, const vo
         if (rc == DPT_OK) c->phase = c->opt.precision == DPT_FP64 ? PH_FP64 : PH_FP32;
         if (rc == DPT_OK && z0) rc = sparse_warm_start(c, p, z0);
     } else {
-        rc = init_dense(c, p, z0);
+        rc = init_dense(c, p, z0);  // device inputs: waits for the symmetry test
     }
     if (rc != DPT_OK) return fail(rc);
+    if (th_deferred && !theta_ok(th_deferred, p->n)) return fail(DPT_EINVAL);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(DPT_EDEVICE);
     pin_pool().give(c->pin);  // its uploads are complete
     c->pin = nullptr;
