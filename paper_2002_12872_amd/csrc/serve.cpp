@@ -19,6 +19,7 @@
 //      space at once; their results are handed out after the next
 //      synchronisation of the stream.
 #include <hip/hip_runtime.h>
+#include <sched.h>
 
 #include <algorithm>
 #include <atomic>
@@ -319,7 +320,16 @@ struct dpt_server_ctx {
     hipStream_t submit_stream = nullptr;
     std::mutex submit_mu;
     StagePool stage_pool;  // host staging of submitted matrices
-    static constexpr int kStageThreads = 4;
+    // staging threads besides the submitting one: half the CPUs this process
+    // may run on, 1 to 8 (the conversion and symmetry test of host FP64
+    // submissions are bound by host memory bandwidth)
+    static int stage_threads() {
+        cpu_set_t set;
+        int cpus = 0;
+        if (sched_getaffinity(0, sizeof(set), &set) == 0) cpus = CPU_COUNT(&set);
+        if (cpus <= 0) cpus = (int)std::thread::hardware_concurrency();
+        return std::min(8, std::max(1, cpus / 2));
+    }
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::chrono::steady_clock::time_point t0;
@@ -922,7 +932,7 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
         for (int k = 0; k < dpt_server_ctx::kOrderClasses; ++k) c->st.tile_shape[pi][k] = c->shape_of[pi][k];
     c->arena.init((size_t)cfg->budget_bytes);
     for (int i = cfg->max_slots - 1; i >= 0; --i) c->free_slots.push_back(i);
-    c->stage_pool.start(dpt_server_ctx::kStageThreads);
+    c->stage_pool.start(dpt_server_ctx::stage_threads());
     c->worker = std::thread([c] { c->run(); });
     *srv = c;
     return DPT_OK;
