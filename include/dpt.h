@@ -235,9 +235,9 @@ int dpt_dominant(const dpt_problem *p, const dpt_options *o, int64_t index, doub
  * cannot call hipMalloc (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation).  Same iteration, kernels and results as
  * dpt_dominant (bitwise), with every work buffer (the two iterates, the scalar
- * (Delta z)[index], per-iteration statistics, the theta and CSR checks) in one
- * fixed array per GPU of 64 MiB + 68 KiB, held by each GPU the library runs on
- * until the process ends.  Requirements beyond dpt_dominant's: p->mem ==
+ * (Delta z)[index], per-iteration statistics, the stop flag, the theta and CSR
+ * checks) in one fixed array per GPU of 64 MiB + 68 KiB, held by each GPU the
+ * library runs on until the process ends.  Requirements beyond dpt_dominant's: p->mem ==
  * DPT_MEM_DEVICE; p->dtype is DPT_DTYPE_F64 for o->precision == DPT_FP64 and
  * DPT_DTYPE_F32 otherwise (no conversion copy); eigvec is device memory of n
  * values of that dtype.  Limits: o->max_iter <= 4096 and n <= 8388608 (FP32) or

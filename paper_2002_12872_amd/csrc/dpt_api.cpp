@@ -1020,6 +1020,8 @@ namespace dpt {
 bool host_theta_ok(const double *theta, int64_t n) { return theta_ok(theta, n); }
 void *pinned_block_take() { return stat_mirror_pool().take(); }
 void pinned_block_give(void *p) { stat_mirror_pool().give(p); }
+hipError_t pooled_malloc(void **p, size_t bytes) { return small_pool().alloc(p, bytes); }
+void pooled_free(void *p) { small_pool().release(p); }
 bool inputs_on_device(const dpt_problem *p) { return p->mem == DPT_MEM_DEVICE && device_inputs_ok(p, nullptr); }
 }  // namespace dpt
 

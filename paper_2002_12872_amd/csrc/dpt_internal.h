@@ -260,6 +260,12 @@ bool host_theta_ok(const double *theta, int64_t n);
 // that used the block has drained.
 void *pinned_block_take();
 void pinned_block_give(void *p);
+// Device buffers from the library's pool (dpt_api.cpp): blocks up to 4 MiB are
+// recycled instead of going through hipMalloc / hipFree (several microseconds
+// each); larger ones are plain allocations.  Free only after the stream that
+// used the block has drained.
+hipError_t pooled_malloc(void **p, size_t bytes);
+void pooled_free(void *p);
 bool inputs_on_device(const dpt_problem *p);
 hipError_t launch_group_retire(const RetireTable *t, int grid, hipStream_t s);
 

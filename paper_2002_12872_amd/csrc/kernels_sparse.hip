@@ -335,10 +335,30 @@ __device__ double csr_row_dot_wave(const int64_t *rowptr, const int *col, const 
     return s;
 }
 
+// Stopping test of the dominant iteration on the device, by the kernel that
+// follows an iteration in stream order (its statistics are complete): raise
+// the stop flag when delta or max|z - e| is not finite, or max|z - e| exceeds
+// blowup, or (may_stop) delta < tol -- the host's rule, so that the iterations
+// enqueued after it in the same batch return at once.  st null: no test.
+__device__ __forceinline__ void dom_stop_test(unsigned int *stop, const unsigned long long *st, double tol,
+                                              double blowup, int may_stop) {
+    if (!st) return;
+    const double dl = __longlong_as_double((long long)st[0]), wm = __longlong_as_double((long long)st[1]);
+    if (!(dl <= DBL_MAX) || !(wm <= blowup) || (may_stop && dl < tol)) *stop = 1u;
+}
+
+// s = (Delta z)[row] (the next iteration's scalar, or the eigenvalue's), then
+// the stopping test of the iteration that produced z; nothing when stop is set.
 template <typename T>
-__global__ void k_csr_row_dot(const int64_t *rowptr, const int *col, const T *val, int64_t row, const T *z, double *s_out) {
+__global__ void k_csr_row_dot(const int64_t *rowptr, const int *col, const T *val, int64_t row, const T *z, double *s_out,
+                              unsigned int *stop, const unsigned long long *st, double tol, double blowup,
+                              int may_stop) {
+    if (stop && *stop) return;
     const double s = csr_row_dot_wave(rowptr, col, val, row, z);
-    if (threadIdx.x == 0) *s_out = s;
+    if (threadIdx.x == 0) {
+        *s_out = s;
+        dom_stop_test(stop, st, tol, blowup, may_stop);
+    }
 }
 
 // One iteration of F_{nstar}: 8 lanes per row, 32 rows per block pass; a
@@ -350,7 +370,8 @@ __global__ __launch_bounds__(256) void k_dom_csr(const int64_t *__restrict__ row
                                                  const T *__restrict__ val, int64_t n, int64_t nstar, double lambda,
                                                  const double *__restrict__ theta, const double *__restrict__ s_in,
                                                  const T *__restrict__ z, T *__restrict__ zn,
-                                                 unsigned long long *stat) {
+                                                 unsigned long long *stat, const unsigned int *__restrict__ stop) {
+    if (*stop) return;  // an earlier iteration of the batch met the stopping rule (uniform)
     const T s = (T)(*s_in);
     const int sub = threadIdx.x & 7;
     double dmax = 0.0, wmax = 0.0;
@@ -444,7 +465,9 @@ __global__ __launch_bounds__(256) void k_dom_first(const int64_t *__restrict__ r
 // Dense dominant mode: s computed first by k_dense_row_dot, then one wave per row.
 template <typename T>
 __global__ void k_dense_row_dot(const T *__restrict__ D, int64_t n, int64_t row, const T *__restrict__ z,
-                                double *s_out) {
+                                double *s_out, unsigned int *stop, const unsigned long long *st, double tol,
+                                double blowup, int may_stop) {
+    if (stop && *stop) return;
     __shared__ double red[4];
     double s = 0.0;
     for (int64_t l = threadIdx.x; l < n; l += 256) s += (double)D[row * n + l] * (double)z[l];
@@ -452,14 +475,18 @@ __global__ void k_dense_row_dot(const T *__restrict__ D, int64_t n, int64_t row,
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) *s_out = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) {
+        *s_out = (red[0] + red[1]) + (red[2] + red[3]);
+        dom_stop_test(stop, st, tol, blowup, may_stop);
+    }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_dom_dense(const T *__restrict__ D, int64_t n, int64_t nstar, double lambda,
                                                    const double *__restrict__ theta, const double *__restrict__ s_in,
                                                    const T *__restrict__ z, T *__restrict__ zn,
-                                                   unsigned long long *stat) {
+                                                   unsigned long long *stat, const unsigned int *__restrict__ stop) {
+    if (*stop) return;  // an earlier iteration of the batch met the stopping rule (uniform)
     const int lane = threadIdx.x & 63;
     const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     double dmax = 0.0, wmax = 0.0;
@@ -900,6 +927,7 @@ struct DomBuffers {
     T *z[2] = {nullptr, nullptr};
     double *s = nullptr;
     unsigned long long *stats = nullptr;
+    unsigned int *stop = nullptr;  // set on the device when an iteration meets the stopping rule
 };
 
 struct DomOutcome {
@@ -911,11 +939,18 @@ struct DomOutcome {
 // caller provides (allocates nothing).  `val` holds the CSR values, or the
 // n x n row-major matrix when rowptr is NULL.  The eigenvector goes to the
 // device array dst (dtype out64 ? double : float); *eigval gets
-// theta_star + lambda (Delta z)[nstar] of the returned iterate.  Each iteration
-// ends with (Delta z)[nstar] of its new iterate (the next iteration's scalar, and
-// the eigenvalue if the iteration is the last), read back with its statistics
-// in one synchronisation; host_words (three words, pinned) receives them, or a
-// local array when it is null.
+// theta_star + lambda (Delta z)[nstar] of the returned iterate.  Iterations are
+// enqueued in batches (2, then up to kDomBatch) with one synchronisation per
+// batch: each ends with (Delta z)[nstar] of its new iterate (the next
+// iteration's scalar, or the eigenvalue's) and the stopping test on the device
+// (the host's rule), after which the rest of the batch returns at once; the
+// batch's statistics and the last scalar come back together into host_words
+// (2 kDomBatch + 1 words, pinned) or a local array when it is null, and the
+// host applies the same rule to them in order, so it ends on the iteration the
+// device ended on.  The iterates are those of one synchronisation per
+// iteration.
+constexpr int kDomBatch = 4;
+
 template <typename T>
 hipError_t dominant_iterate(const dpt_problem *p, const dpt_options *o, const int64_t *rowptr, const int *col,
                             const T *val, const double *theta, double theta_star, int64_t nstar,
@@ -924,16 +959,20 @@ hipError_t dominant_iterate(const dpt_problem *p, const dpt_options *o, const in
                             unsigned long long *host_words = nullptr) {
     const int64_t n = p->n;
     const bool csr = rowptr != nullptr;
-    unsigned long long local[3] = {0ull, 0ull, 0ull};
+    unsigned long long local[2 * kDomBatch + 1] = {};
     unsigned long long *hs = host_words ? host_words : local;
-    auto row_dot = [&](const T *z) {
+    // (Delta z)[nstar] into b.s; with st, then the stopping test of z's iteration
+    auto row_dot = [&](const T *z, const unsigned long long *st, int may_stop) {
         if (csr)
-            hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, rowptr, col, val, nstar, z, b.s);
+            hipLaunchKernelGGL((k_csr_row_dot<T>), dim3(1), dim3(64), 0, s, rowptr, col, val, nstar, z, b.s,
+                               st ? b.stop : (unsigned int *)nullptr, st, o->tol, o->blowup, may_stop);
         else
-            hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, val, n, nstar, z, b.s);
+            hipLaunchKernelGGL((k_dense_row_dot<T>), dim3(1), dim3(256), 0, s, val, n, nstar, z, b.s,
+                               st ? b.stop : (unsigned int *)nullptr, st, o->tol, o->blowup, may_stop);
     };
     hipLaunchKernelGGL((k_zero<unsigned long long>), dim3(blocks_for(2 * (int64_t)cap, 256)), dim3(256), 0, s,
                        b.stats, (int64_t)2 * cap);
+    hipLaunchKernelGGL((k_zero<unsigned int>), dim3(1), dim3(64), 0, s, b.stop, (int64_t)1);
     hipLaunchKernelGGL((k_zero<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, b.z[0], n);
     hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, s, sizeof(T) == 4 ? (float *)b.z[0] : nullptr,
                        sizeof(T) == 8 ? (double *)b.z[0] : nullptr, nstar);
@@ -941,56 +980,69 @@ hipError_t dominant_iterate(const dpt_problem *p, const dpt_options *o, const in
     if (e != hipSuccess) return e;
     int cur = 0;
     double ak = 1.0;  // ramp_alpha^k (Supplement E's coupling ramp)
-    while (out->iters < o->max_iter) {
-        unsigned long long *st = b.stats + 2 * out->iters;
-        double lam = p->lambda;
-        bool ramping = false;
-        if (o->ramp_alpha > 0.0) {
-            ak *= o->ramp_alpha;
-            if (ak >= 0x1p-53) {
-                lam = p->lambda * (1.0 - ak);
-                ramping = true;
+    bool done = false;
+    while (!done && out->iters < o->max_iter) {
+        const int batch = std::min(out->iters == 0 ? 2 : kDomBatch, o->max_iter - out->iters);
+        bool ramping[kDomBatch] = {};
+        for (int j = 0; j < batch; ++j) {
+            const int it = out->iters + j;
+            unsigned long long *st = b.stats + 2 * it;
+            double lam = p->lambda;
+            if (o->ramp_alpha > 0.0) {
+                ak *= o->ramp_alpha;
+                if (ak >= 0x1p-53) {
+                    lam = p->lambda * (1.0 - ak);
+                    ramping[j] = true;
+                }
             }
+            const T *zin = b.z[(cur + j) & 1];
+            T *zout = b.z[(cur + j + 1) & 1];
+            if (it == 0) {  // z = e_nstar: closed form
+                if (csr)
+                    hipLaunchKernelGGL((k_dom_first<T, true>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
+                                       rowptr, col, val, n, nstar, lam, theta, zout, st);
+                else
+                    hipLaunchKernelGGL((k_dom_first<T, false>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
+                                       (const int64_t *)nullptr, (const int *)nullptr, val, n, nstar, lam, theta,
+                                       zout, st);
+            } else if (csr) {  // b.s = (Delta z)[nstar] of zin, from the end of the previous iteration
+                hipLaunchKernelGGL((k_dom_csr<T>), dim3(blocks_for(n, 32, kDomGrid)), dim3(256), 0, s, rowptr, col,
+                                   val, n, nstar, lam, theta, (const double *)b.s, zin, zout, st,
+                                   (const unsigned int *)b.stop);
+            } else {
+                hipLaunchKernelGGL((k_dom_dense<T>), dim3(blocks_for(n, 4)), dim3(256), 0, s, val, n, nstar, lam,
+                                   theta, (const double *)b.s, zin, zout, st, (const unsigned int *)b.stop);
+            }
+            row_dot(zout, st, ramping[j] ? 0 : 1);
         }
-        if (out->iters == 0) {  // z = e_nstar: closed form
-            if (csr)
-                hipLaunchKernelGGL((k_dom_first<T, true>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, rowptr,
-                                   col, val, n, nstar, lam, theta, b.z[cur ^ 1], st);
-            else
-                hipLaunchKernelGGL((k_dom_first<T, false>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s,
-                                   (const int64_t *)nullptr, (const int *)nullptr, val, n, nstar, lam, theta,
-                                   b.z[cur ^ 1], st);
-        } else if (csr) {  // b.s = (Delta z)[nstar] of z[cur], from the end of the previous iteration
-            hipLaunchKernelGGL((k_dom_csr<T>), dim3(blocks_for(n, 32, kDomGrid)), dim3(256), 0, s, rowptr, col, val,
-                               n, nstar, lam, theta, (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
-        } else {
-            hipLaunchKernelGGL((k_dom_dense<T>), dim3(blocks_for(n, 4)), dim3(256), 0, s, val, n, nstar, lam, theta,
-                               (const double *)b.s, (const T *)b.z[cur], b.z[cur ^ 1], st);
-        }
-        row_dot((const T *)b.z[cur ^ 1]);
         e = hipGetLastError();
-        if (e == hipSuccess) e = hipMemcpyAsync(hs, st, 16, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(hs + 2, b.s, 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hs, b.stats + 2 * out->iters, 16 * (size_t)batch, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hs + 2 * batch, b.s, 8, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
-        cur ^= 1;
-        out->iters += 1;
-        const double dl = bits_to_double(hs[0]), wm = bits_to_double(hs[1]);
-        out->last = dl;
-        if (r && r->delta_history && out->iters - 1 < r->history_cap) r->delta_history[out->iters - 1] = dl;
-        if (!std::isfinite(dl) || !(wm <= o->blowup)) {
-            out->status = DPT_DIVERGED;
-            break;
+        int taken = 0;
+        for (int j = 0; j < batch && !done; ++j) {
+            taken = j + 1;
+            out->iters += 1;
+            const double dl = bits_to_double(hs[2 * j]), wm = bits_to_double(hs[2 * j + 1]);
+            out->last = dl;
+            if (r && r->delta_history && out->iters - 1 < r->history_cap) r->delta_history[out->iters - 1] = dl;
+            if (!std::isfinite(dl) || !(wm <= o->blowup)) {
+                out->status = DPT_DIVERGED;
+                done = true;
+            } else if (!ramping[j] && dl < o->tol) {
+                out->status = DPT_OK;
+                done = true;
+            }
         }
-        if (!ramping && dl < o->tol) {
-            out->status = DPT_OK;
-            break;
-        }
+        cur = (cur + taken) & 1;
+        hs[2] = hs[2 * batch];  // the scalar of the returned iterate
     }
     // eigenvalue readout from the returned iterate: read back with the last
-    // iteration, or (no iteration) from e_nstar
+    // batch, or (no iteration) from e_nstar
     if (out->iters == 0) {
-        row_dot((const T *)b.z[cur]);
+        row_dot((const T *)b.z[cur], nullptr, 0);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(hs + 2, b.s, 8, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1064,12 +1116,15 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
                 if (e != hipSuccess) return e;
             }
         }
-        e = hipMalloc((void **)&b.s, sizeof(double));
-        if (e == hipSuccess) e = hipMalloc((void **)&b.stats, sizeof(unsigned long long) * 2 * cap);
-        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc((void **)&b.z[i], sizeof(T) * n);
+        // work buffers from the library's pool (no hipMalloc / hipFree per call
+        // for problems up to 4 MiB per iterate)
+        e = pooled_malloc((void **)&b.s, sizeof(double));
+        if (e == hipSuccess) e = pooled_malloc((void **)&b.stop, sizeof(unsigned int));
+        if (e == hipSuccess) e = pooled_malloc((void **)&b.stats, sizeof(unsigned long long) * 2 * cap);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = pooled_malloc((void **)&b.z[i], sizeof(T) * n);
         if (e != hipSuccess) return e;
         if (theta_host) {  // host inputs: upload theta; device inputs: borrow it
-            e = hipMalloc((void **)&theta_own, sizeof(double) * n);
+            e = pooled_malloc((void **)&theta_own, sizeof(double) * n);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(theta_own, theta_host, sizeof(double) * n, hipMemcpyHostToDevice, s);
             if (e != hipSuccess) return e;
@@ -1082,7 +1137,7 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
         const size_t ob = (size_t)n * (out64 ? 8 : 4);
         void *dst = eigvec;
         if (p->mem == DPT_MEM_HOST) {
-            e = hipMalloc(&out_tmp, ob);
+            e = pooled_malloc(&out_tmp, ob);
             if (e != hipSuccess) return e;
             dst = out_tmp;
         }
@@ -1099,12 +1154,15 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
     if (es == hipSuccess) pinned_block_give(words);  // drained; after a device error the block is not reused
     csr.release();
     if (val) (void)hipFree(val);
-    for (int i = 0; i < 2; ++i)
-        if (b.z[i]) (void)hipFree(b.z[i]);
-    if (theta_own) (void)hipFree(theta_own);
-    if (b.s) (void)hipFree(b.s);
-    if (b.stats) (void)hipFree(b.stats);
-    if (out_tmp) (void)hipFree(out_tmp);
+    // the stream has drained (or failed: then the blocks are not reused)
+    if (es == hipSuccess) {
+        for (int i = 0; i < 2; ++i) pooled_free(b.z[i]);
+        pooled_free(theta_own);
+        pooled_free(b.s);
+        pooled_free(b.stop);
+        pooled_free(b.stats);
+        pooled_free(out_tmp);
+    }
     if (rc != DPT_OK) return rc;
     if (e != hipSuccess) return err_code(e);
     fill_dom_result(r, out, sizeof(T) == 8);
@@ -1154,7 +1212,7 @@ int dominant_solve_device(const dpt_problem *p, const dpt_options *o, int64_t in
                           dpt_result *r) {
     hipStream_t s = (hipStream_t)p->stream;
     unsigned char *dev = nullptr;  // ThetaScan at 0, the CSR flag at 256
-    hipError_t e = hipMalloc((void **)&dev, 512);
+    hipError_t e = pooled_malloc((void **)&dev, 512);
     if (e != hipSuccess) return err_code(e);
     ThetaScan *sc = (ThetaScan *)dev;
     unsigned int *flag = (unsigned int *)(dev + 256);
@@ -1179,8 +1237,8 @@ int dominant_solve_device(const dpt_problem *p, const dpt_options *o, int64_t in
         std::memcpy(&h, hb, sizeof(ThetaScan));
         if (csr) std::memcpy(&hflag, hb + sizeof(ThetaScan), sizeof(unsigned int));
         pinned_block_give(hw);
+        pooled_free(dev);  // drained
     }
-    (void)hipFree(dev);
     if (e != hipSuccess) return err_code(e);
     double theta_index = 0.0;
     int rc = theta_check_verdict(h, p->n, &index, &theta_index);
@@ -1194,7 +1252,8 @@ int dominant_solve_device(const dpt_problem *p, const dpt_options *o, int64_t in
 // ------------------------------------------------- dominant mode, no allocation
 // Work memory of dpt_dominant_noalloc: one fixed array per GPU, for callers that
 // cannot allocate (HIP graph capture, serving loops).  Layout: a 4 KiB header
-// (the scalar s, the theta scan, the CSR check flag), the statistics of up to
+// (the scalar s at 0, the theta scan at 256, the CSR check flag at 512, the
+// iteration's stop flag at 768), the statistics of up to
 // kNoallocMaxIter iterations, then the two iterates.  Host code must use the
 // device address from hipGetSymbolAddress (per device), never `scratch` itself.
 constexpr size_t kScratchHeader = 4096;
@@ -1234,6 +1293,7 @@ int dominant_noalloc_t(const dpt_problem *p, const dpt_options *o, int64_t index
     unsigned int *flag = (unsigned int *)(base + 512);
     DomBuffers<T> b;
     b.s = s_dev;
+    b.stop = (unsigned int *)(base + 768);
     b.stats = (unsigned long long *)(base + kScratchHeader);
     const size_t zb = ((size_t)n * sizeof(T) + 255) / 256 * 256;
     b.z[0] = (T *)(base + kScratchHeader + kScratchStats);
