@@ -582,6 +582,76 @@ __global__ __launch_bounds__(256) void k_theta_count(const double *__restrict__ 
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->value_bits = (unsigned long long)__double_as_longlong(t);
 }
 
+// The whole scan in one workgroup of 1024 threads, for theta of at most
+// kThetaSmall values: one launch and no atomics between workgroups (the general
+// form takes four launches and one atomic per wave on the same word), with the
+// same results: the largest key, the non-finite flag, the first index holding
+// the maximum when no index is given, and the occurrences of theta_index.
+constexpr int64_t kThetaSmall = 65536;
+__global__ __launch_bounds__(1024) void k_theta_scan_small(const double *__restrict__ theta, int64_t n,
+                                                           int64_t index, ThetaScan *sc) {
+    __shared__ unsigned long long red[16];
+    __shared__ int red_bad[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    unsigned long long key = 0ull;
+    bool bad = false;
+    for (int64_t m = t; m < n; m += 1024) {
+        const double x = theta[m];
+        bad |= !isfinite(x);
+        key = max(key, order_key(x));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) key = max(key, (unsigned long long)__shfl_xor((long long)key, o));
+    const bool wave_bad = __any(bad);
+    if (lane == 0) {
+        red[w] = key;
+        red_bad[w] = wave_bad ? 1 : 0;
+    }
+    __syncthreads();
+    unsigned long long maxkey = red[0];
+    int any_bad = red_bad[0];
+    for (int i = 1; i < 16; ++i) {
+        maxkey = max(maxkey, red[i]);
+        any_bad |= red_bad[i];
+    }
+    __syncthreads();  // red is reused below
+    unsigned long long idx = index >= 0 ? (unsigned long long)index : (unsigned long long)n;
+    if (index < 0) {
+        unsigned long long first = (unsigned long long)n;
+        for (int64_t m = t; m < n; m += 1024)
+            if (order_key(theta[m]) == maxkey) {
+                first = (unsigned long long)m;  // this thread's indices increase
+                break;
+            }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) first = min(first, (unsigned long long)__shfl_xor((long long)first, o));
+        if (lane == 0) red[w] = first;
+        __syncthreads();
+        idx = red[0];
+        for (int i = 1; i < 16; ++i) idx = min(idx, red[i]);
+        __syncthreads();
+    }
+    unsigned long long count = 0ull;
+    double tv = 0.0;
+    if (idx < (unsigned long long)n) {  // uniform
+        tv = theta[idx];
+        for (int64_t m = t; m < n; m += 1024) count += theta[m] == tv ? 1ull : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) count += (unsigned long long)__shfl_xor((long long)count, o);
+        if (lane == 0) red[w] = count;
+        __syncthreads();
+        count = 0ull;
+        for (int i = 0; i < 16; ++i) count += red[i];
+    }
+    if (t == 0) {
+        sc->maxkey = maxkey;
+        sc->index = idx;
+        sc->count = count;
+        sc->bad = any_bad ? 1ull : 0ull;
+        sc->value_bits = idx < (unsigned long long)n ? (unsigned long long)__double_as_longlong(tv) : 0ull;
+    }
+}
+
 double bits_to_double(unsigned long long b) {
     double x;
     std::memcpy(&x, &b, sizeof(x));
@@ -1172,6 +1242,10 @@ int dominant_t(const dpt_problem *p, const dpt_options *o, const double *theta_h
 // Device-side theta checks into the caller's ThetaScan: the launches, then the
 // verdict on the scan read back.
 void theta_check_enqueue(const double *theta, int64_t n, int64_t index, ThetaScan *sc, hipStream_t s) {
+    if (n <= kThetaSmall) {
+        hipLaunchKernelGGL(k_theta_scan_small, dim3(1), dim3(1024), 0, s, theta, n, index, sc);
+        return;
+    }
     const unsigned int g = blocks_for(n, 256, 1024);
     hipLaunchKernelGGL(k_theta_scan_init, dim3(1), dim3(64), 0, s, sc, n, index);
     hipLaunchKernelGGL(k_theta_max, dim3(g), dim3(256), 0, s, theta, n, sc);
