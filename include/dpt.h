@@ -321,7 +321,9 @@ int dpt_profile_read(dpt_handle h, dpt_profile *out);
  * Submitted problems wait in FIFO order and are admitted while the arena and
  * the slot table have room; every engine step advances all admitted problems
  * by one application of F with one persistent grouped launch per precision
- * phase (replayed as a HIP graph when use_graph != 0); each problem follows
+ * phase and tile shape (replayed as a HIP graph when use_graph != 0 and
+ * every list in the graph has work; only the lists with work are launched
+ * otherwise); each problem follows
  * its own stopping rule and is retired individually (freeing its memory for
  * the next admissions).  Results do not depend on which other problems share
  * a step: every problem is computed with tiles chosen from its own padded
@@ -336,7 +338,8 @@ typedef struct dpt_server_ctx *dpt_server;
 typedef struct dpt_serve_config {
     int64_t budget_bytes;   /* device arena for in-flight problems (> 0)              */
     int32_t max_slots;      /* concurrent problems, 1 .. 1024                         */
-    int32_t use_graph;      /* 1: replay the grouped step as a HIP graph              */
+    int32_t use_graph;      /* 1: replay the grouped step as a HIP graph in steps     *
+                             * where every (phase, shape) list has work               */
     int32_t grid_blocks;    /* persistent grid of the grouped kernels; 0 = 1024       */
     int32_t autotune;       /* 1: time the fused-step tile shapes (64x64, 128x64,     *
                              * 128x128) per phase and padded-order class at open, on  *

@@ -332,6 +332,7 @@ struct dpt_server_ctx {
     }
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    int list_count[kGroupLists] = {};  // requests per (phase, shape) list in the current step
     std::chrono::steady_clock::time_point t0;
     // fused-step tile shape (index into the grouped shapes) per phase (BF16,
     // FP32) and padded-order class (ld <= 256, <= 512, <= 1024, larger); set by
@@ -387,23 +388,39 @@ struct dpt_server_ctx {
     }
 
     // ------------------------------------------------------------ worker
+    // Whether the (phase, shape) list can hold work: shapes a phase never uses
+    // are left out (64 x 64, the fallback, always stays).
+    bool list_used(int pi, int sh) const {
+        bool used = sh == 0;
+        for (int k = 0; k < kOrderClasses; ++k) used |= shape_of[pi][k] == sh;
+        return used;
+    }
+
     // The launches of one engine step: the pre-pass and the fused step for every
-    // (phase, shape) list; lists without work exit at once.  Shapes a phase
-    // never uses are left out (64 x 64, the fallback, always stays).
-    hipError_t launch_all(hipStream_t s) const {
+    // used (phase, shape) list (the graph's content: lists without work exit at
+    // once), or with only_busy for the lists that have work in this step.
+    hipError_t launch_all(hipStream_t s, bool only_busy = false) const {
         hipError_t e = launch_group_prepass(table_d, grid, s);
         for (int pi = 0; pi < 2; ++pi)
             for (int sh = 0; sh < kGroupShapes; ++sh) {
-                bool used = sh == 0;
-                for (int k = 0; k < kOrderClasses; ++k) used |= shape_of[pi][k] == sh;
-                if (e == hipSuccess && used) e = launch_group_step(table_d, pi == 0 ? PH_BF16 : PH_FP32, sh, grid, s);
+                const int ph = pi == 0 ? PH_BF16 : PH_FP32;
+                const bool go = only_busy ? list_count[group_list(ph, sh)] > 0 : list_used(pi, sh);
+                if (e == hipSuccess && go) e = launch_group_step(table_d, ph, sh, grid, s);
             }
         return e;
     }
 
+    // The graph is replayed only when every list it holds has work.  Otherwise
+    // the lists with work are launched directly: a graph launch costs the host
+    // ≈ 15 us per step against ≈ 2 us for the two launches of a lone problem,
+    // and each empty list in the graph still costs a dispatch on the device.
     hipError_t launch_grouped() {
-        if (cfg.use_graph) return hipGraphLaunch(graph_exec, stream);
-        return launch_all(stream);
+        bool all_busy = cfg.use_graph;
+        for (int pi = 0; pi < 2 && all_busy; ++pi)
+            for (int sh = 0; sh < kGroupShapes; ++sh)
+                if (list_used(pi, sh) && list_count[group_list(pi == 0 ? PH_BF16 : PH_FP32, sh)] == 0) all_busy = false;
+        if (all_busy) return hipGraphLaunch(graph_exec, stream);
+        return launch_all(stream, true);
     }
 
     static int order_class(int64_t ld) { return ld <= 256 ? 0 : ld <= 512 ? 1 : ld <= 1024 ? 2 : 3; }
@@ -657,6 +674,7 @@ struct dpt_server_ctx {
         for (int L = 0; L < kGroupLists; ++L) {
             t.prefix[L][cnt[L]] = tiles_sum[L];
             t.counts[1 + L] = cnt[L];
+            list_count[L] = cnt[L];
         }
         hipError_t e = hipSuccess;
         if (nreq > 0) {
@@ -918,6 +936,10 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
             if (e == hipSuccess) e = e1;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+        // one replay on the empty table (every list exits at once): a graph's
+        // first launch uploads it (milliseconds), which in service would stall
+        // the step where every list first has work
+        if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, c->stream);
     }
     // every slot's stats start at zero (the autotuner's timing runs publish into
     // slot 0; the admission launch publishes into them; retirement clears them)
