@@ -368,6 +368,8 @@ typedef struct dpt_serve_stats {
                                             * <= 512, <= 1024, larger): 0 = 64x64,   *
                                             * 1 = 128x64, 2 = 128x128 (orders that   *
                                             * are not multiples of 128 use 64x64)    */
+    int64_t graph_steps;                   /* engine steps replayed as the HIP graph *
+                                            * (every (phase, shape) list had work)   */
 } dpt_serve_stats;
 
 /* Start a server on the current device (on cfg->stream, or a stream of its own,

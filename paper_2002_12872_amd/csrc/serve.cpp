@@ -419,7 +419,11 @@ struct dpt_server_ctx {
         for (int pi = 0; pi < 2 && all_busy; ++pi)
             for (int sh = 0; sh < kGroupShapes; ++sh)
                 if (list_used(pi, sh) && list_count[group_list(pi == 0 ? PH_BF16 : PH_FP32, sh)] == 0) all_busy = false;
-        if (all_busy) return hipGraphLaunch(graph_exec, stream);
+        if (all_busy) {
+            std::lock_guard<std::mutex> lk(mu);
+            st.graph_steps += 1;
+            return hipGraphLaunch(graph_exec, stream);
+        }
         return launch_all(stream, true);
     }
 

@@ -102,7 +102,7 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("peak_active", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
                 ("active", ctypes.c_int64), ("pending", ctypes.c_int64), ("busy_s", ctypes.c_double),
-                ("tile_shape", (ctypes.c_int32 * 4) * 2)]
+                ("tile_shape", (ctypes.c_int32 * 4) * 2), ("graph_steps", ctypes.c_int64)]
 
 
 _FUNCS = {

@@ -70,6 +70,25 @@ def test_graph_and_direct_launches_agree():
         assert np.array_equal(x["E"], y["E"]) and np.array_equal(x["Z"], y["Z"])
 
 
+def test_graph_replays_agree_with_direct_launches():
+    """With one tile shape for every order class the graph holds one list per
+    phase, so the steps that carry requests in both phases replay it; the other
+    steps launch the busy list directly.  Against direct launches only: the same
+    results bit for bit."""
+    probs = [request(*m) for m in MIX[:6]]
+    out, stats = [], []
+    for use_graph in (True, False):
+        srv = dpt.dpt_serve_open(2 << 30, max_slots=16, use_graph=use_graph, tile_shape=0)
+        out.append(run_all(srv, probs))
+        stats.append(dpt.dpt_serve_stats_read(srv))
+        dpt.dpt_serve_close(srv)
+    assert stats[0]["graph_steps"] > 0 and stats[1]["graph_steps"] == 0
+    assert stats[0]["graph_steps"] < stats[0]["steps"]
+    for x, y in zip(*out):
+        assert x["status"] == dpt.DPT_OK
+        assert np.array_equal(x["E"], y["E"]) and np.array_equal(x["Z"], y["Z"])
+
+
 def test_matches_single_problem_solver():
     th, de = request(300, False, 11)
     srv = dpt.dpt_serve_open(1 << 30, max_slots=4)
