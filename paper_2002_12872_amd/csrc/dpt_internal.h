@@ -9,6 +9,8 @@
 // one CSR non-zero of Delta touches a contiguous run of eigenvectors.
 #pragma once
 
+#include <stddef.h>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -268,6 +270,12 @@ hipError_t pooled_malloc(void **p, size_t bytes);
 void pooled_free(void *p);
 bool inputs_on_device(const dpt_problem *p);
 hipError_t launch_group_retire(const RetireTable *t, int grid, hipStream_t s);
+// bytes (a multiple of 8) of a table in coherent pinned host memory, read by a
+// kernel through src (the allocation's device pointer), into dst on the device.
+hipError_t launch_fetch_table(const void *src, void *dst, size_t bytes, hipStream_t s);
+static_assert(offsetof(GroupTable, reqs) % 8 == 0 && sizeof(GroupReq) % 8 == 0, "tables move in 8-byte words");
+static_assert(offsetof(AdmitTable, reqs) % 8 == 0 && sizeof(AdmitReq) % 8 == 0, "tables move in 8-byte words");
+static_assert(offsetof(RetireTable, reqs) % 8 == 0 && sizeof(RetireReq) % 8 == 0, "tables move in 8-byte words");
 
 // Persistent grouped launches with a fixed grid (graph-capturable): the
 // pre-pass (also clears each request's stats) and the fused step for the

@@ -1447,6 +1447,27 @@ hipError_t launch_group_retire(const RetireTable *t, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Copy of a host-built work table (coherent pinned host memory, read through its
+// device mapping) into its device copy, 8 bytes per thread.  As a kernel on the
+// engine's own queue it is ordered with the kernels that read the table like
+// any other launch; a host-to-device copy runs on a copy engine, and the first
+// kernel after it started ≈ 15 us after the copy ended.
+__global__ __launch_bounds__(256) void k_fetch_table(const unsigned long long *__restrict__ src,
+                                                     unsigned long long *__restrict__ dst, int64_t words) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_fetch_table(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    if (bytes % 8 != 0) return hipErrorInvalidValue;
+    const int64_t words = (int64_t)(bytes / 8);
+    if (words == 0) return hipSuccess;
+    const unsigned int blocks = (unsigned int)std::min<int64_t>((words + 255) / 256, 64);
+    hipLaunchKernelGGL(k_fetch_table, dim3(blocks), dim3(256), 0, s, (const unsigned long long *)src,
+                       (unsigned long long *)dst, words);
+    return hipGetLastError();
+}
+
 int residual_chunks(int64_t ld) { return (int)((ld + kResChunk - 1) / kResChunk); }
 
 hipError_t launch_residual_f32(const float *W, const void *D, int d_is_f64, const StepArgs &a, const int64_t *rows,

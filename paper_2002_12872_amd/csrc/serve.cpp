@@ -309,9 +309,13 @@ struct dpt_server_ctx {
     unsigned char *arena_base = nullptr;
     Arena arena;
     size_t arena_used = 0;
+    // work tables: built on the host in coherent pinned memory (*_h), moved to
+    // the device copy (*_d) by a kernel that reads the host block through its
+    // device mapping (*_hd)
     GroupTable *table_h = nullptr, *table_d = nullptr;
     AdmitTable *admit_h = nullptr, *admit_d = nullptr;
     RetireTable *retire_h = nullptr, *retire_d = nullptr;
+    void *table_hd = nullptr, *admit_hd = nullptr, *retire_hd = nullptr;
     unsigned long long *stats_d = nullptr, *stats_h = nullptr;
     // eigenvalues of retiring requests: device staging and its pinned mirror
     double *e_stage_d = nullptr, *e_stage_h = nullptr;
@@ -623,8 +627,8 @@ struct dpt_server_ctx {
         }
         if (e == hipSuccess && k > 0) {
             admit_h->count = k;
-            e = hipMemcpyAsync(admit_d, admit_h, offsetof(AdmitTable, reqs) + (size_t)k * sizeof(AdmitReq),
-                               hipMemcpyHostToDevice, stream);
+            e = launch_fetch_table(admit_hd, admit_d, offsetof(AdmitTable, reqs) + (size_t)k * sizeof(AdmitReq),
+                                   stream);
             if (e == hipSuccess) e = launch_group_admit(admit_d, grid, stream);
         }
         for (Request *r : zero_w0)
@@ -682,8 +686,8 @@ struct dpt_server_ctx {
         }
         hipError_t e = hipSuccess;
         if (nreq > 0) {
-            e = hipMemcpyAsync(table_d, table_h, offsetof(GroupTable, reqs) + (size_t)nreq * sizeof(GroupReq),
-                               hipMemcpyHostToDevice, stream);
+            e = launch_fetch_table(table_hd, table_d, offsetof(GroupTable, reqs) + (size_t)nreq * sizeof(GroupReq),
+                                   stream);
             if (e == hipSuccess) e = launch_grouped();
         }
         return e;
@@ -765,8 +769,8 @@ struct dpt_server_ctx {
             eoff += (size_t)r->n;
         }
         t.count = (int32_t)out.size();
-        e = hipMemcpyAsync(retire_d, retire_h, offsetof(RetireTable, reqs) + out.size() * sizeof(RetireReq),
-                           hipMemcpyHostToDevice, stream);
+        e = launch_fetch_table(retire_hd, retire_d, offsetof(RetireTable, reqs) + out.size() * sizeof(RetireReq),
+                               stream);
         if (e == hipSuccess) e = launch_group_retire(retire_d, grid, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(e_stage_h, e_stage_d, eoff * 8, hipMemcpyDeviceToHost, stream);
         for (Request *r : out) {
@@ -918,9 +922,14 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     if (e == hipSuccess) e = hipMalloc((void **)&c->retire_d, sizeof(RetireTable));
     if (e == hipSuccess) e = hipMalloc((void **)&c->stats_d, 16 * (size_t)cfg->max_slots);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->submit_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&c->admit_h, sizeof(AdmitTable), 0);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&c->retire_h, sizeof(RetireTable), 0);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&c->table_h, sizeof(GroupTable), 0);
+    // coherent: the host rewrites the tables between steps and a kernel reads them
+    const unsigned int tflags = hipHostMallocCoherent | hipHostMallocMapped;
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->admit_h, sizeof(AdmitTable), tflags);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->retire_h, sizeof(RetireTable), tflags);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->table_h, sizeof(GroupTable), tflags);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&c->admit_hd, c->admit_h, 0);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&c->retire_hd, c->retire_h, 0);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&c->table_hd, c->table_h, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->stats_h, 16 * (size_t)cfg->max_slots, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->ring.base, dpt_server_ctx::kRingBytes, 0);
     if (e == hipSuccess) c->ring.cap = dpt_server_ctx::kRingBytes;
