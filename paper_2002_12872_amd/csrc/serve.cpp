@@ -320,6 +320,7 @@ struct dpt_server_ctx {
     // eigenvalues of retiring requests: device staging and its pinned mirror
     double *e_stage_d = nullptr, *e_stage_h = nullptr;
     size_t e_stage_cap = 0;  // doubles
+    static constexpr size_t kEStage0 = (size_t)1 << 16;  // allocated at open
     // device submissions: theta is read back for validation on a stream of its own
     hipStream_t submit_stream = nullptr;
     std::mutex submit_mu;
@@ -744,7 +745,7 @@ struct dpt_server_ctx {
             if (e_stage_h) (void)hipHostFree(e_stage_h);
             e_stage_d = e_stage_h = nullptr;
             e_stage_cap = 0;
-            const size_t cap = std::max<size_t>(need, (size_t)1 << 16);
+            const size_t cap = std::max<size_t>(need, kEStage0);
             e = hipMalloc((void **)&e_stage_d, cap * 8);
             if (e == hipSuccess) e = hipHostMalloc((void **)&e_stage_h, cap * 8, 0);
             if (e != hipSuccess) return e;
@@ -933,6 +934,11 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->stats_h, 16 * (size_t)cfg->max_slots, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->ring.base, dpt_server_ctx::kRingBytes, 0);
     if (e == hipSuccess) c->ring.cap = dpt_server_ctx::kRingBytes;
+    // the eigenvalue staging of the retirements at its first size, so that the
+    // engine's steps allocate nothing until a retirement needs more
+    if (e == hipSuccess) e = hipMalloc((void **)&c->e_stage_d, dpt_server_ctx::kEStage0 * 8);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->e_stage_h, dpt_server_ctx::kEStage0 * 8, 0);
+    if (e == hipSuccess) c->e_stage_cap = dpt_server_ctx::kEStage0;
     if (e == hipSuccess) {
         std::memset(c->table_h, 0, sizeof(GroupTable));
         e = hipMemcpy(c->table_d, c->table_h, sizeof(GroupTable), hipMemcpyHostToDevice);
@@ -953,6 +959,16 @@ int dpt_serve_open(dpt_server *srv, const dpt_serve_config *cfg) {
         // first launch uploads it (milliseconds), which in service would stall
         // the step where every list first has work
         if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, c->stream);
+    }
+    // the table copy, admission and retirement kernels run once on empty tables
+    // (their item loops do nothing), so that no first launch falls in service
+    if (e == hipSuccess) {
+        std::memset(c->admit_h, 0, offsetof(AdmitTable, reqs));
+        std::memset(c->retire_h, 0, offsetof(RetireTable, reqs));
+        e = launch_fetch_table(c->admit_hd, c->admit_d, offsetof(AdmitTable, reqs), c->stream);
+        if (e == hipSuccess) e = launch_fetch_table(c->retire_hd, c->retire_d, offsetof(RetireTable, reqs), c->stream);
+        if (e == hipSuccess) e = launch_group_admit(c->admit_d, c->grid, c->stream);
+        if (e == hipSuccess) e = launch_group_retire(c->retire_d, c->grid, c->stream);
     }
     // every slot's stats start at zero (the autotuner's timing runs publish into
     // slot 0; the admission launch publishes into them; retirement clears them)
